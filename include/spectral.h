@@ -1,0 +1,263 @@
+/*
+ * spectral.h -- C ABI of the MI355X (gfx950) spectral-clustering library.
+ *
+ * The library implements the hot path of spectral clustering by LOBPCG as
+ * described in "Preconditioned Spectral Clustering for Stochastic Block
+ * Partition Streaming Graph Challenge" (Zhuzhunashvili & Knyazev):
+ *   1. symmetrise the directed adjacency, W <- W + W'        (Section II-A)
+ *   2. form the normalised graph Laplacian I - D^-1/2 W D^-1/2
+ *      (Section II-A defines the Laplacian from W and its row sums D; the
+ *      normalised form is used here)
+ *   3. compute its smallest k eigenpairs with block LOBPCG without
+ *      preconditioning, from a random or warm-start block X0
+ *      (Section II-B, Section III)
+ *   4. label the vertices by k-means on the row-normalised eigenvectors
+ *      (Section II-A).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (memory owned by the caller)
+ *     unless the comment says "host".  The library never allocates device
+ *     memory; each call that needs scratch takes a caller-provided workspace
+ *     `ws` of at least the size returned by the matching *_workspace query,
+ *     aligned to 256 bytes.
+ *   - Work is enqueued on the stream given to sc_ctx_create.  Calls that
+ *     return host values synchronise that stream; their comments say so.
+ *   - Multivectors (n x k blocks) are row-major with a row stride `ld`
+ *     (elements) >= k: the k values of one vertex are contiguous.
+ *   - Every call returns an sc_status; on failure sc_last_error(ctx) holds a
+ *     message.  Arguments are validated on the host before any launch.
+ *   - One context per host thread; calls on one context are not reentrant.
+ */
+#ifndef SPECTRAL_H
+#define SPECTRAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SC_OK = 0,
+    SC_E_INVAL = -1,        /* invalid argument (sizes, ids out of range, null pointers) */
+    SC_E_NOMEM = -2,        /* workspace smaller than the query returned */
+    SC_E_HIP = -3,          /* HIP runtime error */
+    SC_E_BREAKDOWN = -4,    /* Cholesky breakdown that the rules below cannot recover */
+    SC_E_NUMERIC = -5,      /* NaN / Inf in an input block or a residual norm */
+    SC_E_UNSUPPORTED = -6   /* size outside what the kernels support (e.g. k > 256) */
+} sc_status;
+
+/* Symmetrisation of Section II-A: "+" is a logical or (unweighted graph) or
+ * an algebraic sum of non-negative weights. */
+typedef enum { SC_SYM_LOGICAL = 0, SC_SYM_ALGEBRAIC = 1 } sc_sym_mode;
+
+/* Arithmetic of the LOBPCG multivectors.  FP64: everything in FP64.
+ * FP32: Laplacian values, SpMM, multivectors, block updates and Gram
+ * products in FP32 (Gram partial sums promoted to FP64); every Cholesky and
+ * the Rayleigh-Ritz eigenproblem in FP64 (the paper's single-precision
+ * variant, Section IV).  FP32_BF16GRAM: as FP32 but the Gram products of the
+ * Rayleigh-Ritz step read their inputs rounded to BF16 (round to nearest
+ * even) and accumulate in FP32 on the matrix cores. */
+typedef enum { SC_PREC_FP64 = 0, SC_PREC_FP32 = 1, SC_PREC_FP32_BF16GRAM = 2 } sc_precision;
+
+typedef struct sc_ctx sc_ctx;
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Host memory only. */
+sc_status sc_ctx_create(int device, void* hip_stream, sc_ctx** out);
+sc_status sc_ctx_destroy(sc_ctx* ctx);
+/* Text of the last error on this context ("" if none).  Host string owned by ctx. */
+const char* sc_last_error(const sc_ctx* ctx);
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int sc_version(void);
+
+/* ------------------------------------------------------------------------
+ * Graph construction: W <- W + W' (Section II-A).
+ * ------------------------------------------------------------------------ */
+sc_status sc_graph_build_workspace(sc_ctx* ctx, int64_t n, int64_t m, size_t* bytes);
+
+/*
+ * Directed COO (src[e] -> dst[e], e < m; ids in [0, n)) to the CSR of the
+ * symmetric matrix W + W'.  Edge e contributes (src,dst) and (dst,src); self
+ * loops are dropped and counted.  Repeated (row,col) entries are merged:
+ * SC_SYM_LOGICAL gives weight 1; SC_SYM_ALGEBRAIC sums the weights in the
+ * order edge 0 forward, edge 0 backward, edge 1 forward, ...  Columns are
+ * strictly ascending in every row.  degree[i] = sum of row i in ascending
+ * column order (the diagonal matrix D of Section II-A).
+ *   src, dst     int32 [m] (device)
+ *   w            float64 [m] (device) or NULL for unit weights; weights must
+ *                be finite and >= 0 (SC_SYM_ALGEBRAIC only)
+ *   row_ptr      int64 [n+1] (device, out)
+ *   col          int32 [2m] capacity (device, out); first nnz entries valid
+ *   w_sym        float64 [2m] capacity (device, out) or NULL
+ *   degree       float64 [n] (device, out)
+ *   nnz_out      host, out: number of stored entries (synchronises)
+ *   self_loops   host, out, may be NULL
+ * Errors: SC_E_INVAL for n <= 0, m < 0, m >= 2^31, an id outside [0,n) or
+ * an invalid weight (detected on the device, reported after the sync).
+ */
+sc_status sc_graph_build(sc_ctx* ctx, int64_t n, int64_t m, const int32_t* src,
+                         const int32_t* dst, const double* w, sc_sym_mode mode,
+                         int64_t* row_ptr, int32_t* col, double* w_sym, double* degree,
+                         int64_t* nnz_out, int64_t* self_loops, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Normalised Laplacian L = I - D^-1/2 W D^-1/2 on W's pattern.
+ * ------------------------------------------------------------------------ */
+/*
+ * val[p] = -(w_p / sqrt(d_i d_j)) for the entry p = (i, j) of W (0 when
+ * d_i d_j == 0); the unit diagonal is implicit and not stored.
+ * dinv_sqrt[i] = 1 / sqrt(d_i), or 0 for an isolated vertex (whose row of L
+ * is then the unit row).  One rounded quotient per entry keeps L bitwise
+ * symmetric.
+ *   row_ptr, col, degree  from sc_graph_build (device)
+ *   w_sym    float64 [nnz] or NULL (unit weights)
+ *   val64    float64 [nnz] (out) or NULL
+ *   val32    float32 [nnz] (out) or NULL: val64 rounded to nearest
+ *   dinv_sqrt float64 [n] (out) or NULL
+ * No synchronisation.
+ */
+sc_status sc_laplacian_csr(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                           const int32_t* col, const double* w_sym, const double* degree,
+                           double* val64, float* val32, double* dinv_sqrt);
+
+/*
+ * Y = L X: the one multiplication by the graph Laplacian per LOBPCG
+ * iteration (Section III).  For every row i and column j < k,
+ *   y_ij = x_ij, then over row i in ascending column order
+ *   y_ij = fma(val_p, x_{col_p, j}, y_ij).
+ * fp64 != 0: val, X, Y are float64; else float32.  X and Y must not alias.
+ * ldx, ldy >= k.  No synchronisation.
+ */
+sc_status sc_spmm(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                  const int32_t* col, const void* val, int fp64, int k, const void* X,
+                  int64_t ldx, void* Y, int64_t ldy);
+
+/* ------------------------------------------------------------------------
+ * LOBPCG without preconditioning for the k smallest eigenpairs of L.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int k;                 /* block size = number of eigenpairs, 1 <= k <= 256, 3k <= n */
+    int maxit;             /* iterations (products L W) at most, >= 0 */
+    double tol;            /* stop when max_j relres_j <= tol (0: run maxit iterations) */
+    sc_precision prec;
+    int64_t ldx;           /* row stride of X0 / X_out, >= k */
+    double lock_tol;       /* columns with relres_j <= lock_tol leave the W block
+                              (0 = default: 1e-13 in FP64, 1e-6 otherwise) */
+    double chol_tol;       /* relative pivot floor of every Cholesky
+                              (0 = default: 1e-14 in FP64, 1e-6 otherwise) */
+} sc_lobpcg_opts;
+
+typedef struct {
+    int iterations;        /* Rayleigh-Ritz updates after the initial one */
+    int converged;         /* 1 if max relres <= tol (or every column locked) */
+    int p_drops;           /* iterations in which the P block was dropped */
+    int locked_cols;       /* W columns excluded in the last iteration */
+    double max_relres;     /* of the returned block */
+} sc_lobpcg_info;
+
+sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobpcg_opts* opts,
+                              size_t* bytes);
+
+/*
+ * Block LOBPCG (Knyazev 2001) with T = I for the smallest k eigenpairs of
+ * L = I + offdiag(val).  Iteration, with S = [X W P] and LS = L S:
+ *   init: X <- CholQR2(X0); LX = L X; Rayleigh-Ritz on span(X);
+ *   each iteration: R = LX - X diag(theta); relres_j = ||R_j|| / (2 ||x_j||);
+ *     stop if max relres <= tol; W <- CholQR(R without locked columns);
+ *     LW = L W; P, LP <- CholQR(P) (P dropped for this iteration if that
+ *     Cholesky fails); Gram matrices S'LS and S'S (3k x 3k); Rayleigh-Ritz in
+ *     FP64 (Cholesky of S'S; on failure P is dropped and the step redone);
+ *     P <- [W P] C_WP, X <- X C_X + P (and the same for LX, LP).
+ * Every CholQR equilibrates the columns before the Cholesky.
+ *   val     float64 [nnz] (prec FP64) or float32 [nnz] (other precisions)
+ *   X0      n x ldx start block (float64 for FP64, float32 otherwise); must
+ *           have full column rank and finite entries
+ *   X_out   n x ldx result (may alias X0)
+ *   theta   float64 [k] (device, out): Ritz values, ascending
+ *   relres_hist  host float64 [(maxit+1) * k] or NULL: relres of every
+ *           iterate (row t after t iterations)
+ *   info    host, out
+ * Synchronises once per iteration (convergence test).
+ * Errors: SC_E_INVAL (sizes), SC_E_UNSUPPORTED (k > 256), SC_E_NUMERIC (NaN
+ * or Inf in X0 or a residual), SC_E_BREAKDOWN (rank-deficient X0 or W, or
+ * S'S not positive definite even without P).  On SC_E_BREAKDOWN X_out is
+ * not written.
+ */
+sc_status sc_lobpcg_solve(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                          const int32_t* col, const void* val, const sc_lobpcg_opts* opts,
+                          const void* X0, void* X_out, double* theta, double* relres_hist,
+                          sc_lobpcg_info* info, void* ws, size_t ws_bytes);
+
+/* Step API: the same solver advanced one iteration per call, so that a
+ * scheduler can interleave several solves (continuous batching).  The state
+ * lives in the workspace; the same buffers must be passed to every call.
+ *   begin: validates, runs the initial CholQR2 / SpMM / Rayleigh-Ritz and the
+ *          first residual; *done = 1 if already converged.  Synchronises.
+ *   step:  one iteration; *done = 1 when converged or maxit reached.
+ *          Synchronises (convergence test).
+ *   end:   writes X_out, theta and info.  Synchronises. */
+typedef struct sc_lobpcg_state sc_lobpcg_state;
+sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                          const int32_t* col, const void* val, const sc_lobpcg_opts* opts,
+                          const void* X0, void* ws, size_t ws_bytes, sc_lobpcg_state** state,
+                          int* done);
+sc_status sc_lobpcg_step(sc_ctx* ctx, sc_lobpcg_state* state, int* done);
+sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* state, void* X_out, double* theta,
+                        double* relres_hist, sc_lobpcg_info* info);
+
+/* ------------------------------------------------------------------------
+ * k-means on the row-normalised eigenvectors (Section II-A labels).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int n_clusters;        /* K, 1 <= K <= min(n, 1024) */
+    int restarts;          /* k-means++ seedings, >= 1 */
+    int max_iter;          /* Lloyd updates per restart, >= 0 */
+    int normalize_rows;    /* 1: y_i = x_i / ||x_i|| (zero rows stay zero) */
+} sc_kmeans_opts;
+
+sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* opts,
+                              size_t* bytes);
+
+/*
+ * Labels from k-means with k-means++ seeding (Arthur & Vassilvitskii) and
+ * Lloyd iterations, the best of `restarts` runs.
+ *   seeding: c_0 = y[mulhi64(u_0, n)]; for j >= 1 integer weights
+ *     w_i = floor(D2_i * 2^s) (s = 61 - ceil(log2 n) - e, 2^e > 4 max ||y||^2),
+ *     T = sum w, t = mulhi64(u_j, T), c_j = y[min i : prefix_i > t]
+ *     (T = 0: y[mulhi64(u_j, n)]), D2_i <- min(D2_i, |y_i - c_j|^2);
+ *   Lloyd: assign to the nearest centroid (squared distance accumulated with
+ *     fma in dimension order, ties to the lowest index); centroids = member
+ *     sums in ascending vertex order / count (empty clusters keep theirs);
+ *     stop when no label changes or after max_iter updates;
+ *   best restart: least sum_i floor(mind_i * 2^s), ties to the lowest.
+ *   X        float64 n x ldx (device)
+ *   draws    uint64 [restarts * K] uniform words (device), unused when
+ *            init_centroids != NULL
+ *   init_centroids float64 [K * dim] (device) or NULL; requires restarts = 1
+ *   labels   int32 [n] (out); centroids float64 [K * dim] (out)
+ *   inertia  host out (sum of squared distances, FP64), inertia_q host out
+ *            (integer inertia), best_restart host out; each may be NULL.
+ * Synchronises once per Lloyd iteration.
+ */
+sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const double* X, int64_t ldx,
+                           const sc_kmeans_opts* opts, const uint64_t* draws,
+                           const double* init_centroids, int32_t* labels, double* centroids,
+                           double* inertia, uint64_t* inertia_q, int* best_restart,
+                           void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Dense FP64 symmetric eigensolver used inside the Rayleigh-Ritz step,
+ * exposed for testing: the k smallest eigenpairs of the m x m symmetric A
+ * (row-major, device).  w float64 [k] ascending, V float64 m x k row-major
+ * (device, out).  m <= 1024.
+ * ------------------------------------------------------------------------ */
+sc_status sc_symeig_workspace(sc_ctx* ctx, int m, int k, size_t* bytes);
+sc_status sc_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
+                    void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPECTRAL_H */

@@ -1,0 +1,225 @@
+"""Python entry points over the C ABI: argument marshalling only.
+
+Every array is a torch tensor on the GPU (torch provides device memory and the
+stream); every step of the computation runs in the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (SC_PREC_FP32, SC_PREC_FP32_BF16GRAM, SC_PREC_FP64, SC_SYM_ALGEBRAIC,
+                   SC_SYM_LOGICAL, SpectralError, lib)
+
+PRECISIONS = {"fp64": SC_PREC_FP64, "fp32": SC_PREC_FP32, "fp32_bf16gram": SC_PREC_FP32_BF16GRAM}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a device and to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the spectral library runs on the GPU only")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = lib().sc_ctx_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise SpectralError(st, "sc_ctx_create")
+        self.handle = h
+
+    def check(self, st: int, what: str):
+        if st != 0:
+            msg = lib().sc_last_error(self.handle)
+            raise SpectralError(st, what, msg.decode() if msg else "")
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class DeviceCSR:
+    n: int
+    nnz: int
+    row_ptr: torch.Tensor   # int64 [n+1]
+    col: torch.Tensor       # int32 [nnz]
+    w_sym: torch.Tensor | None
+    degree: torch.Tensor    # float64 [n]
+    self_loops: int = 0
+
+
+def graph_build(ctx: Context, n: int, src: torch.Tensor, dst: torch.Tensor,
+                w: torch.Tensor | None = None, algebraic: bool = False) -> DeviceCSR:
+    dev = src.device
+    m = int(src.numel())
+    nb = C.c_size_t()
+    ctx.check(lib().sc_graph_build_workspace(ctx.handle, n, m, C.byref(nb)), "sc_graph_build_workspace")
+    ws = ctx.workspace(nb.value)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev)
+    w_sym = torch.empty(max(2 * m, 1), dtype=torch.float64, device=dev) if algebraic else None
+    degree = torch.empty(n, dtype=torch.float64, device=dev)
+    nnz = C.c_int64()
+    loops = C.c_int64()
+    ctx.check(lib().sc_graph_build(ctx.handle, n, m, _ptr(src), _ptr(dst), _ptr(w),
+                                   SC_SYM_ALGEBRAIC if algebraic else SC_SYM_LOGICAL,
+                                   _ptr(row_ptr), _ptr(col), _ptr(w_sym), _ptr(degree),
+                                   C.byref(nnz), C.byref(loops), _ptr(ws), nb.value),
+              "sc_graph_build")
+    z = nnz.value
+    return DeviceCSR(n, z, row_ptr, col[:max(z, 1)], None if w_sym is None else w_sym[:max(z, 1)],
+                     degree, loops.value)
+
+
+def laplacian_csr(ctx: Context, g: DeviceCSR, fp64: bool = True, fp32: bool = False):
+    dev = g.row_ptr.device
+    val64 = torch.empty(max(g.nnz, 1), dtype=torch.float64, device=dev) if fp64 else None
+    val32 = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev) if fp32 else None
+    dis = torch.empty(g.n, dtype=torch.float64, device=dev)
+    ctx.check(lib().sc_laplacian_csr(ctx.handle, g.n, g.nnz, _ptr(g.row_ptr), _ptr(g.col),
+                                     _ptr(g.w_sym), _ptr(g.degree), _ptr(val64), _ptr(val32),
+                                     _ptr(dis)), "sc_laplacian_csr")
+    return val64, val32, dis
+
+
+def spmm(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
+         Y: torch.Tensor | None = None) -> torch.Tensor:
+    n, k = X.shape
+    if Y is None:
+        Y = torch.empty_like(X)
+    fp64 = X.dtype == torch.float64
+    if val.dtype != X.dtype or Y.dtype != X.dtype:
+        raise TypeError("val, X and Y must share one dtype")
+    ctx.check(lib().sc_spmm(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
+                            int(fp64), k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0)), "sc_spmm")
+    return Y
+
+
+@dataclass
+class LobpcgResult:
+    X: torch.Tensor
+    theta: torch.Tensor
+    relres_hist: "list | None"
+    iterations: int
+    converged: bool
+    p_drops: int
+    locked_cols: int
+    max_relres: float
+
+
+def lobpcg_opts(k, maxit, tol, precision, ldx, lock_tol=0.0, chol_tol=0.0):
+    return _lib.sc_lobpcg_opts(k, maxit, tol, PRECISIONS[precision], ldx, lock_tol, chol_tol)
+
+
+def lobpcg_workspace(ctx: Context, n, nnz, opts) -> int:
+    nb = C.c_size_t()
+    ctx.check(lib().sc_lobpcg_workspace(ctx.handle, n, nnz, C.byref(opts), C.byref(nb)),
+              "sc_lobpcg_workspace")
+    return nb.value
+
+
+def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor, maxit: int,
+                 tol: float = 0.0, precision: str = "fp64", lock_tol: float = 0.0,
+                 chol_tol: float = 0.0, history: bool = True, ws: torch.Tensor | None = None,
+                 X_out: torch.Tensor | None = None) -> LobpcgResult:
+    import numpy as np
+    n, k = X0.shape
+    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol)
+    nb = lobpcg_workspace(ctx, n, g.nnz, opts)
+    if ws is None or ws.numel() < nb:
+        ws = ctx.workspace(nb)
+    if X_out is None:
+        X_out = torch.empty_like(X0)
+    theta = torch.empty(k, dtype=torch.float64, device=X0.device)
+    hist = np.zeros((maxit + 1) * k, dtype=np.float64) if history else None
+    info = _lib.sc_lobpcg_info()
+    ctx.check(lib().sc_lobpcg_solve(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
+                                    C.byref(opts), _ptr(X0), _ptr(X_out), _ptr(theta),
+                                    None if hist is None else hist.ctypes.data_as(C.c_void_p),
+                                    C.byref(info), _ptr(ws), nb), "sc_lobpcg_solve")
+    it = info.iterations
+    return LobpcgResult(X_out, theta, None if hist is None else hist.reshape(maxit + 1, k)[: it + 1],
+                        it, bool(info.converged), info.p_drops, info.locked_cols, info.max_relres)
+
+
+def lobpcg_status(ctx: Context, g: DeviceCSR, val, X0, maxit, tol=0.0, precision="fp64") -> int:
+    """Status code of a solve (for the failure-path tests)."""
+    n, k = X0.shape
+    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0))
+    nb = C.c_size_t()
+    st = lib().sc_lobpcg_workspace(ctx.handle, n, g.nnz, C.byref(opts), C.byref(nb))
+    if st != 0:
+        return st
+    ws = ctx.workspace(nb.value)
+    X_out = torch.empty_like(X0)
+    theta = torch.empty(max(k, 1), dtype=torch.float64, device=X0.device)
+    info = _lib.sc_lobpcg_info()
+    return lib().sc_lobpcg_solve(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
+                                 C.byref(opts), _ptr(X0), _ptr(X_out), _ptr(theta), None,
+                                 C.byref(info), _ptr(ws), nb.value)
+
+
+@dataclass
+class KmeansResult:
+    labels: torch.Tensor
+    centroids: torch.Tensor
+    inertia: float
+    inertia_q: int
+    best_restart: int
+
+
+def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.Tensor | None,
+                  restarts: int | None = None, max_iter: int = 100, normalize: bool = True,
+                  init_centroids: torch.Tensor | None = None,
+                  ws: torch.Tensor | None = None) -> KmeansResult:
+    n, dim = X.shape
+    if init_centroids is not None:
+        restarts = 1
+    elif restarts is None:
+        restarts = draws.shape[0]
+    opts = _lib.sc_kmeans_opts(n_clusters, restarts, max_iter, int(bool(normalize)))
+    nb = C.c_size_t()
+    ctx.check(lib().sc_kmeans_workspace(ctx.handle, n, dim, C.byref(opts), C.byref(nb)),
+              "sc_kmeans_workspace")
+    if ws is None or ws.numel() < nb.value:
+        ws = ctx.workspace(nb.value)
+    labels = torch.empty(n, dtype=torch.int32, device=X.device)
+    cent = torch.empty((n_clusters, dim), dtype=torch.float64, device=X.device)
+    inertia = C.c_double()
+    iq = C.c_uint64()
+    br = C.c_int()
+    ctx.check(lib().sc_kmeans_assign(ctx.handle, n, dim, _ptr(X), X.stride(0), C.byref(opts),
+                                     _ptr(draws), _ptr(init_centroids), _ptr(labels), _ptr(cent),
+                                     C.byref(inertia), C.byref(iq), C.byref(br), _ptr(ws),
+                                     nb.value), "sc_kmeans_assign")
+    return KmeansResult(labels, cent, inertia.value, iq.value, br.value)
+
+
+def symeig(ctx: Context, A: torch.Tensor, k: int):
+    m = A.shape[0]
+    nb = C.c_size_t()
+    ctx.check(lib().sc_symeig_workspace(ctx.handle, m, k, C.byref(nb)), "sc_symeig_workspace")
+    ws = ctx.workspace(nb.value)
+    w = torch.empty(k, dtype=torch.float64, device=A.device)
+    V = torch.empty((m, k), dtype=torch.float64, device=A.device)
+    ctx.check(lib().sc_symeig(ctx.handle, m, k, _ptr(A), _ptr(w), _ptr(V), _ptr(ws), nb.value),
+              "sc_symeig")
+    return w, V

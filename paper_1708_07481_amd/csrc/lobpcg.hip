@@ -1,0 +1,375 @@
+// Block LOBPCG without preconditioning for the smallest k eigenpairs of the
+// normalised graph Laplacian (Section II-B: one product with L per
+// iteration; Section III: random or warm-start initial block, no
+// preconditioner).  The host loop enqueues the kernels of dense.hip, spmm.hip
+// and rr.hip and synchronises once per iteration for the convergence test.
+//
+// Workspace layout: S = [X W P] and LS = [LX LW LP], each n x 3kp row-major
+// (kp = k rounded up to a multiple of 4; pad columns stay zero), the Gram
+// matrices, the small factors, and the per-iteration residual history.
+#include <cstring>
+#include <vector>
+
+#include "sc_internal.h"
+
+namespace {
+
+__global__ void k_fill_bytes(uint32_t* p, int64_t words) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+// mask[0..c) = (j < ones) for `c` columns
+__global__ void k_set_mask(int* mask, int c, int ones) {
+    for (int j = threadIdx.x; j < c; j += blockDim.x) mask[j] = j < ones ? 1 : 0;
+}
+
+template <class Tin, class T>
+__global__ void k_load_block(int64_t n, int k, int kp, const Tin* __restrict__ X0, int64_t ldx,
+                             T* __restrict__ S, int64_t ld, int* status) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * kp) return;
+    const int64_t i = e / kp;
+    const int j = (int)(e % kp);
+    T v = T(0);
+    if (j < k) {
+        const Tin x = X0[i * ldx + j];
+        if (!isfinite((double)x)) atomicOr(status, DEV_NUMERIC);
+        v = (T)x;
+    }
+    S[i * ld + j] = v;
+}
+
+template <class T>
+__global__ void k_store_block(int64_t n, int k, const T* __restrict__ S, int64_t ld,
+                              T* __restrict__ X, int64_t ldx) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (int64_t)k) return;
+    const int64_t i = e / k;
+    const int j = (int)(e % k);
+    X[i * ldx + j] = S[i * ld + j];
+}
+
+}  // namespace
+
+struct sc_lobpcg_state {
+    // problem
+    int64_t n = 0, nnz = 0;
+    const int64_t* row_ptr = nullptr;
+    const int32_t* col = nullptr;
+    const void* val = nullptr;
+    int k = 0, kp = 0, K3 = 0, maxit = 0;
+    double tol = 0, lock_tol = 0, chol_tol = 0;
+    sc_precision prec = SC_PREC_FP64;
+    int64_t ldx = 0;
+    // workspace views
+    void* S = nullptr;
+    void* LS = nullptr;
+    double *GA, *GB, *Gpart, *Gw, *Gwpart, *T64, *C64, *theta, *relres, *res_part, *cq_scr,
+        *rr_scr, *hist, *out_max;
+    float *T32, *C32;
+    int *act, *status, *pdrops, *all_locked;
+    GramPlan plan3{}, plank{};
+    int res_blocks = 0;
+    // progress
+    int t = 0;
+    int has_p = 0;
+    int converged = 0;
+    int done = 0;
+    double max_relres = 0.0;
+};
+
+static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, sc_lobpcg_state& s) {
+    const int kp = (k + 3) / 4 * 4;
+    const int K3 = 3 * kp;
+    const size_t es = prec == SC_PREC_FP64 ? 8 : 4;
+    s.kp = kp;
+    s.K3 = K3;
+    s.S = c.take<char>((size_t)n * K3 * es);
+    s.LS = c.take<char>((size_t)n * K3 * es);
+    s.plan3 = gram_plan(n, K3);
+    s.plank = gram_plan(n, kp);
+    s.GA = c.take<double>((size_t)K3 * K3);
+    s.GB = c.take<double>((size_t)K3 * K3);
+    s.Gpart = c.take<double>(gram_partial_elems(s.plan3, 2));
+    s.Gw = c.take<double>((size_t)kp * kp);
+    s.Gwpart = c.take<double>(gram_partial_elems(s.plank, 1));
+    s.T64 = c.take<double>((size_t)kp * kp);
+    s.T32 = c.take<float>((size_t)kp * kp);
+    s.C64 = c.take<double>((size_t)K3 * kp);
+    s.C32 = c.take<float>((size_t)K3 * kp);
+    s.theta = c.take<double>(kp);
+    s.relres = c.take<double>(kp);
+    s.res_blocks = (int)ceil_div(n, 256);
+    s.res_part = c.take<double>((size_t)s.res_blocks * 2 * kp);
+    s.cq_scr = c.take<double>(3 * (size_t)kp * kp);
+    s.rr_scr = c.take<double>(rr_scratch_elems(K3, k));
+    s.hist = c.take<double>((size_t)(maxit + 1) * kp);
+    s.out_max = c.take<double>(1);
+    s.act = c.take<int>(K3);
+    s.status = c.take<int>(4);
+    s.pdrops = s.status + 1;
+    s.all_locked = s.status + 2;
+    return c.size();
+}
+
+static sc_status validate(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobpcg_opts* o) {
+    if (!o) return sc_fail(ctx, SC_E_INVAL, "lobpcg: opts is NULL");
+    if (n <= 0 || nnz < 0) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need n > 0 and nnz >= 0");
+    if (o->k < 1) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need k >= 1");
+    if (o->k > 256) return sc_fail(ctx, SC_E_UNSUPPORTED, "lobpcg: k = %d > 256", o->k);
+    if (3 * (int64_t)o->k > n) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need 3k <= n");
+    if (o->maxit < 0) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need maxit >= 0");
+    if (o->ldx < o->k) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need ldx >= k");
+    if (!(o->tol >= 0.0)) return sc_fail(ctx, SC_E_INVAL, "lobpcg: need tol >= 0");
+    if (o->prec != SC_PREC_FP64 && o->prec != SC_PREC_FP32 && o->prec != SC_PREC_FP32_BF16GRAM)
+        return sc_fail(ctx, SC_E_INVAL, "lobpcg: unknown precision");
+    return SC_OK;
+}
+
+extern "C" sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz,
+                                         const sc_lobpcg_opts* opts, size_t* bytes) {
+    if (!ctx || !bytes) return SC_E_INVAL;
+    SC_TRY(validate(ctx, n, nnz, opts));
+    Carver c(nullptr);
+    sc_lobpcg_state s;
+    *bytes = carve(c, n, opts->k, opts->maxit, opts->prec, s);
+    return SC_OK;
+}
+
+namespace {
+
+template <class T>
+struct Solver {
+    static T* S(sc_lobpcg_state* s) { return static_cast<T*>(s->S); }
+    static T* LS(sc_lobpcg_state* s) { return static_cast<T*>(s->LS); }
+    static const T* val(sc_lobpcg_state* s) { return static_cast<const T*>(s->val); }
+
+    // W/X/P block CholQR with mask `m` (kp columns at column offset `off`)
+    static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int drop) {
+        const int64_t ld = s->K3;
+        T* V = S(s) + off;
+        SC_TRY(launch_gram<T>(ctx, s->plank, V, ld, V, ld, nullptr, 0, s->Gwpart, s->Gw, nullptr, 0));
+        SC_TRY(launch_cholqr_factor(ctx, s->kp, s->Gw, s->act + off, s->chol_tol, s->T64, s->T32,
+                                    s->cq_scr, drop, s->status, drop ? s->pdrops : nullptr));
+        SC_TRY(launch_apply_right<T>(ctx, s->n, s->kp, V, ld, with_L ? LS(s) + off : nullptr, ld,
+                                     s->T64, s->T32));
+        return SC_OK;
+    }
+
+    static sc_status rr_and_update(sc_ctx* ctx, sc_lobpcg_state* s) {
+        const int64_t ld = s->K3;
+        const int bf16 = s->prec == SC_PREC_FP32_BF16GRAM;
+        SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA, s->GB,
+                              bf16));
+        SC_TRY(launch_rayleigh_ritz(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
+                                    s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops));
+        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, S(s), ld, s->C64, s->C32));
+        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, LS(s), ld, s->C64, s->C32));
+        return SC_OK;
+    }
+
+    // residual of the current iterate, history row t, W mask; one sync
+    static sc_status residual(sc_ctx* ctx, sc_lobpcg_state* s) {
+        int nb = 0;
+        SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
+                                  s->res_part, &nb));
+        SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->lock_tol, s->relres,
+                                        s->hist + (int64_t)s->t * s->kp, s->act + s->kp, s->status,
+                                        s->out_max, s->all_locked));
+        char* h = static_cast<char*>(ctx->stage);
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, 4 * sizeof(int), hipMemcpyDeviceToHost,
+                                         ctx->stream));
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(h + 16, s->out_max, sizeof(double), hipMemcpyDeviceToHost,
+                                         ctx->stream));
+        SC_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        const int* st = reinterpret_cast<const int*>(h);
+        if (st[0] & DEV_BREAKDOWN)
+            return sc_fail(ctx, SC_E_BREAKDOWN,
+                           "lobpcg: Cholesky breakdown (rank-deficient block or Gram matrix)");
+        if (st[0] & DEV_NUMERIC)
+            return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in a residual");
+        double mx;
+        memcpy(&mx, h + 16, sizeof(double));
+        s->max_relres = mx;
+        s->converged = (mx <= s->tol) || st[2];
+        s->done = s->converged || s->t >= s->maxit;
+        return SC_OK;
+    }
+
+    static sc_status begin(sc_ctx* ctx, sc_lobpcg_state* s, const void* X0) {
+        hipStream_t st = ctx->stream;
+        const int64_t ld = s->K3;
+        const int64_t words = (int64_t)s->n * s->K3 * (int64_t)sizeof(T) / 4;
+        hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->S, words);
+        hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->LS, words);
+        hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->status, (int64_t)4);
+        SC_CHECK_LAUNCH(ctx);
+        hipLaunchKernelGGL((k_load_block<T, T>), dim3(ceil_div(s->n * s->kp, 256)), dim3(256), 0, st,
+                           s->n, s->k, s->kp, static_cast<const T*>(X0), s->ldx, S(s), ld, s->status);
+        SC_CHECK_LAUNCH(ctx);
+        {
+            int* h = static_cast<int*>(ctx->stage);
+            SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, sizeof(int), hipMemcpyDeviceToHost, st));
+            SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
+            if (h[0] & DEV_NUMERIC) return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in X0");
+        }
+        // X <- CholQR2(X0)
+        for (int rep = 0; rep < 2; ++rep) {
+            hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->kp, s->k);
+            SC_TRY(cholqr(ctx, s, 0, 0, 0));
+        }
+        SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+        // Rayleigh-Ritz on span(X) alone
+        hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
+        SC_CHECK_LAUNCH(ctx);
+        SC_TRY(rr_and_update(ctx, s));
+        s->t = 0;
+        s->has_p = 0;
+        SC_TRY(residual(ctx, s));
+        return SC_OK;
+    }
+
+    static sc_status step(sc_ctx* ctx, sc_lobpcg_state* s) {
+        hipStream_t st = ctx->stream;
+        const int64_t ld = s->K3;
+        const int kp = s->kp;
+        // X stays fully active; the W mask was set by the residual step
+        hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, kp, s->k);
+        SC_CHECK_LAUNCH(ctx);
+        SC_TRY(cholqr(ctx, s, kp, 0, 0));
+        SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s) + kp, ld,
+                              LS(s) + kp, ld));
+        hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
+                           s->has_p ? s->k : 0);
+        SC_CHECK_LAUNCH(ctx);
+        if (s->has_p) SC_TRY(cholqr(ctx, s, 2 * kp, 1, 1));
+        SC_TRY(rr_and_update(ctx, s));
+        s->has_p = 1;
+        s->t += 1;
+        SC_TRY(residual(ctx, s));
+        return SC_OK;
+    }
+
+    static sc_status finish(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
+                            double* relres_hist, sc_lobpcg_info* info) {
+        hipStream_t st = ctx->stream;
+        if (X_out) {
+            hipLaunchKernelGGL((k_store_block<T>), dim3(ceil_div(s->n * s->k, 256)), dim3(256), 0,
+                               st, s->n, s->k, S(s), s->K3, static_cast<T*>(X_out), s->ldx);
+            SC_CHECK_LAUNCH(ctx);
+        }
+        if (theta)
+            SC_CHECK_HIP(ctx, hipMemcpyAsync(theta, s->theta, s->k * sizeof(double),
+                                             hipMemcpyDeviceToDevice, st));
+        const int rows = s->t + 1;
+        std::vector<double> h((size_t)rows * s->kp);
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(h.data(), s->hist, h.size() * sizeof(double),
+                                         hipMemcpyDeviceToHost, st));
+        int cnt[4];
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(cnt, s->status, sizeof cnt, hipMemcpyDeviceToHost, st));
+        SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
+        if (relres_hist)
+            for (int r = 0; r < rows; ++r)
+                for (int j = 0; j < s->k; ++j) relres_hist[(int64_t)r * s->k + j] = h[(size_t)r * s->kp + j];
+        if (info) {
+            info->iterations = s->t;
+            info->converged = s->converged;
+            info->p_drops = cnt[1];
+            int locked = 0;
+            for (int j = 0; j < s->k; ++j) locked += h[(size_t)s->t * s->kp + j] <= s->lock_tol;
+            info->locked_cols = locked;
+            info->max_relres = s->max_relres;
+        }
+        return SC_OK;
+    }
+};
+
+sc_status dispatch_begin(sc_ctx* ctx, sc_lobpcg_state* s, const void* X0) {
+    return s->prec == SC_PREC_FP64 ? Solver<double>::begin(ctx, s, X0)
+                                   : Solver<float>::begin(ctx, s, X0);
+}
+sc_status dispatch_step(sc_ctx* ctx, sc_lobpcg_state* s) {
+    return s->prec == SC_PREC_FP64 ? Solver<double>::step(ctx, s) : Solver<float>::step(ctx, s);
+}
+sc_status dispatch_finish(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
+                          double* relres_hist, sc_lobpcg_info* info) {
+    return s->prec == SC_PREC_FP64 ? Solver<double>::finish(ctx, s, X_out, theta, relres_hist, info)
+                                   : Solver<float>::finish(ctx, s, X_out, theta, relres_hist, info);
+}
+
+}  // namespace
+
+extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                     const int32_t* col, const void* val,
+                                     const sc_lobpcg_opts* opts, const void* X0, void* ws,
+                                     size_t ws_bytes, sc_lobpcg_state** state, int* done) {
+    if (!ctx || !state) return SC_E_INVAL;
+    *state = nullptr;
+    SC_TRY(validate(ctx, n, nnz, opts));
+    if (!row_ptr || !X0 || !ws || (nnz > 0 && (!col || !val)))
+        return sc_fail(ctx, SC_E_INVAL, "lobpcg: null pointer argument");
+    sc_lobpcg_state* s = new sc_lobpcg_state();
+    Carver c(ws);
+    const size_t need = carve(c, n, opts->k, opts->maxit, opts->prec, *s);
+    if (ws_bytes < need) {
+        delete s;
+        return sc_fail(ctx, SC_E_NOMEM, "lobpcg: workspace %zu < %zu bytes", ws_bytes, need);
+    }
+    s->n = n;
+    s->nnz = nnz;
+    s->row_ptr = row_ptr;
+    s->col = col;
+    s->val = val;
+    s->k = opts->k;
+    s->maxit = opts->maxit;
+    s->tol = opts->tol;
+    s->prec = opts->prec;
+    s->ldx = opts->ldx;
+    const bool f64 = opts->prec == SC_PREC_FP64;
+    s->lock_tol = opts->lock_tol > 0 ? opts->lock_tol : (f64 ? 1e-13 : 1e-6);
+    s->chol_tol = opts->chol_tol > 0 ? opts->chol_tol : (f64 ? 1e-14 : 1e-6);
+    sc_status st = hipSetDevice(ctx->device) == hipSuccess ? SC_OK : SC_E_HIP;
+    if (st == SC_OK) st = dispatch_begin(ctx, s, X0);
+    if (st != SC_OK) {
+        delete s;
+        return st;
+    }
+    *state = s;
+    if (done) *done = s->done;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_lobpcg_step(sc_ctx* ctx, sc_lobpcg_state* s, int* done) {
+    if (!ctx || !s) return SC_E_INVAL;
+    if (!s->done) SC_TRY(dispatch_step(ctx, s));
+    if (done) *done = s->done;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
+                                   double* relres_hist, sc_lobpcg_info* info) {
+    if (!ctx || !s) return SC_E_INVAL;
+    sc_status st = dispatch_finish(ctx, s, X_out, theta, relres_hist, info);
+    delete s;
+    return st;
+}
+
+extern "C" sc_status sc_lobpcg_solve(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                     const int32_t* col, const void* val,
+                                     const sc_lobpcg_opts* opts, const void* X0, void* X_out,
+                                     double* theta, double* relres_hist, sc_lobpcg_info* info,
+                                     void* ws, size_t ws_bytes) {
+    sc_lobpcg_state* s = nullptr;
+    int done = 0;
+    SC_TRY(sc_lobpcg_begin(ctx, n, nnz, row_ptr, col, val, opts, X0, ws, ws_bytes, &s, &done));
+    while (!done) {
+        sc_status st = sc_lobpcg_step(ctx, s, &done);
+        if (st != SC_OK) {
+            delete s;
+            return st;
+        }
+    }
+    return sc_lobpcg_end(ctx, s, X_out, theta, relres_hist, info);
+}

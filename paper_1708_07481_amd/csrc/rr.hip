@@ -1,0 +1,492 @@
+// Rayleigh-Ritz step of LOBPCG in FP64 on one workgroup, and the dense
+// symmetric eigensolver it uses (exposed as sc_symeig for testing).
+//
+// Given the Gram matrices G_A = S'LS and G_B = S'S of the basis S = [X W P]
+// and the mask of active columns:
+//   B = G_B[act,act] = U'U (Cholesky; on failure with P active, P leaves the
+//   basis and the factorisation is redone; a second failure is a breakdown);
+//   M = U^-T G_A[act,act] U^-1, symmetrised;
+//   M = Q diag(lambda) Q' for the k smallest eigenvalues:
+//     Householder reduction to tridiagonal form, bisection with Sturm counts
+//     for the k smallest eigenvalues, inverse iteration with a pivoted
+//     tridiagonal LU for their eigenvectors (vectors of tightly clustered
+//     eigenvalues are re-orthogonalised by modified Gram-Schmidt), and the
+//     Householder reflectors applied back;
+//   C = U^-1 Q (scattered to the rows of the active columns), theta = lambda.
+// The matrices live in a global scratch area (L2 resident at these sizes).
+#include <float.h>
+
+#include "sc_internal.h"
+
+namespace {
+
+constexpr int NT = 1024;
+constexpr int NWAVE = NT / 64;
+constexpr int MAXM = 1024;
+
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NWAVE; ++w) s += red[w];
+        red[NWAVE] = s;
+    }
+    __syncthreads();
+    const double r = red[NWAVE];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline double block_max(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = red[0];
+        for (int w = 1; w < NWAVE; ++w) s = fmax(s, red[w]);
+        red[NWAVE] = s;
+    }
+    __syncthreads();
+    const double r = red[NWAVE];
+    __syncthreads();
+    return r;
+}
+
+__device__ inline uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// Householder reduction of the symmetric m x m matrix A (row-major, both
+// triangles kept current) to tridiagonal form: diagonal d, off-diagonal e.
+// Reflector j (acting on rows j+1..m-1) is I - tau_j v v' with v_0 = 1 and
+// v_r (r >= 1) stored in A[j][j+1+r].
+__device__ void tridiagonalize(int m, double* A, double* d, double* e, double* tau, double* v,
+                               double* p, double* red, double* sh) {
+    const int tid = threadIdx.x;
+    for (int j = 0; j + 2 < m; ++j) {
+        const int len = m - j - 1;
+        const double* x = A + (int64_t)j * m + j + 1;   // row j right of the diagonal
+        double part = 0.0;
+        for (int r = 1 + tid; r < len; r += NT) part = fma(x[r], x[r], part);
+        const double sigma = block_sum(part, red);
+        if (tid == 0) {
+            const double x0 = x[0];
+            d[j] = A[(int64_t)j * m + j];
+            if (sigma == 0.0) {
+                tau[j] = 0.0;
+                e[j] = x0;
+                sh[0] = 1.0;
+            } else {
+                const double mu = sqrt(x0 * x0 + sigma);
+                const double v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+                tau[j] = 2.0 * v0 * v0 / (sigma + v0 * v0);
+                e[j] = mu;
+                sh[0] = v0;
+            }
+        }
+        __syncthreads();
+        const double tj = tau[j];
+        if (tj == 0.0) {
+            __syncthreads();
+            continue;
+        }
+        const double v0 = sh[0];
+        for (int r = tid; r < len; r += NT) v[r] = r == 0 ? 1.0 : x[r] / v0;
+        __syncthreads();
+        // p = tau A22 v, read column-wise (A22 symmetric) for coalescing
+        const double* A22 = A + (int64_t)(j + 1) * m + (j + 1);
+        for (int r = tid; r < len; r += NT) {
+            double s = 0.0;
+            for (int c = 0; c < len; ++c) s = fma(A22[(int64_t)c * m + r], v[c], s);
+            p[r] = tj * s;
+        }
+        __syncthreads();
+        part = 0.0;
+        for (int r = tid; r < len; r += NT) part = fma(p[r], v[r], part);
+        const double K = 0.5 * tj * block_sum(part, red);
+        for (int r = tid; r < len; r += NT) p[r] = p[r] - K * v[r];   // p <- w
+        __syncthreads();
+        double* B22 = A + (int64_t)(j + 1) * m + (j + 1);
+        for (int64_t q = tid; q < (int64_t)len * len; q += NT) {
+            const int r = (int)(q / len), c = (int)(q % len);
+            B22[(int64_t)r * m + c] -= v[r] * p[c] + p[r] * v[c];
+        }
+        __syncthreads();
+        // keep the reflector in row j (no longer read by later steps)
+        double* xs = A + (int64_t)j * m + j + 1;
+        for (int r = 1 + tid; r < len; r += NT) xs[r] = v[r];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (m >= 2) {
+            d[m - 2] = A[(int64_t)(m - 2) * m + (m - 2)];
+            e[m - 2] = A[(int64_t)(m - 2) * m + (m - 1)];
+            tau[m - 2] = 0.0;
+        }
+        d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)];
+        if (m >= 1) tau[m - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// number of eigenvalues of the tridiagonal (d, e) smaller than x
+__device__ inline int sturm_count(int m, const double* d, const double* e, double x, double pivmin) {
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+    for (int i = 1; i < m; ++i) {
+        q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++c;
+    }
+    return c;
+}
+
+// k smallest eigenpairs of the m x m symmetric matrix A (destroyed).  w[k]
+// ascending; V (m x k, row stride ldv) eigenvectors.  `ws` scratch of
+// symeig_scratch_elems(m, k) doubles.
+__device__ void eig_lowest(int m, int k, double* A, double* w, double* V, int ldv, double* ws,
+                           double* red, double* sh) {
+    const int tid = threadIdx.x;
+    double* d = ws;
+    double* e = d + m;
+    double* tau = e + m;
+    double* v = tau + m;
+    double* p = v + m;
+    double* shift = p + m;             // k perturbed shifts
+    double* lu = shift + k;            // k x 6m per-thread LU storage
+    tridiagonalize(m, A, d, e, tau, v, p, red, sh);
+    // Gershgorin interval and scale
+    double lo_l = DBL_MAX, hi_l = -DBL_MAX, nrm_l = 0.0, emax_l = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
+        const double er = i + 1 < m ? fabs(e[i]) : 0.0;
+        lo_l = fmin(lo_l, d[i] - el - er);
+        hi_l = fmax(hi_l, d[i] + el + er);
+        nrm_l = fmax(nrm_l, fabs(d[i]) + el + er);
+        if (i + 1 < m) emax_l = fmax(emax_l, e[i] * e[i]);
+    }
+    const double gl = -block_max(-lo_l, red);
+    const double gu = block_max(hi_l, red);
+    const double tnorm = fmax(block_max(nrm_l, red), DBL_MIN);
+    const double emax2 = block_max(emax_l, red);
+    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    const double eps = DBL_EPSILON;
+    // bisection: thread i finds the (i+1)-th smallest eigenvalue
+    for (int i = tid; i < k; i += NT) {
+        double lo = gl - 2.0 * eps * tnorm - 2.0 * pivmin, hi = gu + 2.0 * eps * tnorm + 2.0 * pivmin;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 1e-18 * tnorm) break;
+            if (sturm_count(m, d, e, mid, pivmin) <= i) lo = mid;
+            else hi = mid;
+        }
+        w[i] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    // shifts: coincident eigenvalues are pulled apart slightly so that the
+    // inverse iterations start from distinct factorisations
+    if (tid == 0) {
+        const double sep = 10.0 * eps * tnorm;
+        for (int i = 0; i < k; ++i) {
+            double s = w[i];
+            if (i > 0 && s - shift[i - 1] < sep) s = shift[i - 1] + sep;
+            shift[i] = s;
+        }
+    }
+    __syncthreads();
+    // inverse iteration, one eigenvector per thread
+    const double tiny = eps * tnorm;
+    for (int i = tid; i < k; i += NT) {
+        double* U0 = lu + (int64_t)i * 6 * m;
+        double* U1 = U0 + m;
+        double* U2 = U1 + m;
+        double* Lm = U2 + m;
+        double* SW = Lm + m;
+        double* z = SW + m;
+        const double lam = shift[i];
+        // LU of T - lam I with partial pivoting; (r0, r1) is the current row
+        // (columns q, q+1) left after eliminating the rows above it
+        double r0 = d[0] - lam, r1 = m > 1 ? e[0] : 0.0;
+        for (int q = 0; q + 1 < m; ++q) {
+            const double sub = e[q];                       // row q+1: (sub, a1, b1)
+            const double a1 = d[q + 1] - lam;
+            const double b1 = q + 2 < m ? e[q + 1] : 0.0;
+            if (fabs(r0) >= fabs(sub)) {
+                if (r0 == 0.0) r0 = tiny;
+                const double l = sub / r0;
+                U0[q] = r0; U1[q] = r1; U2[q] = 0.0; Lm[q] = l; SW[q] = 0.0;
+                r0 = a1 - l * r1;
+                r1 = b1;
+            } else {
+                const double l = r0 / sub;
+                U0[q] = sub; U1[q] = a1; U2[q] = b1; Lm[q] = l; SW[q] = 1.0;
+                r0 = r1 - l * a1;
+                r1 = -l * b1;
+            }
+        }
+        if (r0 == 0.0) r0 = tiny;
+        U0[m - 1] = r0;
+        for (int r = 0; r < m; ++r)
+            z[r] = (double)(mix64(((uint64_t)i << 32) ^ (uint64_t)r) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        for (int itn = 0; itn < 3; ++itn) {
+            double rc = z[0];
+            for (int q = 0; q + 1 < m; ++q) {
+                const double nxt = z[q + 1];
+                if (SW[q] != 0.0) {
+                    z[q] = nxt;
+                    rc = rc - Lm[q] * nxt;
+                } else {
+                    z[q] = rc;
+                    rc = nxt - Lm[q] * rc;
+                }
+            }
+            z[m - 1] = rc;
+            for (int q = m - 1; q >= 0; --q) {
+                double sacc = z[q];
+                if (q + 1 < m) sacc -= U1[q] * z[q + 1];
+                if (q + 2 < m) sacc -= U2[q] * z[q + 2];
+                z[q] = sacc / U0[q];
+            }
+            double nn = 0.0;
+            for (int r = 0; r < m; ++r) nn = fma(z[r], z[r], nn);
+            const double inv = 1.0 / sqrt(nn);
+            for (int r = 0; r < m; ++r) z[r] *= inv;
+        }
+        for (int r = 0; r < m; ++r) V[(int64_t)r * ldv + i] = z[r];
+    }
+    __syncthreads();
+    // modified Gram-Schmidt (twice) inside clusters of close eigenvalues
+    const double ctol = 1e-4 * tnorm;
+    for (int c0 = 0; c0 < k;) {
+        int c1 = c0 + 1;
+        while (c1 < k && w[c1] - w[c1 - 1] <= ctol) ++c1;
+        if (c1 - c0 > 1) {
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int q = c0; q < c1; ++q) {
+                    for (int pp = c0; pp < q; ++pp) {
+                        double part = 0.0;
+                        for (int r = tid; r < m; r += NT)
+                            part = fma(V[(int64_t)r * ldv + pp], V[(int64_t)r * ldv + q], part);
+                        const double dt = block_sum(part, red);
+                        for (int r = tid; r < m; r += NT)
+                            V[(int64_t)r * ldv + q] -= dt * V[(int64_t)r * ldv + pp];
+                        __syncthreads();
+                    }
+                    double part = 0.0;
+                    for (int r = tid; r < m; r += NT)
+                        part = fma(V[(int64_t)r * ldv + q], V[(int64_t)r * ldv + q], part);
+                    const double inv = 1.0 / sqrt(block_sum(part, red));
+                    for (int r = tid; r < m; r += NT) V[(int64_t)r * ldv + q] *= inv;
+                    __syncthreads();
+                }
+            }
+        }
+        c0 = c1;
+    }
+    // back-transform: Q = H_0 H_1 ... H_{m-3} Z, one column per thread
+    for (int i = tid; i < k; i += NT) {
+        for (int j = m - 3; j >= 0; --j) {
+            const double tj = tau[j];
+            if (tj == 0.0) continue;
+            const double* vj = A + (int64_t)j * m + j + 1;   // v_0 = 1 implicit
+            double s = V[(int64_t)(j + 1) * ldv + i];
+            for (int r = 1; r < m - j - 1; ++r) s = fma(vj[r], V[(int64_t)(j + 1 + r) * ldv + i], s);
+            s *= tj;
+            V[(int64_t)(j + 1) * ldv + i] -= s;
+            for (int r = 1; r < m - j - 1; ++r) V[(int64_t)(j + 1 + r) * ldv + i] -= s * vj[r];
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(NT) k_symeig(int m, int k, const double* __restrict__ Ain,
+                                               double* __restrict__ w, double* __restrict__ V,
+                                               double* __restrict__ scr) {
+    __shared__ double red[NWAVE + 1];
+    __shared__ double sh[4];
+    double* A = scr;
+    for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += NT) A[q] = Ain[q];
+    __syncthreads();
+    eig_lowest(m, k, A, w, V, k, scr + (int64_t)m * m, red, sh);
+}
+
+__global__ void __launch_bounds__(NT)
+k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const double* __restrict__ GB,
+                int* __restrict__ act, double tol, double* __restrict__ C64, float* __restrict__ C32,
+                double* __restrict__ theta, double* __restrict__ scr, int* status, int* counter) {
+    __shared__ double red[NWAVE + 1];
+    __shared__ double sh[4];
+    __shared__ int idx[MAXM];
+    __shared__ int m_s, fail_s;
+    const int tid = threadIdx.x;
+    double* U = scr;                               // K3 x K3 (m x m used)
+    double* Ui = U + (int64_t)K3 * K3;
+    double* M = Ui + (int64_t)K3 * K3;
+    double* Tm = M + (int64_t)K3 * K3;
+    double* Q = Tm + (int64_t)K3 * K3;             // m x k
+    double* ews = Q + (int64_t)K3 * k;             // eigensolver scratch
+    int m = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (tid == 0) {
+            int mm = 0;
+            for (int j = 0; j < K3; ++j)
+                if (act[j]) idx[mm++] = j;
+            m_s = mm;
+            fail_s = 0;
+        }
+        __syncthreads();
+        m = m_s;
+        for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
+            const int a = (int)(q / m), b = (int)(q % m);
+            U[q] = GB[(int64_t)idx[a] * K3 + idx[b]];
+        }
+        __syncthreads();
+        // right-looking Cholesky B = U'U in place (upper triangle)
+        for (int j = 0; j < m; ++j) {
+            if (tid == 0) {
+                const double s = U[(int64_t)j * m + j];
+                const double g = GB[(int64_t)idx[j] * K3 + idx[j]];
+                if (!isfinite(s) || !(s > tol * g) || !(s > 0.0)) fail_s = 1;
+                else U[(int64_t)j * m + j] = sqrt(s);
+            }
+            __syncthreads();
+            if (fail_s) break;
+            const double rjj = U[(int64_t)j * m + j];
+            for (int b = j + 1 + tid; b < m; b += NT) U[(int64_t)j * m + b] /= rjj;
+            __syncthreads();
+            const int len = m - j - 1;
+            for (int64_t q = tid; q < (int64_t)len * len; q += NT) {
+                const int a = j + 1 + (int)(q / len), b = j + 1 + (int)(q % len);
+                if (b >= a) U[(int64_t)a * m + b] -= U[(int64_t)j * m + a] * U[(int64_t)j * m + b];
+            }
+            __syncthreads();
+        }
+        if (!fail_s) break;
+        // drop P (columns 2kp..3kp) and retry once
+        __shared__ int has_p;
+        if (tid == 0) {
+            has_p = 0;
+            for (int j = 2 * kp; j < K3; ++j) has_p |= act[j];
+        }
+        __syncthreads();
+        if (!has_p || attempt == 1) {
+            if (tid == 0) atomicOr(status, DEV_BREAKDOWN);
+            return;
+        }
+        for (int j = 2 * kp + tid; j < K3; j += NT) act[j] = 0;
+        if (tid == 0) {
+            atomicOr(status, DEV_P_DROPPED);
+            if (counter) atomicAdd(counter, 1);
+        }
+        __syncthreads();
+    }
+    // U^-1 (upper), one column per thread
+    for (int j = tid; j < m; j += NT) {
+        for (int a = 0; a < m; ++a) Ui[(int64_t)a * m + j] = 0.0;
+        Ui[(int64_t)j * m + j] = 1.0 / U[(int64_t)j * m + j];
+        for (int a = j - 1; a >= 0; --a) {
+            double s = 0.0;
+            for (int l = a + 1; l <= j; ++l) s = fma(U[(int64_t)a * m + l], Ui[(int64_t)l * m + j], s);
+            Ui[(int64_t)a * m + j] = -s / U[(int64_t)a * m + a];
+        }
+    }
+    __syncthreads();
+    // Tm = A U^-1, then M = U^-T Tm, symmetrised
+    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
+        const int a = (int)(q / m), b = (int)(q % m);
+        const double* arow = GA + (int64_t)idx[a] * K3;
+        double s = 0.0;
+        for (int l = 0; l <= b; ++l) s = fma(arow[idx[l]], Ui[(int64_t)l * m + b], s);
+        Tm[q] = s;
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
+        const int a = (int)(q / m), b = (int)(q % m);
+        double s = 0.0;
+        for (int l = 0; l <= a; ++l) s = fma(Ui[(int64_t)l * m + a], Tm[(int64_t)l * m + b], s);
+        M[q] = s;
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
+        const int a = (int)(q / m), b = (int)(q % m);
+        if (a < b) {
+            const double s = 0.5 * (M[(int64_t)a * m + b] + M[(int64_t)b * m + a]);
+            M[(int64_t)a * m + b] = s;
+            M[(int64_t)b * m + a] = s;
+        }
+    }
+    __syncthreads();
+    eig_lowest(m, k, M, theta, Q, k, ews, red, sh);
+    // C = U^-1 Q scattered to the active rows; zero elsewhere
+    for (int64_t q = tid; q < (int64_t)K3 * kp; q += NT) {
+        C64[q] = 0.0;
+        C32[q] = 0.0f;
+    }
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)m * k; q += NT) {
+        const int a = (int)(q / k), i = (int)(q % k);
+        double s = 0.0;
+        for (int l = a; l < m; ++l) s = fma(Ui[(int64_t)a * m + l], Q[(int64_t)l * k + i], s);
+        C64[(int64_t)idx[a] * kp + i] = s;
+        C32[(int64_t)idx[a] * kp + i] = (float)s;
+    }
+    for (int i = k + tid; i < kp; i += NT) theta[i] = 0.0;
+}
+
+}  // namespace
+
+size_t symeig_scratch_elems(int m, int k) {
+    return (size_t)m * m + 5 * (size_t)m + k + 6 * (size_t)m * k + 64;
+}
+
+size_t rr_scratch_elems(int K3, int k) {
+    return 4 * (size_t)K3 * K3 + (size_t)K3 * k + symeig_scratch_elems(K3, k);
+}
+
+sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
+                               const double* GB, int* act, double tol, double* C64, float* C32,
+                               double* theta, double* scratch, int* status, int* counter) {
+    if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
+    hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(NT), 0, ctx->stream, K3, kp, k, GA, GB, act,
+                       tol, C64, C32, theta, scratch, status, counter);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
+sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
+                        double* scratch) {
+    hipLaunchKernelGGL(k_symeig, dim3(1), dim3(NT), 0, ctx->stream, m, k, A, w, V, scratch);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
+extern "C" sc_status sc_symeig_workspace(sc_ctx* ctx, int m, int k, size_t* bytes) {
+    if (!ctx || !bytes) return SC_E_INVAL;
+    if (m <= 0 || k <= 0 || k > m || m > MAXM)
+        return sc_fail(ctx, SC_E_INVAL, "symeig: need 0 < k <= m <= %d", MAXM);
+    *bytes = (symeig_scratch_elems(m, k) + (size_t)m * m) * sizeof(double) + 256;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
+                               void* ws, size_t ws_bytes) {
+    if (!ctx) return SC_E_INVAL;
+    size_t need = 0;
+    SC_TRY(sc_symeig_workspace(ctx, m, k, &need));
+    if (!A || !w || !V || !ws) return sc_fail(ctx, SC_E_INVAL, "symeig: null pointer argument");
+    if (ws_bytes < need) return sc_fail(ctx, SC_E_NOMEM, "symeig: workspace too small");
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    return launch_symeig(ctx, m, k, A, w, V, static_cast<double*>(ws));
+}

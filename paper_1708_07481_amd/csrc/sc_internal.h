@@ -1,0 +1,148 @@
+// Internal declarations of the gfx950 spectral-clustering library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "../../include/spectral.h"
+
+struct sc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // pinned host staging area for the small device-to-host reads of the
+    // convergence tests (hipHostMalloc'ed once per context)
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
+};
+
+sc_status sc_fail(sc_ctx* ctx, sc_status st, const char* fmt, ...);
+
+#define SC_CHECK_HIP(ctx, call)                                                         \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return sc_fail((ctx), SC_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define SC_CHECK_LAUNCH(ctx) SC_CHECK_HIP(ctx, hipGetLastError())
+
+#define SC_TRY(expr)                     \
+    do {                                 \
+        sc_status s_ = (expr);           \
+        if (s_ != SC_OK) return s_;      \
+    } while (0)
+
+// Device status word bits (set with atomicOr by kernels, read by the host).
+enum : int {
+    DEV_BAD_INPUT = 1,      // id out of range / invalid weight
+    DEV_NUMERIC = 2,        // NaN or Inf
+    DEV_BREAKDOWN = 4,      // unrecoverable Cholesky failure
+    DEV_P_DROPPED = 8,      // P dropped in this iteration (informational)
+};
+
+// Bump allocator over a caller-provided workspace.  With base == nullptr it
+// only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+    template <class T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t size() const { return (off + 255) & ~size_t(255); }
+};
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int ceil_log2_u64(uint64_t v) {
+    int e = 0;
+    while (e < 64 && (uint64_t(1) << e) < v) ++e;
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide primitives (scan.hip, radix.hip)
+// ---------------------------------------------------------------------------
+// Exclusive (inclusive = 0) or inclusive scan of n uint64 values, in place
+// allowed.  tmp needs scan_u64_tmp_elems(n) elements.
+size_t scan_u64_tmp_elems(int64_t n);
+sc_status scan_u64(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n, int inclusive,
+                   uint64_t* tmp);
+// Batched inclusive scan: `batch` independent rows of length n (row stride n).
+sc_status scan_u64_batched(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n, int batch,
+                           uint64_t* tmp);
+size_t scan_u64_batched_tmp_elems(int64_t n, int batch);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.
+// Buffers: keys/vals (in/out), keys_alt/vals_alt (same size, scratch),
+// tmp: radix_tmp_elems(n) uint64.  Result ends in keys/vals.
+size_t radix_tmp_elems(int64_t n);
+sc_status radix_sort_pairs(sc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                           uint32_t* vals_alt, int64_t n, int bits, uint64_t* tmp);
+
+// ---------------------------------------------------------------------------
+// Kernels used by the LOBPCG driver (spmm.hip, dense.hip, rr.hip)
+// ---------------------------------------------------------------------------
+template <class T>
+sc_status launch_spmm(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                      const T* val, int k, const T* X, int64_t ldx, T* Y, int64_t ldy);
+
+// Gram products G1 = A^T B1 (and G2 = A^T B2 when B2 != nullptr), ca x cb,
+// upper triangle computed, mirrored; FP64 results.  A/B1/B2 are n x c blocks
+// of T with row strides.  bf16 != 0 (T = float only) rounds the inputs to
+// BF16 and accumulates in FP32 on the matrix cores.
+struct GramPlan {
+    int64_t n;
+    int c;          // columns of A and B (square Gram)
+    int chunks;     // row chunks (split-K)
+    int tiles;      // 64-wide tiles per side
+};
+GramPlan gram_plan(int64_t n, int c);
+size_t gram_partial_elems(const GramPlan& p, int nout);
+template <class T>
+sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, const T* B1,
+                      int64_t ldb1, const T* B2, int64_t ldb2, double* partial, double* G1,
+                      double* G2, int bf16);
+
+// Small-matrix Cholesky QR factor: from the c x c FP64 Gram G and the
+// active-column mask, T = D^-1 R^-1 (zero rows/cols for inactive columns).
+// On Cholesky failure: drop_on_fail ? (T = 0, mask = 0, status |= P_DROPPED,
+// counter[0]++) : status |= BREAKDOWN.
+sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, double tol,
+                               double* T64, float* T32, double* scratch, int drop_on_fail,
+                               int* status, int* counter);
+// V <- V T (and V2 <- V2 T) on n x c row blocks, in place.
+template <class T>
+sc_status launch_apply_right(sc_ctx* ctx, int64_t n, int c, T* V, int64_t ldv, T* V2,
+                             int64_t ldv2, const double* T64, const float* T32);
+// Block update on S (n x 3kp, row stride ld): P <- [W P] C_WP, X <- X C_X + P.
+template <class T>
+sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, T* S, int64_t ld, const double* C64,
+                              const float* C32);
+// Residual R = LX - X diag(theta) into W; per-block partial sums of R^2, X^2.
+template <class T>
+sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* LS, int64_t ld,
+                          const double* theta, double* partial, int* nblocks_out);
+// Finalise: relres, history row, W mask, flags; out[0] = max relres,
+// out_flags[0] = all columns locked.
+sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k,
+                                   const double* partial, double lock_tol, double* relres,
+                                   double* hist_row, int* wmask, int* status, double* out_max,
+                                   int* out_all_locked);
+
+// Rayleigh-Ritz (FP64) on the active columns: C (K3 x kp), theta (kp).
+size_t rr_scratch_elems(int K3, int k);
+sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
+                               const double* GB, int* act, double tol, double* C64, float* C32,
+                               double* theta, double* scratch, int* status, int* counter);
+sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
+                        double* scratch);
+size_t symeig_scratch_elems(int m, int k);

@@ -1,0 +1,117 @@
+"""GPU parity: graph symmetrisation, Laplacian values and SpMM through the
+C ABI against the oracle, element by element (bit-exact: integer CSR and
+degrees by definition; Laplacian values and FP64 SpMM because both sides
+evaluate the same IEEE operations in the same order)."""
+import numpy as np
+import pytest
+
+from synth import dcsbm
+from tests import graphs
+from tests.gpu_common import gpu_ctx, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _both(orc, ctx, n, src, dst, w=None, algebraic=False):
+    from paper_1708_07481_amd import api
+    go = orc.graph_build(n, src, dst, w, algebraic)
+    gd = api.graph_build(ctx, n, to_dev(src), to_dev(dst), None if w is None else to_dev(w),
+                         algebraic)
+    return go, gd
+
+
+def _assert_same_csr(go, gd):
+    assert gd.nnz == go.nnz
+    assert np.array_equal(host(gd.row_ptr), go.row_ptr)
+    assert np.array_equal(host(gd.col)[: go.nnz], go.col)
+    assert np.array_equal(host(gd.degree), go.degree)
+    assert gd.self_loops == go.self_loops
+
+
+CASES = [
+    ("tiny-multigraph", lambda: graphs.random_multigraph(17, 60, 1)),
+    ("isolated+loops", lambda: (50, np.array([0, 1, 1, 7, 7, 3], np.int32),
+                                np.array([1, 0, 1, 3, 49, 3], np.int32))),
+    ("cliques", lambda: graphs.cliques([5, 9, 13])),
+    ("ragged-2k", lambda: graphs.random_multigraph(2003, 30011, 4)),
+    ("sbm1k", lambda: (lambda g: (g.n, g.src, g.dst))(dcsbm(1000, 8, 20.0, 0.8, seed=1))),
+    ("sbm20k", lambda: (lambda g: (g.n, g.src, g.dst))(
+        dcsbm(20000, 32, 40.0, 0.75, "dirichlet", 5.0, seed=2))),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_graph_build_bit_exact(orc, ctx, name, make):
+    n, src, dst = make()
+    go, gd = _both(orc, ctx, n, src, dst)
+    _assert_same_csr(go, gd)
+
+
+def test_graph_build_algebraic_bit_exact(orc, ctx):
+    n, src, dst = graphs.random_multigraph(300, 5000, 9)
+    w = np.random.default_rng(9).random(src.shape[0])  # non-dyadic: order of the sums matters
+    go, gd = _both(orc, ctx, n, src, dst, w, True)
+    _assert_same_csr(go, gd)
+    assert np.array_equal(host(gd.w_sym)[: go.nnz], go.w)
+
+
+def test_graph_build_empty_and_errors(orc, ctx):
+    from paper_1708_07481_amd import api
+    from paper_1708_07481_amd._lib import SpectralError, SC_E_INVAL
+    go, gd = _both(orc, ctx, 5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    _assert_same_csr(go, gd)
+    with pytest.raises(SpectralError) as e:
+        api.graph_build(ctx, 4, to_dev(np.array([0, 4], np.int32)), to_dev(np.array([1, 2], np.int32)))
+    assert e.value.status == SC_E_INVAL
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_laplacian_bit_exact(orc, ctx, name, make):
+    from paper_1708_07481_amd import api
+    n, src, dst = make()
+    go, gd = _both(orc, ctx, n, src, dst)
+    vo, dio = orc.laplacian(go)
+    v64, v32, di = api.laplacian_csr(ctx, gd, True, True)
+    assert np.array_equal(host(v64)[: go.nnz], vo)
+    assert np.array_equal(host(v32)[: go.nnz], vo.astype(np.float32))
+    assert np.array_equal(host(di), dio)
+
+
+@pytest.mark.parametrize("k", [1, 5, 8, 19, 44, 64, 98, 130, 160])
+def test_spmm_fp64_bit_exact(orc, ctx, k):
+    from paper_1708_07481_amd import api
+    import torch
+    g0 = dcsbm(3001, 7, 24.0, 0.7, "dirichlet", 2.0, seed=k)
+    go, gd = _both(orc, ctx, g0.n, g0.src, g0.dst)
+    vo, _ = orc.laplacian(go)
+    v64, _, _ = api.laplacian_csr(ctx, gd)
+    X = np.random.default_rng(k).standard_normal((g0.n, k))
+    Yo = orc.spmm(go, vo, X)
+    Yd = host(api.spmm(ctx, gd, v64, to_dev(X)))
+    assert np.array_equal(Yd, Yo)
+    # strided operands (a block inside a wider row-major array)
+    big = torch.zeros((g0.n, 3 * k + 5), dtype=torch.float64, device="cuda")
+    big[:, k:2 * k] = to_dev(X)
+    out = torch.zeros((g0.n, 3 * k + 5), dtype=torch.float64, device="cuda")
+    api.spmm(ctx, gd, v64, big[:, k:2 * k], out[:, 2 * k:3 * k])
+    assert np.array_equal(host(out[:, 2 * k:3 * k]), Yo)
+    assert float(out[:, :2 * k].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("k", [8, 44, 160])
+def test_spmm_fp32(orc, ctx, k):
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(4000, 9, 30.0, 0.7, seed=k + 1)
+    go, gd = _both(orc, ctx, g0.n, g0.src, g0.dst)
+    vo, _ = orc.laplacian(go)
+    _, v32, _ = api.laplacian_csr(ctx, gd, False, True)
+    X = np.random.default_rng(k).standard_normal((g0.n, k)).astype(np.float32)
+    Yo = orc.spmm(go, vo, X.astype(np.float64))
+    Yd = host(api.spmm(ctx, gd, v32, to_dev(X))).astype(np.float64)
+    # FP32 arithmetic: |err| <= (deg + 1) * 2^-24 * (|x| + sum |v x|), well below 1e-5 here
+    assert np.max(np.abs(Yd - Yo)) < 1e-5 * max(1.0, np.abs(Yo).max())
