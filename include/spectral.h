@@ -215,6 +215,7 @@ typedef struct {
     int restarts;          /* k-means++ seedings, >= 1 */
     int max_iter;          /* Lloyd updates per restart, >= 0 */
     int normalize_rows;    /* 1: y_i = x_i / ||x_i|| (zero rows stay zero) */
+    int x_fp32;            /* 1: X is float32 (widened to float64 on load), 0: float64 */
 } sc_kmeans_opts;
 
 sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* opts,
@@ -232,7 +233,7 @@ sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_o
  *     sums in ascending vertex order / count (empty clusters keep theirs);
  *     stop when no label changes or after max_iter updates;
  *   best restart: least sum_i floor(mind_i * 2^s), ties to the lowest.
- *   X        float64 n x ldx (device)
+ *   X        float64 (or float32 when opts->x_fp32) n x ldx (device)
  *   draws    uint64 [restarts * K] uniform words (device), unused when
  *            init_centroids != NULL
  *   init_centroids float64 [K * dim] (device) or NULL; requires restarts = 1
@@ -241,11 +242,27 @@ sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_o
  *            (integer inertia), best_restart host out; each may be NULL.
  * Synchronises once per Lloyd iteration.
  */
-sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const double* X, int64_t ldx,
+sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx,
                            const sc_kmeans_opts* opts, const uint64_t* draws,
                            const double* init_centroids, int32_t* labels, double* centroids,
                            double* inertia, uint64_t* inertia_q, int* best_restart,
                            void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing on the context's stream (HIP events around every launch of
+ * the selected kinds).  Used to report per-kernel durations and roofline
+ * fractions; off by default.  Reading the totals synchronises the stream.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    SC_KIND_SPMM = 0, SC_KIND_GRAM = 1, SC_KIND_RR = 2, SC_KIND_UPDATE = 3,
+    SC_KIND_CHOLQR = 4, SC_KIND_RESIDUAL = 5, SC_KIND_GRAPH = 6, SC_KIND_KMEANS = 7,
+    SC_KIND_COUNT = 8
+} sc_kernel_kind;
+/* mask: bit (1 << kind) enables timing of that kind; 0 disables all. */
+sc_status sc_ctx_set_profiling(sc_ctx* ctx, unsigned mask);
+/* Launch count and summed duration (ms) of `kind` since the last reset. */
+sc_status sc_ctx_profile(sc_ctx* ctx, int kind, int64_t* launches, double* total_ms);
+sc_status sc_ctx_profile_reset(sc_ctx* ctx);
 
 /* ------------------------------------------------------------------------
  * Dense FP64 symmetric eigensolver used inside the Rayleigh-Ritz step,

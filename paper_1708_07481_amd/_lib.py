@@ -40,7 +40,13 @@ class sc_lobpcg_info(C.Structure):
 
 class sc_kmeans_opts(C.Structure):
     _fields_ = [("n_clusters", _int), ("restarts", _int), ("max_iter", _int),
-                ("normalize_rows", _int)]
+                ("normalize_rows", _int), ("x_fp32", _int)]
+
+
+SC_KIND_SPMM, SC_KIND_GRAM, SC_KIND_RR, SC_KIND_UPDATE, SC_KIND_CHOLQR, SC_KIND_RESIDUAL, \
+    SC_KIND_GRAPH, SC_KIND_KMEANS = range(8)
+KIND_NAMES = ["spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual",
+              "graph_build", "kmeans"]
 
 
 # name -> (restype, argtypes); every function declared in include/spectral.h
@@ -65,6 +71,9 @@ SIGNATURES = {
     "sc_kmeans_assign": (_int, [_p, _i64, _int, _p, _i64, C.POINTER(sc_kmeans_opts), _p, _p, _p,
                                 _p, C.POINTER(_dbl), C.POINTER(C.c_uint64), C.POINTER(_int), _p,
                                 _size]),
+    "sc_ctx_set_profiling": (_int, [_p, C.c_uint]),
+    "sc_ctx_profile": (_int, [_p, _int, C.POINTER(_i64), C.POINTER(_dbl)]),
+    "sc_ctx_profile_reset": (_int, [_p]),
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
 }

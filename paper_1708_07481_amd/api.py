@@ -43,6 +43,27 @@ class Context:
     def workspace(self, nbytes: int) -> torch.Tensor:
         return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
 
+    def set_profiling(self, kinds=()):
+        mask = 0
+        for k in kinds:
+            mask |= 1 << (_lib.KIND_NAMES.index(k) if isinstance(k, str) else int(k))
+        self.check(lib().sc_ctx_set_profiling(self.handle, mask), "sc_ctx_set_profiling")
+
+    def profile(self) -> dict:
+        out = {}
+        for i, name in enumerate(_lib.KIND_NAMES):
+            cnt = C.c_int64()
+            ms = C.c_double()
+            self.check(lib().sc_ctx_profile(self.handle, i, C.byref(cnt), C.byref(ms)),
+                       "sc_ctx_profile")
+            if cnt.value:
+                out[name] = {"launches": cnt.value, "total_ms": ms.value,
+                             "avg_ms": ms.value / cnt.value}
+        return out
+
+    def profile_reset(self):
+        self.check(lib().sc_ctx_profile_reset(self.handle), "sc_ctx_profile_reset")
+
     def close(self):
         if getattr(self, "handle", None):
             lib().sc_ctx_destroy(self.handle)
@@ -195,7 +216,10 @@ def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.T
         restarts = 1
     elif restarts is None:
         restarts = draws.shape[0]
-    opts = _lib.sc_kmeans_opts(n_clusters, restarts, max_iter, int(bool(normalize)))
+    if X.dtype not in (torch.float64, torch.float32):
+        raise TypeError("X must be float64 or float32")
+    opts = _lib.sc_kmeans_opts(n_clusters, restarts, max_iter, int(bool(normalize)),
+                               int(X.dtype == torch.float32))
     nb = C.c_size_t()
     ctx.check(lib().sc_kmeans_workspace(ctx.handle, n, dim, C.byref(opts), C.byref(nb)),
               "sc_kmeans_workspace")

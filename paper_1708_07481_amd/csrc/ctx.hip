@@ -38,8 +38,74 @@ extern "C" sc_status sc_ctx_create(int device, void* hip_stream, sc_ctx** out) {
 
 extern "C" sc_status sc_ctx_destroy(sc_ctx* ctx) {
     if (!ctx) return SC_E_INVAL;
+    prof_drain(ctx, true);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     delete ctx;
+    return SC_OK;
+}
+
+static hipEvent_t ev_get(sc_ctx* ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(sc_ctx* c, int k) : ctx(c), kind(k) {
+    if (!(ctx->prof_mask & (1u << kind))) return;
+    a = ev_get(ctx);
+    b = ev_get(ctx);
+    if (a && b) (void)hipEventRecord(a, ctx->stream);
+}
+
+ProfScope::~ProfScope() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->pending.push_back({kind, a, b});
+}
+
+void prof_drain(sc_ctx* ctx, bool sync) {
+    if (ctx->pending.empty()) return;
+    if (sync) (void)hipStreamSynchronize(ctx->stream);
+    for (auto& p : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->prof_count[p.kind] += 1;
+            ctx->prof_ms[p.kind] += ms;
+        }
+        ctx->pool.push_back(p.a);
+        ctx->pool.push_back(p.b);
+    }
+    ctx->pending.clear();
+}
+
+extern "C" sc_status sc_ctx_set_profiling(sc_ctx* ctx, unsigned mask) {
+    if (!ctx) return SC_E_INVAL;
+    prof_drain(ctx, true);
+    ctx->prof_mask = mask;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_ctx_profile(sc_ctx* ctx, int kind, int64_t* launches, double* total_ms) {
+    if (!ctx || kind < 0 || kind >= SC_KIND_COUNT) return SC_E_INVAL;
+    prof_drain(ctx, true);
+    if (launches) *launches = ctx->prof_count[kind];
+    if (total_ms) *total_ms = ctx->prof_ms[kind];
+    return SC_OK;
+}
+
+extern "C" sc_status sc_ctx_profile_reset(sc_ctx* ctx) {
+    if (!ctx) return SC_E_INVAL;
+    prof_drain(ctx, true);
+    for (int k = 0; k < SC_KIND_COUNT; ++k) {
+        ctx->prof_count[k] = 0;
+        ctx->prof_ms[k] = 0.0;
+    }
     return SC_OK;
 }
 

@@ -172,6 +172,7 @@ extern "C" sc_status sc_graph_build(sc_ctx* ctx, int64_t n, int64_t m, const int
     SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     const int64_t len = 2 * m;
+    ProfScope ps(ctx, SC_KIND_GRAPH);
     const uint64_t sentinel = (uint64_t)n * (uint64_t)n;
 
     SC_CHECK_HIP(ctx, hipMemsetAsync(g.loops, 0, sizeof(unsigned long long), st));

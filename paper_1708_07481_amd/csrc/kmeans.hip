@@ -22,24 +22,26 @@ constexpr int TH = 256;
 
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 
-__global__ void k_rownorm(int64_t n, int dim, const double* __restrict__ X, int64_t ldx,
+template <class TX>
+__global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx,
                           int normalize, double* __restrict__ Y, double* __restrict__ Yt,
                           unsigned long long* m2bits, int* status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double* x = X + i * ldx;
+    const TX* x = X + i * ldx;
     double s = 0.0;
     bool bad = false;
     for (int d = 0; d < dim; ++d) {
-        bad |= !isfinite(x[d]);
-        s = fma(x[d], x[d], s);
+        const double xd = (double)x[d];
+        bad |= !isfinite(xd);
+        s = fma(xd, xd, s);
     }
     if (bad) atomicOr(status, DEV_NUMERIC);
     const double nrm = sqrt(s);
     double s2 = 0.0;
     for (int d = 0; d < dim; ++d) {
-        double y = x[d];
-        if (normalize) y = nrm > 0.0 ? x[d] / nrm : 0.0;
+        double y = (double)x[d];
+        if (normalize) y = nrm > 0.0 ? y / nrm : 0.0;
         Y[i * dim + d] = y;
         Yt[(int64_t)d * n + i] = y;
         s2 = fma(y, y, s2);
@@ -291,7 +293,7 @@ extern "C" sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim,
     return SC_OK;
 }
 
-extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const double* X,
+extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X,
                                       int64_t ldx, const sc_kmeans_opts* opts,
                                       const uint64_t* draws, const double* init_centroids,
                                       int32_t* labels, double* centroids, double* inertia,
@@ -316,8 +318,15 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const dou
 
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.m2, 0, sizeof(unsigned long long), st));
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.status, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_rownorm, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, X, ldx,
-                       opts->normalize_rows, w.Y, w.Yt, w.m2, w.status);
+    ProfScope ps(ctx, SC_KIND_KMEANS);
+    if (opts->x_fp32)
+        hipLaunchKernelGGL((k_rownorm<float>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
+                           static_cast<const float*>(X), ldx, opts->normalize_rows, w.Y, w.Yt, w.m2,
+                           w.status);
+    else
+        hipLaunchKernelGGL((k_rownorm<double>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
+                           static_cast<const double*>(X), ldx, opts->normalize_rows, w.Y, w.Yt,
+                           w.m2, w.status);
     SC_CHECK_LAUNCH(ctx);
     char* h = static_cast<char*>(ctx->stage);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(h, w.m2, 8, hipMemcpyDeviceToHost, st));

@@ -150,6 +150,7 @@ struct Solver {
     static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int drop) {
         const int64_t ld = s->K3;
         T* V = S(s) + off;
+        ProfScope ps(ctx, SC_KIND_CHOLQR);
         SC_TRY(launch_gram<T>(ctx, s->plank, V, ld, V, ld, nullptr, 0, s->Gwpart, s->Gw, nullptr, 0));
         SC_TRY(launch_cholqr_factor(ctx, s->kp, s->Gw, s->act + off, s->chol_tol, s->T64, s->T32,
                                     s->cq_scr, drop, s->status, drop ? s->pdrops : nullptr));
@@ -161,10 +162,17 @@ struct Solver {
     static sc_status rr_and_update(sc_ctx* ctx, sc_lobpcg_state* s) {
         const int64_t ld = s->K3;
         const int bf16 = s->prec == SC_PREC_FP32_BF16GRAM;
-        SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA, s->GB,
-                              bf16));
-        SC_TRY(launch_rayleigh_ritz(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
-                                    s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops));
+        {
+            ProfScope ps(ctx, SC_KIND_GRAM);
+            SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
+                                  s->GB, bf16));
+        }
+        {
+            ProfScope ps(ctx, SC_KIND_RR);
+            SC_TRY(launch_rayleigh_ritz(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
+                                        s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops));
+        }
+        ProfScope ps(ctx, SC_KIND_UPDATE);
         SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, S(s), ld, s->C64, s->C32));
         SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, LS(s), ld, s->C64, s->C32));
         return SC_OK;
@@ -173,17 +181,22 @@ struct Solver {
     // residual of the current iterate, history row t, W mask; one sync
     static sc_status residual(sc_ctx* ctx, sc_lobpcg_state* s) {
         int nb = 0;
-        SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
-                                  s->res_part, &nb));
-        SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->lock_tol, s->relres,
-                                        s->hist + (int64_t)s->t * s->kp, s->act + s->kp, s->status,
-                                        s->out_max, s->all_locked));
+        {
+            ProfScope ps(ctx, SC_KIND_RESIDUAL);
+            SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
+                                      s->res_part, &nb));
+            SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->lock_tol,
+                                            s->relres, s->hist + (int64_t)s->t * s->kp,
+                                            s->act + s->kp, s->status, s->out_max,
+                                            s->all_locked));
+        }
         char* h = static_cast<char*>(ctx->stage);
         SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, 4 * sizeof(int), hipMemcpyDeviceToHost,
                                          ctx->stream));
         SC_CHECK_HIP(ctx, hipMemcpyAsync(h + 16, s->out_max, sizeof(double), hipMemcpyDeviceToHost,
                                          ctx->stream));
         SC_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        prof_drain(ctx, false);
         const int* st = reinterpret_cast<const int*>(h);
         if (st[0] & DEV_BREAKDOWN)
             return sc_fail(ctx, SC_E_BREAKDOWN,
@@ -220,7 +233,10 @@ struct Solver {
             hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->kp, s->k);
             SC_TRY(cholqr(ctx, s, 0, 0, 0));
         }
-        SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+        {
+            ProfScope ps(ctx, SC_KIND_SPMM);
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+        }
         // Rayleigh-Ritz on span(X) alone
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
         SC_CHECK_LAUNCH(ctx);
@@ -239,8 +255,11 @@ struct Solver {
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, kp, s->k);
         SC_CHECK_LAUNCH(ctx);
         SC_TRY(cholqr(ctx, s, kp, 0, 0));
-        SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s) + kp, ld,
-                              LS(s) + kp, ld));
+        {
+            ProfScope ps(ctx, SC_KIND_SPMM);
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s) + kp, ld,
+                                  LS(s) + kp, ld));
+        }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
                            s->has_p ? s->k : 0);
         SC_CHECK_LAUNCH(ctx);

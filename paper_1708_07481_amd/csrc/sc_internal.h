@@ -7,6 +7,7 @@
 #include <stdio.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/spectral.h"
 
@@ -18,6 +19,30 @@ struct sc_ctx {
     // convergence tests (hipHostMalloc'ed once per context)
     void* stage = nullptr;
     size_t stage_bytes = 0;
+    // kernel timing (HIP events on `stream` around launches of the kinds in prof_mask)
+    unsigned prof_mask = 0;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    int64_t prof_count[SC_KIND_COUNT] = {};
+    double prof_ms[SC_KIND_COUNT] = {};
+};
+
+// Accumulate the durations of completed timed launches (the caller has
+// synchronised the stream, or calls with sync = true).
+void prof_drain(sc_ctx* ctx, bool sync);
+
+// Times everything enqueued on ctx->stream during its lifetime when the kind
+// is enabled.
+struct ProfScope {
+    sc_ctx* ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(sc_ctx* c, int k);
+    ~ProfScope();
 };
 
 sc_status sc_fail(sc_ctx* ctx, sc_status st, const char* fmt, ...);

@@ -104,6 +104,7 @@ extern "C" sc_status sc_spmm(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t*
         return sc_fail(ctx, SC_E_INVAL, "spmm: null pointer argument");
     if (X == Y) return sc_fail(ctx, SC_E_INVAL, "spmm: X and Y must not alias");
     SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    ProfScope ps(ctx, SC_KIND_SPMM);
     if (fp64)
         return launch_spmm<double>(ctx, n, row_ptr, col, static_cast<const double*>(val), k,
                                    static_cast<const double*>(X), ldx, static_cast<double*>(Y),
