@@ -208,72 +208,92 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
 }
 
 // ---------------------------------------------------------------------------
-// In-place V <- V T for an n x c row block (T upper triangular, c x c).
+// Row-block products with a small matrix, in place.  For every row of V:
+//   acc1[j] = sum_{l in [a0,a1)} V[row][l] M[l][j]
+//   acc2[j] = sum_{l in [b0,b1)} V[row][l] M[l][j]       (empty range: 0)
+//   V[row][o1 + j] = acc1 + acc2,   V[row][o2 + j] = acc2 (when o2 >= 0)
+// for j < nout.  A workgroup owns BM whole rows, so every read of a row
+// precedes every write to it.  K is staged through LDS in chunks of 32; each
+// thread keeps RPT rows x NC columns of accumulators (columns tx + 16 c).
+// This serves the block update (P <- [W P] C_WP, X <- X C_X + P) and the
+// right multiplication by the Cholesky-QR factor (V <- V T).
 // ---------------------------------------------------------------------------
 template <class T>
 struct Prec;
 template <>
 struct Prec<double> {
-    static __device__ inline double coef(const double* c64, const float*, int64_t i) { return c64[i]; }
+    static __host__ __device__ inline const double* pick(const double* c64, const float*) { return c64; }
 };
 template <>
 struct Prec<float> {
-    static __device__ inline float coef(const double*, const float* c32, int64_t i) { return c32[i]; }
+    static __host__ __device__ inline const float* pick(const double*, const float* c32) { return c32; }
 };
 
-template <class T>
-__global__ void __launch_bounds__(256)
-k_apply_right(int64_t n, int c, int ROWS, T* __restrict__ V, int64_t ldv, T* __restrict__ V2,
-              int64_t ldv2, const double* __restrict__ T64, const float* __restrict__ T32) {
-    extern __shared__ unsigned char smem_raw[];
-    T* Vs = reinterpret_cast<T*>(smem_raw);
-    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
-    const int rows = (int)min<int64_t>(ROWS, n - r0);
-    for (int pass = 0; pass < (V2 ? 2 : 1); ++pass) {
-        T* M = pass ? V2 : V;
-        const int64_t ld = pass ? ldv2 : ldv;
-        for (int e = threadIdx.x; e < rows * c; e += 256) {
-            const int r = e / c, j = e % c;
-            Vs[e] = M[(r0 + r) * ld + j];
+constexpr int RG_BK = 32;
+
+template <class T, int RPT, int NC>
+__device__ inline void rowgemm_section(const T* __restrict__ V, int64_t ld, int64_t r0, int64_t n,
+                                       int lo, int hi, const T* __restrict__ M, int ldm, int nout,
+                                       T (*Vs)[16 * RPT + 1], T (*Ms)[16 * NC], T (&acc)[RPT][NC]) {
+    constexpr int BM = 16 * RPT;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int l0 = lo; l0 < hi; l0 += RG_BK) {
+        const int kc = min(RG_BK, hi - l0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < BM * RG_BK; e += 256) {
+            const int row = e / RG_BK, kk = e % RG_BK;
+            Vs[kk][row] = (r0 + row < n && kk < kc) ? V[(r0 + row) * ld + l0 + kk] : T(0);
+        }
+        for (int e = threadIdx.x; e < RG_BK * 16 * NC; e += 256) {
+            const int kk = e / (16 * NC), j = e % (16 * NC);
+            Ms[kk][j] = (kk < kc && j < nout) ? M[(int64_t)(l0 + kk) * ldm + j] : T(0);
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < rows * c; e += 256) {
-            const int r = e / c, j = e % c;
-            T acc = T(0);
-            for (int a = 0; a <= j; ++a)
-                acc = fma(Vs[r * c + a], Prec<T>::coef(T64, T32, (int64_t)a * c + j), acc);
-            M[(r0 + r) * ld + j] = acc;
+        for (int kk = 0; kk < kc; ++kk) {
+            T v[RPT], m[NC];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) v[r] = Vs[kk][ty * RPT + r];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) m[c] = Ms[kk][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[r][c] = fma(v[r], m[c], acc[r][c]);
         }
-        __syncthreads();
     }
 }
 
-// ---------------------------------------------------------------------------
-// Block update on S = [X W P] (row stride ld, blocks of kp columns):
-//   P <- [W P] C_WP,  X <- X C_X + P.   Row-local, so it runs in place.
-// ---------------------------------------------------------------------------
-template <class T>
+template <class T, int RPT, int NC>
 __global__ void __launch_bounds__(256)
-k_block_update(int64_t n, int kp, int ROWS, T* __restrict__ S, int64_t ld,
-               const double* __restrict__ C64, const float* __restrict__ C32) {
-    extern __shared__ unsigned char smem_raw[];
-    T* Ss = reinterpret_cast<T*>(smem_raw);
-    const int K3 = 3 * kp;
-    const int64_t r0 = (int64_t)blockIdx.x * ROWS;
-    const int rows = (int)min<int64_t>(ROWS, n - r0);
-    for (int e = threadIdx.x; e < rows * K3; e += 256) {
-        const int r = e / K3, j = e % K3;
-        Ss[e] = S[(r0 + r) * ld + j];
-    }
+k_rowgemm(int64_t n, T* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
+          const T* __restrict__ M, int ldm, int nout, int o1, int o2) {
+    constexpr int BM = 16 * RPT;
+    __shared__ T Vs[RG_BK][BM + 1];
+    __shared__ T Ms[RG_BK][16 * NC];
+    const int64_t r0 = (int64_t)blockIdx.x * BM;
+    T acc1[RPT][NC], acc2[RPT][NC];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            acc1[r][c] = T(0);
+            acc2[r][c] = T(0);
+        }
+    rowgemm_section<T, RPT, NC>(V, ld, r0, n, a0, a1, M, ldm, nout, Vs, Ms, acc1);
+    rowgemm_section<T, RPT, NC>(V, ld, r0, n, b0, b1, M, ldm, nout, Vs, Ms, acc2);
     __syncthreads();
-    for (int e = threadIdx.x; e < rows * kp; e += 256) {
-        const int r = e / kp, j = e % kp;
-        const T* s = Ss + r * K3;
-        T accP = T(0), accX = T(0);
-        for (int l = kp; l < K3; ++l) accP = fma(s[l], Prec<T>::coef(C64, C32, (int64_t)l * kp + j), accP);
-        for (int l = 0; l < kp; ++l) accX = fma(s[l], Prec<T>::coef(C64, C32, (int64_t)l * kp + j), accX);
-        S[(r0 + r) * ld + j] = accX + accP;
-        S[(r0 + r) * ld + 2 * kp + j] = accP;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int64_t row = r0 + ty * RPT + r;
+        if (row >= n) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int j = tx + 16 * c;
+            if (j >= nout) continue;
+            V[row * ld + o1 + j] = acc1[r][c] + acc2[r][c];
+            if (o2 >= 0) V[row * ld + o2 + j] = acc2[r][c];
+        }
     }
 }
 
@@ -412,14 +432,43 @@ sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, d
     return SC_OK;
 }
 
+template <class T, int NC>
+static void rowgemm_go(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
+                       const T* M, int ldm, int nout, int o1, int o2) {
+    constexpr int RPT = sizeof(T) == 8 ? 2 : 4;
+    constexpr int BM = 16 * RPT;
+    hipLaunchKernelGGL((k_rowgemm<T, RPT, NC>), dim3((unsigned)ceil_div(n, BM)), dim3(256), 0,
+                       ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+}
+
+template <class T>
+static sc_status rowgemm(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
+                         const T* M, int ldm, int nout, int o1, int o2) {
+    const int nc = (nout + 15) / 16;
+    switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
+        case 1: rowgemm_go<T, 1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 2: rowgemm_go<T, 2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 3: rowgemm_go<T, 3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 4: rowgemm_go<T, 4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 6: rowgemm_go<T, 6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 8: rowgemm_go<T, 8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 10: rowgemm_go<T, 10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 12: rowgemm_go<T, 12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        default:
+            if (nout > 256) return sc_fail(ctx, SC_E_UNSUPPORTED, "rowgemm: %d columns > 256", nout);
+            rowgemm_go<T, 16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+            break;
+    }
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
 template <class T>
 sc_status launch_apply_right(sc_ctx* ctx, int64_t n, int c, T* V, int64_t ldv, T* V2, int64_t ldv2,
                              const double* T64, const float* T32) {
-    const int ROWS = (int)std::max<int64_t>(1, std::min<int64_t>(64, 65536 / ((int64_t)c * sizeof(T))));
-    const size_t lds = (size_t)ROWS * c * sizeof(T);
-    hipLaunchKernelGGL((k_apply_right<T>), dim3(ceil_div(n, ROWS)), dim3(256), lds, ctx->stream, n,
-                       c, ROWS, V, ldv, V2, ldv2, T64, T32);
-    SC_CHECK_LAUNCH(ctx);
+    const T* M = Prec<T>::pick(T64, T32);
+    SC_TRY(rowgemm<T>(ctx, n, V, ldv, 0, c, 0, 0, M, c, c, 0, -1));
+    if (V2) SC_TRY(rowgemm<T>(ctx, n, V2, ldv2, 0, c, 0, 0, M, c, c, 0, -1));
     return SC_OK;
 }
 template sc_status launch_apply_right<double>(sc_ctx*, int64_t, int, double*, int64_t, double*,
@@ -430,13 +479,8 @@ template sc_status launch_apply_right<float>(sc_ctx*, int64_t, int, float*, int6
 template <class T>
 sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, T* S, int64_t ld, const double* C64,
                               const float* C32) {
-    const int ROWS =
-        (int)std::max<int64_t>(1, std::min<int64_t>(32, 65536 / (3 * (int64_t)kp * sizeof(T))));
-    const size_t lds = (size_t)ROWS * 3 * kp * sizeof(T);
-    hipLaunchKernelGGL((k_block_update<T>), dim3(ceil_div(n, ROWS)), dim3(256), lds, ctx->stream,
-                       n, kp, ROWS, S, ld, C64, C32);
-    SC_CHECK_LAUNCH(ctx);
-    return SC_OK;
+    const T* M = Prec<T>::pick(C64, C32);
+    return rowgemm<T>(ctx, n, S, ld, 0, kp, kp, 3 * kp, M, kp, kp, 0, 2 * kp);
 }
 template sc_status launch_block_update<double>(sc_ctx*, int64_t, int, double*, int64_t,
                                                const double*, const float*);

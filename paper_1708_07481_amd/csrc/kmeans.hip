@@ -4,12 +4,18 @@
 //
 // Exactness rules, so that labels do not depend on the launch shape:
 //   - a squared distance is accumulated with fma in dimension order by one
-//     thread;
+//     lane (the same chain for every point/centroid pair, wherever computed);
 //   - k-means++ draws use integer weights floor(D2 * 2^s) and an exact
 //     integer prefix sum;
 //   - a centroid is the sum of its members in ascending vertex order (a
 //     stable radix sort by label gives the member lists), divided by the count;
 //   - the restart with the least integer inertia wins (ties: lowest restart).
+// Lloyd iterations skip points whose assignment provably cannot change
+// (Hamerly's bounds: an upper bound on the distance to the assigned centre
+// and a lower bound on the distance to every other centre, both moved by the
+// centre displacements).  The bounds are inflated by a relative margin far
+// above the rounding error of the distance chain, so a skipped point's
+// computed argmin is exactly the one a full scan would give.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -19,8 +25,11 @@
 namespace {
 
 constexpr int TH = 256;
+constexpr double BOUND_MARGIN = 1e-12;   // relative inflation of every bound
+constexpr double BOUND_TINY = 1e-150;    // absolute slack for zero distances
 
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 template <class TX>
 __global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx,
@@ -48,16 +57,6 @@ __global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t 
     }
     // non-negative doubles order like their bit patterns
     atomicMax(m2bits, (unsigned long long)__double_as_longlong(s2));
-}
-
-__device__ inline double sqdist_t(int dim, int64_t n, const double* __restrict__ Yt, int64_t i,
-                                  const double* __restrict__ c) {
-    double acc = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        const double diff = Yt[(int64_t)d * n + i] - c[d];
-        acc = fma(diff, diff, acc);
-    }
-    return acc;
 }
 
 // centre j of every restart r from a chosen row (grid: R blocks)
@@ -92,117 +91,338 @@ __global__ void k_seed_pick(int64_t n, int dim, int K, int j, const double* __re
     for (int d = threadIdx.x; d < dim; d += blockDim.x) c[d] = Y[pick * dim + d];
 }
 
-// D2 <- dist(y_i, c_j) (j == 0) or min(D2, dist(y_i, c_j)); then integer weights
-__global__ void k_seed_d2(int64_t n, int dim, int K, int j, int R, const double* __restrict__ Yt,
-                          const double* __restrict__ C, double* __restrict__ D2,
-                          uint64_t* __restrict__ wq, int shift) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    const int r = (int)(e / n);
-    const int64_t i = e % n;
-    const double dd = sqdist_t(dim, n, Yt, i, C + ((int64_t)r * K + j) * dim);
-    double v = D2[e];
-    if (j == 0 || dd < v) v = dd;
-    D2[e] = v;
-    wq[e] = (uint64_t)floor(ldexp(v, shift));
-}
-
-// nearest centroid (ties to the lowest index) for every (restart, point)
-__global__ void k_assign(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
-                         const double* __restrict__ C, const int* __restrict__ active,
-                         const int32_t* __restrict__ old_lab, int32_t* __restrict__ lab,
-                         double* __restrict__ D2, int* __restrict__ changed, int count_changes) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    const int r = (int)(e / n);
-    if (!active[r]) return;
-    const int64_t i = e % n;
-    const double* Cr = C + (int64_t)r * K * dim;
-    double best = 0.0;
-    int bj = 0;
-    constexpr int JB = 8;
-    for (int j0 = 0; j0 < K; j0 += JB) {
-        double acc[JB];
+// For every point and every restart: D2 <- dist(y_i, c_j) (j == 0) or
+// min(D2, dist(y_i, c_j)); then the integer weights.  One pass over Y serves
+// up to RB restarts.
+constexpr int RB = 8;
+__global__ void __launch_bounds__(TH)
+k_seed_d2(int64_t n, int dim, int K, int j, int R, const double* __restrict__ Yt,
+          const double* __restrict__ C, double* __restrict__ D2, uint64_t* __restrict__ wq,
+          int shift) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int r0 = 0; r0 < R; r0 += RB) {
+        double acc[RB];
 #pragma unroll
-        for (int u = 0; u < JB; ++u) acc[u] = 0.0;
+        for (int q = 0; q < RB; ++q) acc[q] = 0.0;
         for (int d = 0; d < dim; ++d) {
             const double y = Yt[(int64_t)d * n + i];
 #pragma unroll
-            for (int u = 0; u < JB; ++u) {
-                if (j0 + u < K) {
-                    const double diff = y - Cr[(int64_t)(j0 + u) * dim + d];
-                    acc[u] = fma(diff, diff, acc[u]);
+            for (int q = 0; q < RB; ++q) {
+                if (r0 + q < R) {
+                    const double diff = y - C[((int64_t)(r0 + q) * K + j) * dim + d];
+                    acc[q] = fma(diff, diff, acc[q]);
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < JB; ++u) {
-            const int j = j0 + u;
-            if (j < K && (j == 0 || acc[u] < best)) {
-                best = acc[u];
-                bj = j;
+        for (int q = 0; q < RB; ++q) {
+            if (r0 + q < R) {
+                const int64_t e = (int64_t)(r0 + q) * n + i;
+                double v = D2[e];
+                if (j == 0 || acc[q] < v) v = acc[q];
+                D2[e] = v;
+                wq[e] = (uint64_t)floor(ldexp(v, shift));
             }
         }
     }
-    lab[e] = bj;
-    D2[e] = best;
-    if (count_changes && old_lab[e] != bj) atomicAdd(&changed[r], 1);
 }
 
-__global__ void k_label_keys(int64_t n, int K, int R, const int32_t* __restrict__ lab,
-                             const int* __restrict__ active, uint64_t* __restrict__ keys,
-                             uint32_t* __restrict__ vals, int* __restrict__ counts) {
+// Ct[r][d][j] = C[r][j][d] for j < K; columns K <= j < Kpad hold +inf, a
+// centre no point is ever nearest (or second nearest) to
+__global__ void k_transpose_centroids(int R, int K, int Kpad, int dim, const double* __restrict__ C,
+                                      double* __restrict__ Ct) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    const int r = (int)(e / n);
-    const int64_t key = (int64_t)r * K + lab[e];
-    keys[e] = (uint64_t)key;
-    vals[e] = (uint32_t)(e % n);
-    (void)active;
-    atomicAdd(&counts[key], 1);   // every restart: offsets index the whole sorted list
+    if (e >= (int64_t)R * Kpad * dim) return;
+    const int j = (int)(e % Kpad);
+    const int64_t rd = e / Kpad;
+    const int d = (int)(rd % dim);
+    const int r = (int)(rd / dim);
+    Ct[e] = j < K ? C[((int64_t)r * K + j) * dim + d] : INFINITY;
 }
 
-__global__ void k_counts_scan(int total, const int* __restrict__ counts, int64_t* __restrict__ off) {
-    // one thread: total = R*K is small
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int64_t s = 0;
-        for (int q = 0; q < total; ++q) {
-            off[q] = s;
-            s += counts[q];
+__global__ void k_fill_lists(int64_t n, int R, uint32_t* __restrict__ pts, int* __restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n * R) pts[e] = (uint32_t)(e % n);
+    if (e < R) cnt[e] = (int)n;
+}
+
+// Nearest and second-nearest centre for the listed points of restart r
+// (blockIdx.y).  64 points per workgroup; their coordinates are staged in
+// LDS in chunks of 32 dimensions; each of the four waves scans its own range
+// of JB centres per pass, with the centre coordinates read as wave-uniform
+// (scalar) loads from the transposed centroid table.  Every distance is the
+// full fma chain over the dimensions in order.
+template <int JB>
+__global__ void __launch_bounds__(TH)
+k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
+              const double* __restrict__ Ct, const uint32_t* __restrict__ pts,
+              const int* __restrict__ cnt, const int* __restrict__ active,
+              int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
+              int* __restrict__ changed, int first) {
+    constexpr int DC = 32;
+    __shared__ double ys[DC][65];   // padded row: fewer LDS bank conflicts on the transposing store
+    __shared__ uint32_t pid[64];
+    __shared__ double wbest[4][64], wsec[4][64];
+    __shared__ int wj[4][64];
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int c = cnt[r];
+    const int q0 = blockIdx.x * 64;
+    if (q0 >= c) return;
+    const int np = min(64, c - q0);
+    const int lane = threadIdx.x & 63;
+    const int wave = uniform(threadIdx.x >> 6);
+    if (threadIdx.x < 64) pid[threadIdx.x] = pts[(int64_t)r * n + q0 + min((int)threadIdx.x, np - 1)];
+    double best = INFINITY, second = INFINITY;
+    int bj = K;
+    const int passes = Kpad / (4 * JB);
+    const double* Ctr = Ct + (int64_t)r * dim * Kpad;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int cb = uniform(pass * 4 * JB + wave * JB);
+        double acc[JB];
+#pragma unroll
+        for (int u = 0; u < JB; ++u) acc[u] = 0.0;
+        for (int d0 = 0; d0 < dim; d0 += DC) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < 64 * DC; q += TH) {
+                const int p = q / DC, dd = q % DC;
+                ys[dd][p] = d0 + dd < dim ? Y[(int64_t)pid[p] * dim + d0 + dd] : 0.0;
+            }
+            __syncthreads();
+            if (cb < K) {
+                const int nd = min(DC, dim - d0);
+                for (int dd = 0; dd < nd; ++dd) {
+                    const double y = ys[dd][lane];
+                    const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad + cb;
+                    constexpr int G = JB < 8 ? JB : 8;
+#pragma unroll
+                    for (int u0 = 0; u0 < JB; u0 += G) {
+                        double cv[G];
+#pragma unroll
+                        for (int q = 0; q < G; ++q) cv[q] = crow[u0 + q];
+#pragma unroll
+                        for (int q = 0; q < G; ++q) {
+                            const double diff = y - cv[q];
+                            acc[u0 + q] = fma(diff, diff, acc[u0 + q]);
+                        }
+                    }
+                }
+            }
         }
-        off[total] = s;
+        if (cb < K) {
+#pragma unroll
+            for (int u = 0; u < JB; ++u) {
+                if (cb + u < K) {
+                    const double v = acc[u];
+                    if (v < best) {
+                        second = best;
+                        best = v;
+                        bj = cb + u;
+                    } else if (v < second) {
+                        second = v;
+                    }
+                }
+            }
+        }
+    }
+    wbest[wave][lane] = best;
+    wsec[wave][lane] = second;
+    wj[wave][lane] = bj;
+    __syncthreads();
+    if (threadIdx.x < 64 && lane < np) {
+        double b = INFINITY, s = INFINITY;
+        int j = K;
+        for (int w = 0; w < 4; ++w) {
+            const double v = wbest[w][lane], sv = wsec[w][lane];
+            const int jw = wj[w][lane];
+            if (jw >= K) continue;
+            if (v < b || (v == b && jw < j)) {
+                s = fmin(fmin(s, b), sv);
+                b = v;
+                j = jw;
+            } else {
+                s = fmin(s, v);
+            }
+        }
+        const int64_t e = (int64_t)r * n + pid[lane];
+        if (!first && lab[e] != j) atomicAdd(&changed[r], 1);
+        lab[e] = j;
+        ub[e] = sqrt(b) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+        lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
     }
 }
 
+// centre displacements: delta[r][j] = ||c_new - c_old|| (inflated), and per
+// restart the largest (with its index) and second largest displacement
+__global__ void __launch_bounds__(TH)
+k_delta(int K, int dim, const double* __restrict__ C, const double* __restrict__ Cold,
+        const int* __restrict__ active, double* __restrict__ delta, double* __restrict__ dinfo) {
+    const int r = blockIdx.x;
+    if (!active[r]) return;
+    __shared__ double smax[TH], ssec[TH];
+    __shared__ int sarg[TH];
+    double m1 = 0.0, m2 = 0.0;
+    int a1 = -1;
+    for (int j = threadIdx.x; j < K; j += TH) {
+        const double* cn = C + ((int64_t)r * K + j) * dim;
+        const double* co = Cold + ((int64_t)r * K + j) * dim;
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            const double t = cn[d] - co[d];
+            s = fma(t, t, s);
+        }
+        const double dj = sqrt(s) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+        delta[(int64_t)r * K + j] = dj;
+        if (dj > m1) {
+            m2 = m1;
+            m1 = dj;
+            a1 = j;
+        } else if (dj > m2) {
+            m2 = dj;
+        }
+    }
+    smax[threadIdx.x] = m1;
+    ssec[threadIdx.x] = m2;
+    sarg[threadIdx.x] = a1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b1 = 0.0, b2 = 0.0;
+        int arg = -1;
+        for (int t = 0; t < TH; ++t) {
+            if (smax[t] > b1) {
+                b2 = fmax(b1, ssec[t]);
+                b1 = smax[t];
+                arg = sarg[t];
+            } else {
+                b2 = fmax(b2, smax[t]);
+            }
+        }
+        dinfo[3 * r + 0] = b1;
+        dinfo[3 * r + 1] = (double)arg;
+        dinfo[3 * r + 2] = b2;
+    }
+}
+
+// move the bounds by the displacements; list the points that need a scan
+// (grid: x over points, y over restarts; one list append per wave)
+__global__ void k_bounds(int64_t n, int K, const int32_t* __restrict__ lab,
+                         double* __restrict__ ub, double* __restrict__ lb,
+                         const double* __restrict__ delta, const double* __restrict__ dinfo,
+                         const int* __restrict__ active, uint32_t* __restrict__ pts,
+                         int* __restrict__ cnt) {
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool need = false;
+    if (i < n) {
+        const int64_t e = (int64_t)r * n + i;
+        const int a = lab[e];
+        const double dmax = ((int)dinfo[3 * r + 1] == a) ? dinfo[3 * r + 2] : dinfo[3 * r + 0];
+        const double u = (ub[e] + delta[(int64_t)r * K + a]) * (1.0 + BOUND_MARGIN);
+        const double l = (lb[e] - dmax) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+        ub[e] = u;
+        lb[e] = l;
+        need = !(u < l);
+    }
+    const unsigned long long mask = __ballot(need);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cnt[r], __popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (need) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        pts[(int64_t)r * n + base + rank] = (uint32_t)i;
+    }
+}
+
+__global__ void k_label_keys(int64_t n, int K, int R, const int32_t* __restrict__ lab,
+                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * R) return;
+    const int r = (int)(e / n);
+    keys[e] = (uint64_t)((int64_t)r * K + lab[e]);
+    vals[e] = (uint32_t)(e % n);
+}
+
+// segment [start, end) of every key in the sorted list (empty keys: 0, 0)
+__global__ void k_segments(int64_t len, const uint64_t* __restrict__ keys, int64_t* __restrict__ seg) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= len) return;
+    const uint64_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) seg[2 * k] = p;
+    if (p + 1 == len || keys[p + 1] != k) seg[2 * k + 1] = p + 1;
+}
+
 // centroid (r, j), dimension d: members in ascending vertex order
-__global__ void k_centroids(int dim, int K, int R, const double* __restrict__ Y,
-                            const uint32_t* __restrict__ members, const int* __restrict__ counts,
-                            const int64_t* __restrict__ off, const int* __restrict__ active,
-                            int64_t n, double* __restrict__ C) {
+__global__ void __launch_bounds__(TH)
+k_centroids(int dim, int K, int R, const double* __restrict__ Y,
+            const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
+            const int* __restrict__ active, double* __restrict__ C) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)R * K * dim) return;
     const int d = (int)(e % dim);
     const int64_t rj = e / dim;
     const int r = (int)(rj / K);
     if (!active[r]) return;
-    const int cnt = counts[rj];
-    if (cnt == 0) return;
-    // the sorted list holds all restarts back to back
-    const uint32_t* mem = members + off[rj];
+    const int64_t lo = seg[2 * rj], hi = seg[2 * rj + 1];
+    const int64_t cnt = hi - lo;
+    if (cnt <= 0) return;
+    const uint32_t* mem = members + lo;
     double s = 0.0;
-    for (int p = 0; p < cnt; ++p) s += Y[(int64_t)mem[p] * dim + d];
+    int64_t p = 0;
+    constexpr int U = 8;
+    for (; p + U <= cnt; p += U) {
+        uint32_t id[U];
+        double v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) id[q] = mem[p + q];
+#pragma unroll
+        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * dim + d];
+#pragma unroll
+        for (int q = 0; q < U; ++q) s += v[q];
+    }
+    for (; p < cnt; ++p) s += Y[(int64_t)mem[p] * dim + d];
     C[e] = s / (double)cnt;
 }
 
-__global__ void k_inertia(int64_t n, int R, const double* __restrict__ D2, int shift,
-                          unsigned long long* __restrict__ q) {
+// exact squared distance of every point to its assigned centre
+__global__ void k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
+                           const double* __restrict__ C, const int32_t* __restrict__ lab,
+                           double* __restrict__ D2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * R) return;
     const int r = (int)(e / n);
-    atomicAdd(&q[r], (unsigned long long)floor(ldexp(D2[e], shift)));
+    const int64_t i = e % n;
+    const double* c = C + ((int64_t)r * K + lab[e]) * dim;
+    double acc = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        const double diff = Yt[(int64_t)d * n + i] - c[d];
+        acc = fma(diff, diff, acc);
+    }
+    D2[e] = acc;
 }
 
-// FP64 inertia of restart r: fixed-shape tree (block sums in order)
+// integer inertia per restart: block sums (exact) then one atomic per block
+__global__ void __launch_bounds__(TH)
+k_inertia(int64_t n, const double* __restrict__ D2, int shift, unsigned long long* __restrict__ q) {
+    __shared__ unsigned long long sm[TH];
+    const int r = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * TH + threadIdx.x;
+    unsigned long long v = 0;
+    if (i < n) v = (unsigned long long)floor(ldexp(D2[(int64_t)r * n + i], shift));
+    sm[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = TH / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&q[r], sm[0]);
+}
+
+// FP64 inertia of one restart: fixed-shape tree (block sums in order)
 __global__ void k_sum_rows(int64_t n, const double* __restrict__ D2, double* __restrict__ part) {
     __shared__ double sm[TH];
     const int64_t base = (int64_t)blockIdx.x * TH * 16;
@@ -228,27 +448,53 @@ __global__ void k_sum_final(int nb, const double* __restrict__ part, double* out
     }
 }
 
-__global__ void k_zero_i32(int* p, int64_t n) {
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
+__global__ void k_zero_i32(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// centres per wave and pass: the smallest supported width covering K in one
+// pass (four waves), else 64 with several passes; Kpad = passes * 4 * JB
+int assign_width(int K) {
+    const int need = (K + 3) / 4;
+    const int widths[] = {2, 8, 16, 24, 32, 40, 48, 56, 64};
+    for (int wdt : widths)
+        if (wdt >= need) return wdt;
+    return 64;
+}
+int assign_kpad(int K) {
+    const int jb = assign_width(K);
+    return (int)ceil_div(K, 4 * jb) * 4 * jb;
+}
+
 struct KmWs {
-    double *Y, *Yt, *D2, *C, *part, *inertia;
+    double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
     uint64_t *wq, *scan_tmp, *keys, *keys_alt, *radix_tmp;
-    uint32_t *vals, *vals_alt;
-    int32_t *lab, *lab2;
-    int *changed, *active, *counts, *status;
-    int64_t* off;
+    uint32_t *vals, *vals_alt, *pts;
+    int32_t* lab;
+    int *changed, *active, *cnt, *status;
+    int64_t* seg;
     unsigned long long *m2, *q;
 };
 
 size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     const int64_t nr = n * R;
+    const size_t cent = (size_t)R * K * dim;
     w.Y = c.take<double>((size_t)n * dim);
     w.Yt = c.take<double>((size_t)n * dim);
     w.D2 = c.take<double>(nr);
-    w.C = c.take<double>((size_t)R * K * dim);
+    w.C = c.take<double>(cent);
+    w.Cold = c.take<double>(cent);
+    w.Ct = c.take<double>((size_t)R * assign_kpad(K) * dim);
+    w.ub = c.take<double>(nr);
+    w.lb = c.take<double>(nr);
+    w.delta = c.take<double>((size_t)R * K);
+    w.dinfo = c.take<double>(3 * (size_t)R);
     w.part = c.take<double>(ceil_div(n, TH * 16) + 1);
     w.inertia = c.take<double>(1);
     w.wq = c.take<uint64_t>(nr);
@@ -257,14 +503,14 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.keys_alt = c.take<uint64_t>(nr);
     w.vals = c.take<uint32_t>(nr);
     w.vals_alt = c.take<uint32_t>(nr);
+    w.pts = c.take<uint32_t>(nr);
     w.radix_tmp = c.take<uint64_t>(radix_tmp_elems(nr));
     w.lab = c.take<int32_t>(nr);
-    w.lab2 = c.take<int32_t>(nr);
     w.changed = c.take<int>(R);
     w.active = c.take<int>(R);
-    w.counts = c.take<int>((size_t)R * K);
+    w.cnt = c.take<int>(R);
     w.status = c.take<int>(1);
-    w.off = c.take<int64_t>((size_t)R * K + 1);
+    w.seg = c.take<int64_t>(2 * (size_t)R * K);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
     return c.size();
@@ -273,12 +519,35 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
 sc_status km_validate(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* o) {
     if (!o) return sc_fail(ctx, SC_E_INVAL, "kmeans: opts is NULL");
     if (n <= 0 || dim <= 0) return sc_fail(ctx, SC_E_INVAL, "kmeans: need n > 0 and dim > 0");
-    if (n >= (int64_t(1) << 32)) return sc_fail(ctx, SC_E_UNSUPPORTED, "kmeans: n >= 2^32");
     if (o->n_clusters < 1 || o->n_clusters > n || o->n_clusters > 1024)
         return sc_fail(ctx, SC_E_INVAL, "kmeans: need 1 <= K <= min(n, 1024)");
     if (o->restarts < 1 || o->max_iter < 0)
         return sc_fail(ctx, SC_E_INVAL, "kmeans: need restarts >= 1 and max_iter >= 0");
+    if ((int64_t)o->restarts * n >= (int64_t(1) << 31))
+        return sc_fail(ctx, SC_E_UNSUPPORTED, "kmeans: restarts * n >= 2^31");
     return SC_OK;
+}
+
+template <int JB>
+void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
+    dim3 grid((unsigned)ceil_div(n, 64), (unsigned)R);
+    hipLaunchKernelGGL((k_assign_list<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                       assign_kpad(K), w.Y, w.Ct, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
+                       w.changed, first);
+}
+
+void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
+    switch (assign_width(K)) {
+        case 2: launch_assign<2>(ctx, n, dim, K, R, w, first); break;
+        case 8: launch_assign<8>(ctx, n, dim, K, R, w, first); break;
+        case 16: launch_assign<16>(ctx, n, dim, K, R, w, first); break;
+        case 24: launch_assign<24>(ctx, n, dim, K, R, w, first); break;
+        case 32: launch_assign<32>(ctx, n, dim, K, R, w, first); break;
+        case 40: launch_assign<40>(ctx, n, dim, K, R, w, first); break;
+        case 48: launch_assign<48>(ctx, n, dim, K, R, w, first); break;
+        case 56: launch_assign<56>(ctx, n, dim, K, R, w, first); break;
+        default: launch_assign<64>(ctx, n, dim, K, R, w, first); break;
+    }
 }
 
 }  // namespace
@@ -314,11 +583,12 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     const int64_t nr = n * R;
-    const dim3 gnr(ceil_div(nr, TH));
+    const dim3 gnr((unsigned)ceil_div(nr, TH));
+    const size_t cent_bytes = (size_t)R * K * dim * sizeof(double);
+    ProfScope ps(ctx, SC_KIND_KMEANS);
 
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.m2, 0, sizeof(unsigned long long), st));
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.status, 0, sizeof(int), st));
-    ProfScope ps(ctx, SC_KIND_KMEANS);
     if (opts->x_fp32)
         hipLaunchKernelGGL((k_rownorm<float>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
                            static_cast<const float*>(X), ldx, opts->normalize_rows, w.Y, w.Yt, w.m2,
@@ -342,68 +612,78 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (m2 == 0.0) e = 0;
     const int shift = 61 - ceil_log2_u64((uint64_t)n) - e;
 
-    // all restarts active
     std::vector<int> act_h(R, 1);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(w.active, act_h.data(), R * sizeof(int), hipMemcpyHostToDevice, st));
+    // seeding
     if (init_centroids) {
-        SC_CHECK_HIP(ctx, hipMemcpyAsync(w.C, init_centroids, (size_t)K * dim * sizeof(double),
-                                         hipMemcpyDeviceToDevice, st));
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(w.C, init_centroids, cent_bytes, hipMemcpyDeviceToDevice, st));
     } else {
         for (int j = 0; j < K; ++j) {
             hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Y, draws,
                                w.wq, w.C);
             SC_CHECK_LAUNCH(ctx);
             if (j + 1 < K) {
-                hipLaunchKernelGGL(k_seed_d2, gnr, dim3(TH), 0, st, n, dim, K, j, R, w.Yt, w.C, w.D2,
-                                   w.wq, shift);
+                hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, j, R,
+                                   w.Yt, w.C, w.D2, w.wq, shift);
                 SC_CHECK_LAUNCH(ctx);
                 SC_TRY(scan_u64_batched(ctx, w.wq, w.wq, n, R, w.scan_tmp));
             }
         }
     }
-    // Lloyd
-    hipLaunchKernelGGL(k_assign, gnr, dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C, w.active, w.lab,
-                       w.lab, w.D2, w.changed, 0);
+    const dim3 gcent((unsigned)ceil_div((int64_t)R * K * dim, TH));
+    const int Kpad = assign_kpad(K);
+    const dim3 gcentp((unsigned)ceil_div((int64_t)R * Kpad * dim, TH));
+    // first assignment: every point of every restart
+    hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C, w.Ct);
+    hipLaunchKernelGGL(k_fill_lists, gnr, dim3(TH), 0, st, n, R, w.pts, w.cnt);
+    SC_CHECK_LAUNCH(ctx);
+    assign(ctx, n, dim, K, R, w, 1);
     SC_CHECK_LAUNCH(ctx);
     const int bits = ceil_log2_u64((uint64_t)R * K);
-    int32_t* cur = w.lab;
-    int32_t* nxt = w.lab2;
     int n_active = R;
+    std::vector<int> ch(R);
     for (int it = 1; it <= opts->max_iter && n_active > 0; ++it) {
-        hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.counts,
-                           (int64_t)R * K);
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(TH), 0, st, w.changed, (int64_t)R);
-        hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, K, R, cur, w.active, w.keys,
-                           w.vals, w.counts);
+        // centroid update from the stable member lists
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(w.Cold, w.C, cent_bytes, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, K, R, w.lab, w.keys, w.vals);
         SC_CHECK_LAUNCH(ctx);
         SC_TRY(radix_sort_pairs(ctx, w.keys, w.vals, w.keys_alt, w.vals_alt, nr, bits, w.radix_tmp));
-        hipLaunchKernelGGL(k_counts_scan, dim3(1), dim3(64), 0, st, R * K, w.counts, w.off);
-        hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)R * K * dim, TH)), dim3(TH), 0, st,
-                           dim, K, R, w.Y, w.vals, w.counts, w.off, w.active, n, w.C);
-        hipLaunchKernelGGL(k_assign, gnr, dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C, w.active, cur,
-                           nxt, w.D2, w.changed, 1);
+        hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div(2 * (int64_t)R * K, TH)), dim3(TH), 0, st, w.seg,
+                           2 * (int64_t)R * K);
+        hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, nr, w.keys, w.seg);
+        hipLaunchKernelGGL(k_centroids, gcent, dim3(TH), 0, st, dim, K, R, w.Y, w.vals, w.seg,
+                           w.active, w.C);
+        hipLaunchKernelGGL(k_delta, dim3(R), dim3(TH), 0, st, K, dim, w.C, w.Cold, w.active, w.delta,
+                           w.dinfo);
+        hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C,
+                           w.Ct);
         SC_CHECK_LAUNCH(ctx);
-        // inactive restarts keep their labels in `cur`; carry them into `nxt`
-        std::vector<int> ch(R);
+        // points whose assignment may change, then their scans
+        hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.cnt, R);
+        hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.changed, R);
+        hipLaunchKernelGGL(k_bounds, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st,
+                           n, K, w.lab, w.ub, w.lb, w.delta, w.dinfo, w.active, w.pts, w.cnt);
+        SC_CHECK_LAUNCH(ctx);
+        assign(ctx, n, dim, K, R, w, 0);
+        SC_CHECK_LAUNCH(ctx);
         SC_CHECK_HIP(ctx, hipMemcpyAsync(ch.data(), w.changed, R * sizeof(int), hipMemcpyDeviceToHost, st));
         SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
-        for (int r = 0; r < R; ++r) {
-            if (!act_h[r]) {
-                SC_CHECK_HIP(ctx, hipMemcpyAsync(nxt + (int64_t)r * n, cur + (int64_t)r * n,
-                                                 n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-            } else if (ch[r] == 0) {
+        bool any_stop = false;
+        for (int r = 0; r < R; ++r)
+            if (act_h[r] && ch[r] == 0) {
                 act_h[r] = 0;
                 --n_active;
+                any_stop = true;
             }
-        }
-        std::swap(cur, nxt);
-        SC_CHECK_HIP(ctx, hipMemcpyAsync(w.active, act_h.data(), R * sizeof(int),
-                                         hipMemcpyHostToDevice, st));
-        SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
+        if (any_stop)
+            SC_CHECK_HIP(ctx, hipMemcpyAsync(w.active, act_h.data(), R * sizeof(int),
+                                             hipMemcpyHostToDevice, st));
     }
-    // choose the restart
+    // exact distances to the final centres, integer inertia, best restart
+    hipLaunchKernelGGL(k_final_d2, gnr, dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C, w.lab, w.D2);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(k_inertia, gnr, dim3(TH), 0, st, n, R, w.D2, shift, w.q);
+    hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st, n,
+                       w.D2, shift, w.q);
     SC_CHECK_LAUNCH(ctx);
     std::vector<unsigned long long> qh(R);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(qh.data(), w.q, R * sizeof(unsigned long long),
@@ -412,7 +692,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     int best = 0;
     for (int r = 1; r < R; ++r)
         if (qh[r] < qh[best]) best = r;
-    SC_CHECK_HIP(ctx, hipMemcpyAsync(labels, cur + (int64_t)best * n, n * sizeof(int32_t),
+    SC_CHECK_HIP(ctx, hipMemcpyAsync(labels, w.lab + (int64_t)best * n, n * sizeof(int32_t),
                                      hipMemcpyDeviceToDevice, st));
     SC_CHECK_HIP(ctx, hipMemcpyAsync(centroids, w.C + (int64_t)best * K * dim,
                                      (size_t)K * dim * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -322,21 +322,16 @@ __global__ void __launch_bounds__(NT) k_symeig(int m, int k, const double* __res
     eig_lowest(m, k, A, w, V, k, scr + (int64_t)m * m, red, sh);
 }
 
+// --- Rayleigh-Ritz, step 1 (one workgroup): active set, Cholesky of the
+// basis Gram matrix (P dropped and retried once on failure), U^-1, and the
+// reduced G_A gathered to a dense m x m block.  info[0] = m (0 on breakdown).
 __global__ void __launch_bounds__(NT)
-k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const double* __restrict__ GB,
-                int* __restrict__ act, double tol, double* __restrict__ C64, float* __restrict__ C32,
-                double* __restrict__ theta, double* __restrict__ scr, int* status, int* counter) {
-    __shared__ double red[NWAVE + 1];
-    __shared__ double sh[4];
+k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restrict__ GB,
+           int* __restrict__ act, double tol, double* __restrict__ U, double* __restrict__ Ui,
+           double* __restrict__ Am, int* __restrict__ info, int* status, int* counter) {
     __shared__ int idx[MAXM];
-    __shared__ int m_s, fail_s;
+    __shared__ int m_s, fail_s, has_p;
     const int tid = threadIdx.x;
-    double* U = scr;                               // K3 x K3 (m x m used)
-    double* Ui = U + (int64_t)K3 * K3;
-    double* M = Ui + (int64_t)K3 * K3;
-    double* Tm = M + (int64_t)K3 * K3;
-    double* Q = Tm + (int64_t)K3 * K3;             // m x k
-    double* ews = Q + (int64_t)K3 * k;             // eigensolver scratch
     int m = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         if (tid == 0) {
@@ -374,15 +369,16 @@ k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const doub
             __syncthreads();
         }
         if (!fail_s) break;
-        // drop P (columns 2kp..3kp) and retry once
-        __shared__ int has_p;
         if (tid == 0) {
             has_p = 0;
             for (int j = 2 * kp; j < K3; ++j) has_p |= act[j];
         }
         __syncthreads();
         if (!has_p || attempt == 1) {
-            if (tid == 0) atomicOr(status, DEV_BREAKDOWN);
+            if (tid == 0) {
+                atomicOr(status, DEV_BREAKDOWN);
+                info[0] = 0;
+            }
             return;
         }
         for (int j = 2 * kp + tid; j < K3; j += NT) act[j] = 0;
@@ -392,9 +388,9 @@ k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const doub
         }
         __syncthreads();
     }
-    // U^-1 (upper), one column per thread
+    // U^-1 (upper), one column per thread; lower parts zero
     for (int j = tid; j < m; j += NT) {
-        for (int a = 0; a < m; ++a) Ui[(int64_t)a * m + j] = 0.0;
+        for (int a = j + 1; a < m; ++a) Ui[(int64_t)a * m + j] = 0.0;
         Ui[(int64_t)j * m + j] = 1.0 / U[(int64_t)j * m + j];
         for (int a = j - 1; a >= 0; --a) {
             double s = 0.0;
@@ -402,24 +398,74 @@ k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const doub
             Ui[(int64_t)a * m + j] = -s / U[(int64_t)a * m + a];
         }
     }
-    __syncthreads();
-    // Tm = A U^-1, then M = U^-T Tm, symmetrised
     for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
         const int a = (int)(q / m), b = (int)(q % m);
-        const double* arow = GA + (int64_t)idx[a] * K3;
-        double s = 0.0;
-        for (int l = 0; l <= b; ++l) s = fma(arow[idx[l]], Ui[(int64_t)l * m + b], s);
-        Tm[q] = s;
+        Am[q] = GA[(int64_t)idx[a] * K3 + idx[b]];
     }
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
-        const int a = (int)(q / m), b = (int)(q % m);
-        double s = 0.0;
-        for (int l = 0; l <= a; ++l) s = fma(Ui[(int64_t)l * m + a], Tm[(int64_t)l * m + b], s);
-        M[q] = s;
+    if (tid == 0) info[0] = m;
+    for (int j = tid; j < m; j += NT) info[1 + j] = idx[j];
+}
+
+// --- dense FP64 products on many workgroups: C = op(A) B with op(A) = A or
+// A', all row-major m x m (N = m or k columns); m is read from info[0].
+// 64 x 64 output tiles, 4 x 4 per thread, K staged in LDS by 16.
+__global__ void __launch_bounds__(256)
+k_gemm64(const int* __restrict__ info, int n_fixed, int transA, const double* __restrict__ A,
+         const double* __restrict__ B, double* __restrict__ C) {
+    const int m = info[0];
+    const int N = n_fixed > 0 ? n_fixed : m;
+    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+    if (row0 >= m || col0 >= N) return;
+    __shared__ double As[16][65];
+    __shared__ double Bs[16][64];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < m; k0 += 16) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int kk = e / 64, r = e % 64;
+            const int gr = row0 + r, gk = k0 + kk;
+            double v = 0.0;
+            if (gr < m && gk < m) v = transA ? A[(int64_t)gk * m + gr] : A[(int64_t)gr * m + gk];
+            As[kk][r] = v;
+            const int gc = col0 + r;
+            Bs[kk][r] = (gk < m && gc < N) ? B[(int64_t)gk * N + gc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int gr = row0 + ty * 4 + r;
+        if (gr >= m) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int gc = col0 + tx + 16 * c;
+            if (gc < N) C[(int64_t)gr * N + gc] = acc[r][c];
+        }
+    }
+}
+
+// --- step 3 (one workgroup): symmetrise M, k smallest eigenpairs
+__global__ void __launch_bounds__(NT)
+k_rr_eig(int k, const int* __restrict__ info, double* __restrict__ M, double* __restrict__ theta,
+         double* __restrict__ Q, double* __restrict__ ews) {
+    __shared__ double red[NWAVE + 1];
+    __shared__ double sh[4];
+    const int m = info[0];
+    if (m == 0) return;
+    for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += NT) {
         const int a = (int)(q / m), b = (int)(q % m);
         if (a < b) {
             const double s = 0.5 * (M[(int64_t)a * m + b] + M[(int64_t)b * m + a]);
@@ -429,20 +475,31 @@ k_rayleigh_ritz(int K3, int kp, int k, const double* __restrict__ GA, const doub
     }
     __syncthreads();
     eig_lowest(m, k, M, theta, Q, k, ews, red, sh);
-    // C = U^-1 Q scattered to the active rows; zero elsewhere
-    for (int64_t q = tid; q < (int64_t)K3 * kp; q += NT) {
-        C64[q] = 0.0;
-        C32[q] = 0.0f;
+}
+
+// --- step 5: scatter C_act (m x k) to the rows of the active columns (the
+// other rows were zeroed by k_rr_zero)
+__global__ void k_rr_zero(int K3, int kp, int k, double* __restrict__ C64, float* __restrict__ C32,
+                          double* __restrict__ theta) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (int64_t)K3 * kp) {
+        C64[e] = 0.0;
+        C32[e] = 0.0f;
     }
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * k; q += NT) {
-        const int a = (int)(q / k), i = (int)(q % k);
-        double s = 0.0;
-        for (int l = a; l < m; ++l) s = fma(Ui[(int64_t)a * m + l], Q[(int64_t)l * k + i], s);
-        C64[(int64_t)idx[a] * kp + i] = s;
-        C32[(int64_t)idx[a] * kp + i] = (float)s;
-    }
-    for (int i = k + tid; i < kp; i += NT) theta[i] = 0.0;
+    if (e < kp && e >= k) theta[e] = 0.0;
+}
+
+__global__ void k_rr_scatter(int k, int kp, const int* __restrict__ info,
+                             const double* __restrict__ Cq, double* __restrict__ C64,
+                             float* __restrict__ C32) {
+    const int m = info[0];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * k) return;
+    const int a = (int)(e / k), i = (int)(e % k);
+    const int row = info[1 + a];
+    const double v = Cq[(int64_t)a * k + i];
+    C64[(int64_t)row * kp + i] = v;
+    C32[(int64_t)row * kp + i] = (float)v;
 }
 
 }  // namespace
@@ -452,15 +509,36 @@ size_t symeig_scratch_elems(int m, int k) {
 }
 
 size_t rr_scratch_elems(int K3, int k) {
-    return 4 * (size_t)K3 * K3 + (size_t)K3 * k + symeig_scratch_elems(K3, k);
+    // U, Ui, Am, Tm/M (K3^2 each), Q and Cq (K3 x k), info (ints), eigensolver scratch
+    return 4 * (size_t)K3 * K3 + 2 * (size_t)K3 * k + (size_t)K3 + 64 + symeig_scratch_elems(K3, k);
 }
 
 sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
                                const double* GB, int* act, double tol, double* C64, float* C32,
                                double* theta, double* scratch, int* status, int* counter) {
     if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
-    hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(NT), 0, ctx->stream, K3, kp, k, GA, GB, act,
-                       tol, C64, C32, theta, scratch, status, counter);
+    const size_t sq = (size_t)K3 * K3;
+    double* U = scratch;
+    double* Ui = U + sq;
+    double* Am = Ui + sq;
+    double* Tm = Am + sq;                    // A U^-1, then reused for M
+    double* Q = Tm + sq;                     // m x k
+    double* Cq = Q + (size_t)K3 * k;         // m x k
+    int* info = reinterpret_cast<int*>(Cq + (size_t)K3 * k);
+    double* ews = Cq + (size_t)K3 * k + (K3 + 64) / 2 + 32;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_rr_setup, dim3(1), dim3(NT), 0, st, K3, kp, GA, GB, act, tol, U, Ui, Am,
+                       info, status, counter);
+    const dim3 gsq((unsigned)ceil_div(K3, 64), (unsigned)ceil_div(K3, 64));
+    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 0, Am, Ui, Tm);   // Tm = A U^-1
+    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 1, Ui, Tm, U);    // M = U^-T Tm (into U)
+    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(NT), 0, st, k, info, U, theta, Q, ews);
+    const dim3 gk((unsigned)ceil_div(k, 64), (unsigned)ceil_div(K3, 64));
+    hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, info, k, 0, Ui, Q, Cq);    // C = U^-1 Q
+    hipLaunchKernelGGL(k_rr_zero, dim3((unsigned)ceil_div((int64_t)K3 * kp, 256)), dim3(256), 0, st,
+                       K3, kp, k, C64, C32, theta);
+    hipLaunchKernelGGL(k_rr_scatter, dim3((unsigned)ceil_div((int64_t)K3 * k, 256)), dim3(256), 0,
+                       st, k, kp, info, Cq, C64, C32);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }
