@@ -11,18 +11,91 @@
 namespace {
 
 // ---------------------------------------------------------------------------
-// Gram products: G = A^T B over n rows; 64 x 64 output tiles, 256 threads,
-// 4 x 4 outputs per thread, 16 rows staged in LDS per step.
+// Gram products on the matrix cores.  Each of the four waves of a workgroup
+// owns a (16 WT) x (16 WT) block of the output (the workgroup a 2x2 arrangement
+// of them) and accumulates WT x WT MFMA 16x16 tiles for both outputs while
+// walking its row chunk KR rows at a time.  Operand lanes (16x16xK MFMA):
+// lane l supplies column (l % 16) of its 16-wide column strip at rows
+// r0 + KR/4 * (l / 16) + t; the accumulator's element v of lane l is output
+// row 4 (l / 16) + v (FP32, BF16) or (l / 16) + 4 v (FP64), column l % 16.
+//   float : v_mfma_f32_16x16x4_f32   (FP32 in, FP32 accumulate)
+//   double: v_mfma_f64_16x16x4_f64   (FP64 in, FP64 accumulate)
+//   bf16  : v_mfma_f32_16x16x32_bf16 (FP32 in, rounded to BF16 (RNE), FP32 accumulate)
 // ---------------------------------------------------------------------------
-constexpr int GT = 64;      // tile edge
-constexpr int GR = 16;      // rows per LDS stage
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
 
-template <class T, class ACC, bool TWO>
+__device__ inline __bf16 to_bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+}
+
+struct MfF32 {
+    using in_t = float;
+    using acc_t = mf_f4;
+    using frag_t = float;
+    static constexpr int KR = 4;
+    static constexpr int WT = 4;
+    __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static frag_t load(const float* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
+                                  int col, int c, int lane) {
+        const int64_t r = r0 + (lane >> 4);
+        return (r < r1 && col < c) ? M[r * ld + col] : 0.0f;
+    }
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+};
+struct MfF64 {
+    using in_t = double;
+    using acc_t = mf_d4;
+    using frag_t = double;
+    static constexpr int KR = 4;
+    static constexpr int WT = 2;
+    __device__ static int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static frag_t load(const double* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
+                                  int col, int c, int lane) {
+        const int64_t r = r0 + (lane >> 4);
+        return (r < r1 && col < c) ? M[r * ld + col] : 0.0;
+    }
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+};
+struct MfBF16 {
+    using in_t = float;
+    using acc_t = mf_f4;
+    using frag_t = mf_bf8;
+    static constexpr int KR = 32;
+    static constexpr int WT = 4;
+    __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    __device__ static frag_t load(const float* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
+                                  int col, int c, int lane) {
+        frag_t f;
+        const int64_t rb = r0 + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t r = rb + t;
+            f[t] = to_bf16_rne((r < r1 && col < c) ? M[r * ld + col] : 0.0f);
+        }
+        return f;
+    }
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+};
+
+template <class MF, bool TWO>
 __global__ void __launch_bounds__(256)
-k_gram_partial(int64_t n, int c, int64_t chunk_rows, const T* __restrict__ A, int64_t lda,
-               const T* __restrict__ B1, int64_t ldb1, const T* __restrict__ B2, int64_t ldb2,
-               double* __restrict__ partial, int tiles) {
-    // upper tile (ti <= tj) from the linear block index
+k_gram_mfma(int64_t n, int c, int64_t chunk_rows, const typename MF::in_t* __restrict__ A, int64_t lda,
+            const typename MF::in_t* __restrict__ B1, int64_t ldb1,
+            const typename MF::in_t* __restrict__ B2, int64_t ldb2, double* __restrict__ partial,
+            int tiles) {
+    constexpr int WT = MF::WT;
+    constexpr int WTILE = 16 * WT;          // wave tile edge
+    constexpr int BT = 2 * WTILE;           // workgroup tile edge
     int t = blockIdx.x, ti = 0;
     while (t >= tiles - ti) {
         t -= tiles - ti;
@@ -32,64 +105,52 @@ k_gram_partial(int64_t n, int c, int64_t chunk_rows, const T* __restrict__ A, in
     const int chunk = blockIdx.y;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min<int64_t>(n, r0 + chunk_rows);
-    __shared__ T As[GR][GT];
-    __shared__ T Bs1[GR][GT];
-    __shared__ T Bs2[TWO ? GR : 1][GT];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    ACC acc1[4][4], acc2[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ca = ti * BT + (wave >> 1) * WTILE;      // this wave's output rows (columns of A)
+    const int cb = tj * BT + (wave & 1) * WTILE;       // this wave's output cols (columns of B)
+    using acc_t = typename MF::acc_t;
+    acc_t acc1[WT][WT], acc2[WT][WT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int p = 0; p < WT; ++p)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            acc1[r][s] = ACC(0);
-            acc2[r][s] = ACC(0);
+        for (int q = 0; q < WT; ++q) {
+            acc1[p][q] = acc_t{0, 0, 0, 0};
+            acc2[p][q] = acc_t{0, 0, 0, 0};
         }
-    const int ca = ti * GT, cb = tj * GT;
-    for (int64_t row = r0; row < r1; row += GR) {
+    const int lc = lane & 15;
+    for (int64_t row = r0; row < r1; row += MF::KR) {
+        typename MF::frag_t fa[WT], fb1[WT], fb2[WT];
 #pragma unroll
-        for (int q = 0; q < (GR * GT) / 256; ++q) {
-            const int e = q * 256 + threadIdx.x;
-            const int rr = e / GT, cc = e % GT;
-            const int64_t gr = row + rr;
-            const bool in = gr < r1;
-            As[rr][cc] = (in && ca + cc < c) ? A[gr * lda + ca + cc] : T(0);
-            Bs1[rr][cc] = (in && cb + cc < c) ? B1[gr * ldb1 + cb + cc] : T(0);
-            if (TWO) Bs2[rr][cc] = (in && cb + cc < c) ? B2[gr * ldb2 + cb + cc] : T(0);
+        for (int p = 0; p < WT; ++p) fa[p] = MF::load(A, lda, row, r1, ca + 16 * p + lc, c, lane);
+#pragma unroll
+        for (int q = 0; q < WT; ++q) {
+            fb1[q] = MF::load(B1, ldb1, row, r1, cb + 16 * q + lc, c, lane);
+            if (TWO) fb2[q] = MF::load(B2, ldb2, row, r1, cb + 16 * q + lc, c, lane);
         }
-        __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < GR; ++rr) {
-            ACC a[4], b1[4], b2[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = (ACC)As[rr][ty * 4 + r];
+        for (int p = 0; p < WT; ++p)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                b1[s] = (ACC)Bs1[rr][tx * 4 + s];
-                if (TWO) b2[s] = (ACC)Bs2[rr][tx * 4 + s];
+            for (int q = 0; q < WT; ++q) {
+                acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
+                if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
             }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    acc1[r][s] = fma(a[r], b1[s], acc1[r][s]);
-                    if (TWO) acc2[r][s] = fma(a[r], b2[s], acc2[r][s]);
-                }
-        }
-        __syncthreads();
     }
     const int64_t cc2 = (int64_t)c * c;
     double* p1 = partial + (int64_t)chunk * (TWO ? 2 : 1) * cc2;
     double* p2 = p1 + cc2;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int p = 0; p < WT; ++p)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int a = ca + ty * 4 + r, b = cb + tx * 4 + s;
-            if (a < c && b < c) {
-                p1[(int64_t)a * c + b] = (double)acc1[r][s];
-                if (TWO) p2[(int64_t)a * c + b] = (double)acc2[r][s];
+        for (int q = 0; q < WT; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = ca + 16 * p + MF::out_row(lane, v);
+                const int b = cb + 16 * q + lc;
+                if (a < c && b < c) {
+                    p1[(int64_t)a * c + b] = (double)acc1[p][q][v];
+                    if (TWO) p2[(int64_t)a * c + b] = (double)acc2[p][q][v];
+                }
             }
-        }
 }
 
 // sum the chunk partials in chunk order; upper entries, mirrored
@@ -376,15 +437,20 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-GramPlan gram_plan(int64_t n, int c) {
+GramPlan gram_plan(int64_t n, int c, int elem_bytes) {
     GramPlan p;
     p.n = n;
     p.c = c;
-    p.tiles = (int)ceil_div(c, GT);
+    // workgroup tile edge: 128 (FP32 / BF16 matrix-core path), 64 (FP64)
+    p.bt = elem_bytes == 8 ? 64 : 128;
+    p.tiles = (int)ceil_div(c, p.bt);
     const int upper = p.tiles * (p.tiles + 1) / 2;
     // enough workgroups to fill 256 CUs several times, each chunk >= 512 rows
     int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, upper), ceil_div(n, 512)));
     p.chunks = std::min(chunks, 256);
+    // chunk boundaries on multiples of 32 rows (the BF16 MFMA step)
+    p.chunk_rows = ceil_div(ceil_div(n, p.chunks), 32) * 32;
+    p.chunks = (int)ceil_div(n, p.chunk_rows);
     return p;
 }
 
@@ -396,17 +462,30 @@ template <class T>
 sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, const T* B1,
                       int64_t ldb1, const T* B2, int64_t ldb2, double* partial, double* G1,
                       double* G2, int bf16) {
-    (void)bf16;
     const int upper = p.tiles * (p.tiles + 1) / 2;
-    const int64_t chunk_rows = ceil_div(p.n, p.chunks);
     dim3 grid(upper, p.chunks);
-    using ACC = T;
-    if (B2)
-        hipLaunchKernelGGL((k_gram_partial<T, ACC, true>), grid, dim3(256), 0, ctx->stream, p.n,
-                           p.c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
-    else
-        hipLaunchKernelGGL((k_gram_partial<T, ACC, false>), grid, dim3(256), 0, ctx->stream, p.n,
-                           p.c, chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+    if constexpr (sizeof(T) == 8) {
+        if (B2)
+            hipLaunchKernelGGL((k_gram_mfma<MfF64, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
+        else
+            hipLaunchKernelGGL((k_gram_mfma<MfF64, false>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                               p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+    } else if (bf16) {
+        if (B2)
+            hipLaunchKernelGGL((k_gram_mfma<MfBF16, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
+        else
+            hipLaunchKernelGGL((k_gram_mfma<MfBF16, false>), grid, dim3(256), 0, ctx->stream, p.n,
+                               p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+    } else {
+        if (B2)
+            hipLaunchKernelGGL((k_gram_mfma<MfF32, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
+        else
+            hipLaunchKernelGGL((k_gram_mfma<MfF32, false>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                               p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+    }
     SC_CHECK_LAUNCH(ctx);
     const int64_t cc2 = (int64_t)p.c * p.c;
     hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(cc2, 256)), dim3(256), 0, ctx->stream, p.c,

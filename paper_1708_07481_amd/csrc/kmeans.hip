@@ -159,7 +159,7 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
               const double* __restrict__ Ct, const uint32_t* __restrict__ pts,
               const int* __restrict__ cnt, const int* __restrict__ active,
               int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
-              int* __restrict__ changed, int first) {
+              int* __restrict__ changed, int* __restrict__ dirty, int first) {
     constexpr int DC = 32;
     __shared__ double ys[DC][65];   // padded row: fewer LDS bank conflicts on the transposing store
     __shared__ uint32_t pid[64];
@@ -246,7 +246,14 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
             }
         }
         const int64_t e = (int64_t)r * n + pid[lane];
-        if (!first && lab[e] != j) atomicAdd(&changed[r], 1);
+        if (!first) {
+            const int old = lab[e];
+            if (old != j) {
+                atomicAdd(&changed[r], 1);
+                dirty[(int64_t)r * K + old] = 1;    // both member lists changed
+                dirty[(int64_t)r * K + j] = 1;
+            }
+        }
         lab[e] = j;
         ub[e] = sqrt(b) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
         lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
@@ -304,37 +311,59 @@ k_delta(int K, int dim, const double* __restrict__ C, const double* __restrict__
     }
 }
 
-// move the bounds by the displacements; list the points that need a scan
-// (grid: x over points, y over restarts; one list append per wave)
-__global__ void k_bounds(int64_t n, int K, const int32_t* __restrict__ lab,
-                         double* __restrict__ ub, double* __restrict__ lb,
-                         const double* __restrict__ delta, const double* __restrict__ dinfo,
-                         const int* __restrict__ active, uint32_t* __restrict__ pts,
-                         int* __restrict__ cnt) {
+// move the bounds by the displacements; list the points that need a scan.
+// Grid: x over tiles of TH * PPT points, y over restarts; the tile's list
+// entries are reserved with a single atomic (the counters are per restart,
+// so per-wave atomics would serialise on a handful of addresses).
+constexpr int PPT = 8;
+__global__ void __launch_bounds__(TH)
+k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, double* __restrict__ ub,
+         double* __restrict__ lb, const double* __restrict__ delta, const double* __restrict__ dinfo,
+         const int* __restrict__ active, uint32_t* __restrict__ pts, int* __restrict__ cnt) {
+    __shared__ int wtot[TH / 64];
+    __shared__ int base_s;
     const int r = blockIdx.y;
     if (!active[r]) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool need = false;
-    if (i < n) {
-        const int64_t e = (int64_t)r * n + i;
-        const int a = lab[e];
-        const double dmax = ((int)dinfo[3 * r + 1] == a) ? dinfo[3 * r + 2] : dinfo[3 * r + 0];
-        const double u = (ub[e] + delta[(int64_t)r * K + a]) * (1.0 + BOUND_MARGIN);
-        const double l = (lb[e] - dmax) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
-        ub[e] = u;
-        lb[e] = l;
-        need = !(u < l);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double dmax0 = dinfo[3 * r + 0], dmax1 = dinfo[3 * r + 2];
+    const int amax = (int)dinfo[3 * r + 1];
+    unsigned long long masks[PPT];
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int64_t i = ((int64_t)blockIdx.x * PPT + u) * TH + threadIdx.x;
+        bool need = false;
+        if (i < n) {
+            const int64_t e = (int64_t)r * n + i;
+            const int a = lab[e];
+            const double dmax = a == amax ? dmax1 : dmax0;
+            const double uu = (ub[e] + delta[(int64_t)r * K + a]) * (1.0 + BOUND_MARGIN);
+            const double ll = (lb[e] - dmax) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+            ub[e] = uu;
+            lb[e] = ll;
+            need = !(uu < ll);
+        }
+        masks[u] = __ballot(need);
+        mine += __popcll(masks[u]);
     }
-    const unsigned long long mask = __ballot(need);
-    if (mask == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&cnt[r], __popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (need) {
-        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
-        pts[(int64_t)r * n + base + rank] = (uint32_t)i;
+    if (lane == 0) wtot[wave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int q = 0; q < TH / 64; ++q) t += wtot[q];
+        base_s = t ? atomicAdd(&cnt[r], t) : 0;
+    }
+    __syncthreads();
+    int off = base_s;
+    for (int q = 0; q < wave; ++q) off += wtot[q];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const unsigned long long mask = masks[u];
+        if ((mask >> lane) & 1ull) {
+            const int64_t i = ((int64_t)blockIdx.x * PPT + u) * TH + threadIdx.x;
+            pts[(int64_t)r * n + off + __popcll(mask & ((1ull << lane) - 1ull))] = (uint32_t)i;
+        }
+        off += __popcll(mask);
     }
 }
 
@@ -356,17 +385,19 @@ __global__ void k_segments(int64_t len, const uint64_t* __restrict__ keys, int64
     if (p + 1 == len || keys[p + 1] != k) seg[2 * k + 1] = p + 1;
 }
 
-// centroid (r, j), dimension d: members in ascending vertex order
+// centroid (r, j), dimension d: members in ascending vertex order.  Only
+// clusters whose member list changed since their last update are summed
+// again (an unchanged list gives a bitwise identical sum).
 __global__ void __launch_bounds__(TH)
 k_centroids(int dim, int K, int R, const double* __restrict__ Y,
             const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
-            const int* __restrict__ active, double* __restrict__ C) {
+            const int* __restrict__ active, const int* __restrict__ dirty, double* __restrict__ C) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)R * K * dim) return;
     const int d = (int)(e % dim);
     const int64_t rj = e / dim;
     const int r = (int)(rj / K);
-    if (!active[r]) return;
+    if (!active[r] || !dirty[rj]) return;
     const int64_t lo = seg[2 * rj], hi = seg[2 * rj + 1];
     const int64_t cnt = hi - lo;
     if (cnt <= 0) return;
@@ -458,6 +489,11 @@ __global__ void k_zero_i32(int* p, int n) {
     if (i < n) p[i] = 0;
 }
 
+__global__ void k_fill_i32(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // centres per wave and pass: the smallest supported width covering K in one
 // pass (four waves), else 64 with several passes; Kpad = passes * 4 * JB
 int assign_width(int K) {
@@ -477,7 +513,7 @@ struct KmWs {
     uint64_t *wq, *scan_tmp, *keys, *keys_alt, *radix_tmp;
     uint32_t *vals, *vals_alt, *pts;
     int32_t* lab;
-    int *changed, *active, *cnt, *status;
+    int *changed, *active, *cnt, *status, *dirty;
     int64_t* seg;
     unsigned long long *m2, *q;
 };
@@ -510,6 +546,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.active = c.take<int>(R);
     w.cnt = c.take<int>(R);
     w.status = c.take<int>(1);
+    w.dirty = c.take<int>((size_t)R * K);
     w.seg = c.take<int64_t>(2 * (size_t)R * K);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
@@ -533,7 +570,7 @@ void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
     dim3 grid((unsigned)ceil_div(n, 64), (unsigned)R);
     hipLaunchKernelGGL((k_assign_list<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
                        assign_kpad(K), w.Y, w.Ct, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
-                       w.changed, first);
+                       w.changed, w.dirty, first);
 }
 
 void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
@@ -618,16 +655,16 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (init_centroids) {
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.C, init_centroids, cent_bytes, hipMemcpyDeviceToDevice, st));
     } else {
+        uint64_t* pref = w.keys;            // prefix sums of the weights (scan output)
         for (int j = 0; j < K; ++j) {
-            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Y, draws,
-                               w.wq, w.C);
+            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Y, draws, pref,
+                               w.C);
             SC_CHECK_LAUNCH(ctx);
-            if (j + 1 < K) {
-                hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, j, R,
-                                   w.Yt, w.C, w.D2, w.wq, shift);
-                SC_CHECK_LAUNCH(ctx);
-                SC_TRY(scan_u64_batched(ctx, w.wq, w.wq, n, R, w.scan_tmp));
-            }
+            if (j + 1 == K) break;
+            hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, j, R,
+                               w.Yt, w.C, w.D2, w.wq, shift);
+            SC_CHECK_LAUNCH(ctx);
+            SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
         }
     }
     const dim3 gcent((unsigned)ceil_div((int64_t)R * K * dim, TH));
@@ -638,6 +675,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     hipLaunchKernelGGL(k_fill_lists, gnr, dim3(TH), 0, st, n, R, w.pts, w.cnt);
     SC_CHECK_LAUNCH(ctx);
     assign(ctx, n, dim, K, R, w, 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
+                       R * K, 1);
     SC_CHECK_LAUNCH(ctx);
     const int bits = ceil_log2_u64((uint64_t)R * K);
     int n_active = R;
@@ -652,7 +691,9 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                            2 * (int64_t)R * K);
         hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, nr, w.keys, w.seg);
         hipLaunchKernelGGL(k_centroids, gcent, dim3(TH), 0, st, dim, K, R, w.Y, w.vals, w.seg,
-                           w.active, w.C);
+                           w.active, w.dirty, w.C);
+        hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
+                           R * K);
         hipLaunchKernelGGL(k_delta, dim3(R), dim3(TH), 0, st, K, dim, w.C, w.Cold, w.active, w.delta,
                            w.dinfo);
         hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C,
@@ -661,8 +702,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         // points whose assignment may change, then their scans
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.cnt, R);
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.changed, R);
-        hipLaunchKernelGGL(k_bounds, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st,
-                           n, K, w.lab, w.ub, w.lb, w.delta, w.dinfo, w.active, w.pts, w.cnt);
+        hipLaunchKernelGGL(k_bounds, dim3((unsigned)ceil_div(n, TH * PPT), (unsigned)R), dim3(TH), 0,
+                           st, n, K, w.lab, w.ub, w.lb, w.delta, w.dinfo, w.active, w.pts, w.cnt);
         SC_CHECK_LAUNCH(ctx);
         assign(ctx, n, dim, K, R, w, 0);
         SC_CHECK_LAUNCH(ctx);

@@ -88,8 +88,8 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.K3 = K3;
     s.S = c.take<char>((size_t)n * K3 * es);
     s.LS = c.take<char>((size_t)n * K3 * es);
-    s.plan3 = gram_plan(n, K3);
-    s.plank = gram_plan(n, kp);
+    s.plan3 = gram_plan(n, K3, (int)es);
+    s.plank = gram_plan(n, kp, (int)es);
     s.GA = c.take<double>((size_t)K3 * K3);
     s.GB = c.take<double>((size_t)K3 * K3);
     s.Gpart = c.take<double>(gram_partial_elems(s.plan3, 2));

@@ -152,23 +152,32 @@ __device__ inline int sturm_count(int m, const double* d, const double* e, doubl
     return c;
 }
 
-// k smallest eigenpairs of the m x m symmetric matrix A (destroyed).  w[k]
-// ascending; V (m x k, row stride ldv) eigenvectors.  `ws` scratch of
-// symeig_scratch_elems(m, k) doubles.
-__device__ void eig_lowest(int m, int k, double* A, double* w, double* V, int ldv, double* ws,
-                           double* red, double* sh) {
-    const int tid = threadIdx.x;
-    double* d = ws;
-    double* e = d + m;
-    double* tau = e + m;
-    double* v = tau + m;
-    double* p = v + m;
-    double* shift = p + m;             // k perturbed shifts
-    double* lu = shift + k;            // k x 6m per-thread LU storage
-    tridiagonalize(m, A, d, e, tau, v, p, red, sh);
-    // Gershgorin interval and scale
+// ---------------------------------------------------------------------------
+// Eigenpairs of the symmetric tridiagonal T = (d, e) for its k smallest
+// eigenvalues, in four launches:
+//   k_tri_params  Gershgorin interval, scale and pivot floor;
+//   k_tri_bisect  one wave per eigenvalue: 64-way multisection with Sturm
+//                 counts (lane l evaluates the count at the l-th interior
+//                 point; the bracket keeps count(lo) <= i < count(hi));
+//   k_tri_invit   one thread per eigenvector: inverse iteration with a
+//                 pivoted LU of T - shift I (3 steps from a fixed
+//                 pseudo-random start); coincident eigenvalues get shifts
+//                 pulled apart by 10 eps ||T||;
+//   k_tri_mgs     vectors of eigenvalues closer than 1e-4 ||T|| are
+//                 re-orthogonalised by modified Gram-Schmidt (twice).
+// Layout of the tridiagonal block `tri` (doubles): d[MAXM], e[MAXM],
+// tau[MAXM], params[8].
+// ---------------------------------------------------------------------------
+constexpr int TRI_PARAMS = 3 * MAXM;
+
+__global__ void __launch_bounds__(NT) k_tri_params(const int* __restrict__ info, double* __restrict__ tri) {
+    __shared__ double red[NWAVE + 1];
+    const int m = info[0];
+    if (m == 0) return;
+    const double* d = tri;
+    const double* e = tri + MAXM;
     double lo_l = DBL_MAX, hi_l = -DBL_MAX, nrm_l = 0.0, emax_l = 0.0;
-    for (int i = tid; i < m; i += NT) {
+    for (int i = threadIdx.x; i < m; i += NT) {
         const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
         const double er = i + 1 < m ? fabs(e[i]) : 0.0;
         lo_l = fmin(lo_l, d[i] - el - er);
@@ -180,155 +189,208 @@ __device__ void eig_lowest(int m, int k, double* A, double* w, double* V, int ld
     const double gu = block_max(hi_l, red);
     const double tnorm = fmax(block_max(nrm_l, red), DBL_MIN);
     const double emax2 = block_max(emax_l, red);
-    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    if (threadIdx.x == 0) {
+        const double pivmin = DBL_MIN * fmax(1.0, emax2);
+        double* P = tri + TRI_PARAMS;
+        P[0] = gl - 2.0 * DBL_EPSILON * tnorm - 2.0 * pivmin;
+        P[1] = gu + 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+        P[2] = tnorm;
+        P[3] = pivmin;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_tri_bisect(int k, const int* __restrict__ info, const double* __restrict__ tri,
+             double* __restrict__ w) {
+    const int m = info[0];
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (m == 0 || i >= k) return;
+    const double* d = tri;
+    const double* e = tri + MAXM;
+    const double* P = tri + TRI_PARAMS;
+    double lo = P[0], hi = P[1];
+    const double tnorm = P[2], pivmin = P[3];
+    for (int it = 0; it < 24; ++it) {
+        if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 1e-18 * tnorm) break;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
+        const bool le = (x > lo && x < hi) ? sturm_count(m, d, e, x, pivmin) <= i : (x <= lo);
+        const unsigned long long mask = __ballot(le);
+        // first lane whose point has more than i eigenvalues below it
+        const unsigned long long gt = ~mask;
+        const int t = gt ? __ffsll((long long)gt) - 1 : 64;
+        const double xl = __shfl(x, t > 0 ? t - 1 : 0, 64);
+        const double xh = __shfl(x, t < 64 ? t : 63, 64);
+        const double nlo = t > 0 ? xl : lo;
+        const double nhi = t < 64 ? xh : hi;
+        if (nlo == lo && nhi == hi) break;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) w[i] = 0.5 * (lo + hi);
+}
+
+// one thread per eigenvector; LU arrays laid out [q][eigenvector] so that
+// the lanes of a wave touch consecutive addresses
+__global__ void __launch_bounds__(64)
+k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
+            const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ lu) {
+    const int m = info[0];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (m == 0 || i >= k) return;
+    const double* d = tri;
+    const double* e = tri + MAXM;
+    const double tnorm = tri[TRI_PARAMS + 2];
     const double eps = DBL_EPSILON;
-    // bisection: thread i finds the (i+1)-th smallest eigenvalue
-    for (int i = tid; i < k; i += NT) {
-        double lo = gl - 2.0 * eps * tnorm - 2.0 * pivmin, hi = gu + 2.0 * eps * tnorm + 2.0 * pivmin;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 1e-18 * tnorm) break;
-            if (sturm_count(m, d, e, mid, pivmin) <= i) lo = mid;
-            else hi = mid;
-        }
-        w[i] = 0.5 * (lo + hi);
-    }
-    __syncthreads();
-    // shifts: coincident eigenvalues are pulled apart slightly so that the
-    // inverse iterations start from distinct factorisations
-    if (tid == 0) {
-        const double sep = 10.0 * eps * tnorm;
-        for (int i = 0; i < k; ++i) {
-            double s = w[i];
-            if (i > 0 && s - shift[i - 1] < sep) s = shift[i - 1] + sep;
-            shift[i] = s;
-        }
-    }
-    __syncthreads();
-    // inverse iteration, one eigenvector per thread
     const double tiny = eps * tnorm;
-    for (int i = tid; i < k; i += NT) {
-        double* U0 = lu + (int64_t)i * 6 * m;
-        double* U1 = U0 + m;
-        double* U2 = U1 + m;
-        double* Lm = U2 + m;
-        double* SW = Lm + m;
-        double* z = SW + m;
-        const double lam = shift[i];
-        // LU of T - lam I with partial pivoting; (r0, r1) is the current row
-        // (columns q, q+1) left after eliminating the rows above it
-        double r0 = d[0] - lam, r1 = m > 1 ? e[0] : 0.0;
-        for (int q = 0; q + 1 < m; ++q) {
-            const double sub = e[q];                       // row q+1: (sub, a1, b1)
-            const double a1 = d[q + 1] - lam;
-            const double b1 = q + 2 < m ? e[q + 1] : 0.0;
-            if (fabs(r0) >= fabs(sub)) {
-                if (r0 == 0.0) r0 = tiny;
-                const double l = sub / r0;
-                U0[q] = r0; U1[q] = r1; U2[q] = 0.0; Lm[q] = l; SW[q] = 0.0;
-                r0 = a1 - l * r1;
-                r1 = b1;
-            } else {
-                const double l = r0 / sub;
-                U0[q] = sub; U1[q] = a1; U2[q] = b1; Lm[q] = l; SW[q] = 1.0;
-                r0 = r1 - l * a1;
-                r1 = -l * b1;
-            }
-        }
-        if (r0 == 0.0) r0 = tiny;
-        U0[m - 1] = r0;
-        for (int r = 0; r < m; ++r)
-            z[r] = (double)(mix64(((uint64_t)i << 32) ^ (uint64_t)r) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
-        for (int itn = 0; itn < 3; ++itn) {
-            double rc = z[0];
-            for (int q = 0; q + 1 < m; ++q) {
-                const double nxt = z[q + 1];
-                if (SW[q] != 0.0) {
-                    z[q] = nxt;
-                    rc = rc - Lm[q] * nxt;
-                } else {
-                    z[q] = rc;
-                    rc = nxt - Lm[q] * rc;
-                }
-            }
-            z[m - 1] = rc;
-            for (int q = m - 1; q >= 0; --q) {
-                double sacc = z[q];
-                if (q + 1 < m) sacc -= U1[q] * z[q + 1];
-                if (q + 2 < m) sacc -= U2[q] * z[q + 2];
-                z[q] = sacc / U0[q];
-            }
-            double nn = 0.0;
-            for (int r = 0; r < m; ++r) nn = fma(z[r], z[r], nn);
-            const double inv = 1.0 / sqrt(nn);
-            for (int r = 0; r < m; ++r) z[r] *= inv;
-        }
-        for (int r = 0; r < m; ++r) V[(int64_t)r * ldv + i] = z[r];
+    // shift: coincident eigenvalues pulled apart (sequential over lower indices)
+    const double sep = 10.0 * eps * tnorm;
+    double lam = w[0];
+    for (int q = 1; q <= i; ++q) {
+        const double s = w[q];
+        lam = (s - lam < sep) ? lam + sep : s;
     }
-    __syncthreads();
-    // modified Gram-Schmidt (twice) inside clusters of close eigenvalues
-    const double ctol = 1e-4 * tnorm;
-    for (int c0 = 0; c0 < k;) {
+    double* U0 = lu;
+    double* U1 = U0 + (int64_t)MAXM * k;
+    double* U2 = U1 + (int64_t)MAXM * k;
+    double* Lm = U2 + (int64_t)MAXM * k;
+    double* SW = Lm + (int64_t)MAXM * k;
+#define AT(arr, q) arr[(int64_t)(q) * k + i]
+    double r0 = d[0] - lam, r1 = m > 1 ? e[0] : 0.0;
+    for (int q = 0; q + 1 < m; ++q) {
+        const double sub = e[q];
+        const double a1 = d[q + 1] - lam;
+        const double b1 = q + 2 < m ? e[q + 1] : 0.0;
+        if (fabs(r0) >= fabs(sub)) {
+            if (r0 == 0.0) r0 = tiny;
+            const double l = sub / r0;
+            AT(U0, q) = r0; AT(U1, q) = r1; AT(U2, q) = 0.0; AT(Lm, q) = l; AT(SW, q) = 0.0;
+            r0 = a1 - l * r1;
+            r1 = b1;
+        } else {
+            const double l = r0 / sub;
+            AT(U0, q) = sub; AT(U1, q) = a1; AT(U2, q) = b1; AT(Lm, q) = l; AT(SW, q) = 1.0;
+            r0 = r1 - l * a1;
+            r1 = -l * b1;
+        }
+    }
+    if (r0 == 0.0) r0 = tiny;
+    AT(U0, m - 1) = r0;
+    double* z = V + i;      // column i, row stride ldv
+    for (int r = 0; r < m; ++r)
+        z[(int64_t)r * ldv] =
+            (double)(mix64(((uint64_t)i << 32) ^ (uint64_t)r) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    for (int itn = 0; itn < 3; ++itn) {
+        double rc = z[0];
+        for (int q = 0; q + 1 < m; ++q) {
+            const double nxt = z[(int64_t)(q + 1) * ldv];
+            const double l = AT(Lm, q);
+            if (AT(SW, q) != 0.0) {
+                z[(int64_t)q * ldv] = nxt;
+                rc = rc - l * nxt;
+            } else {
+                z[(int64_t)q * ldv] = rc;
+                rc = nxt - l * rc;
+            }
+        }
+        z[(int64_t)(m - 1) * ldv] = rc;
+        // back substitution; the last two solution values stay in registers
+        double z1 = 0.0, z2 = 0.0, nn = 0.0;
+        for (int q = m - 1; q >= 0; --q) {
+            double sacc = z[(int64_t)q * ldv];
+            sacc -= AT(U1, q) * z1;
+            sacc -= AT(U2, q) * z2;
+            const double zq = sacc / AT(U0, q);
+            z[(int64_t)q * ldv] = zq;
+            nn = fma(zq, zq, nn);
+            z2 = z1;
+            z1 = zq;
+        }
+        const double inv = 1.0 / sqrt(nn);
+        for (int r = 0; r < m; ++r) z[(int64_t)r * ldv] *= inv;
+    }
+#undef AT
+}
+
+// Vectors of a cluster are orthonormalised in index order; vector q is
+// projected against all earlier members at once (classical Gram-Schmidt,
+// applied twice) and normalised.  Clusters are independent: workgroup g takes
+// clusters g, g + gridDim, ...
+__global__ void __launch_bounds__(NT)
+k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
+          const double* __restrict__ w, double* __restrict__ V, int ldv) {
+    __shared__ double red[NWAVE + 1];
+    __shared__ double dots[MAXM];
+    const int m = info[0];
+    if (m == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double ctol = 1e-4 * tri[TRI_PARAMS + 2];
+    int cl = 0;
+    for (int c0 = 0; c0 < k; ++cl) {
         int c1 = c0 + 1;
         while (c1 < k && w[c1] - w[c1 - 1] <= ctol) ++c1;
-        if (c1 - c0 > 1) {
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int q = c0; q < c1; ++q) {
-                    for (int pp = c0; pp < q; ++pp) {
+        if (c1 - c0 > 1 && cl % gridDim.x == blockIdx.x) {
+            for (int q = c0; q < c1; ++q) {
+                for (int pass = 0; pass < 2 && q > c0; ++pass) {
+                    // dots with the earlier members, one wave per member
+                    for (int pp = c0 + wave; pp < q; pp += NWAVE) {
                         double part = 0.0;
-                        for (int r = tid; r < m; r += NT)
+                        for (int r = lane; r < m; r += 64)
                             part = fma(V[(int64_t)r * ldv + pp], V[(int64_t)r * ldv + q], part);
-                        const double dt = block_sum(part, red);
-                        for (int r = tid; r < m; r += NT)
-                            V[(int64_t)r * ldv + q] -= dt * V[(int64_t)r * ldv + pp];
-                        __syncthreads();
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+                        if (lane == 0) dots[pp - c0] = part;
                     }
-                    double part = 0.0;
-                    for (int r = tid; r < m; r += NT)
-                        part = fma(V[(int64_t)r * ldv + q], V[(int64_t)r * ldv + q], part);
-                    const double inv = 1.0 / sqrt(block_sum(part, red));
-                    for (int r = tid; r < m; r += NT) V[(int64_t)r * ldv + q] *= inv;
+                    __syncthreads();
+                    for (int r = tid; r < m; r += NT) {
+                        double x = V[(int64_t)r * ldv + q];
+                        for (int pp = c0; pp < q; ++pp) x = fma(-dots[pp - c0], V[(int64_t)r * ldv + pp], x);
+                        V[(int64_t)r * ldv + q] = x;
+                    }
                     __syncthreads();
                 }
+                double part = 0.0;
+                for (int r = tid; r < m; r += NT)
+                    part = fma(V[(int64_t)r * ldv + q], V[(int64_t)r * ldv + q], part);
+                const double inv = 1.0 / sqrt(block_sum(part, red));
+                for (int r = tid; r < m; r += NT) V[(int64_t)r * ldv + q] *= inv;
+                __syncthreads();
             }
         }
         c0 = c1;
     }
-    // back-transform: Q = H_0 H_1 ... H_{m-3} Z, one column per thread
-    for (int i = tid; i < k; i += NT) {
-        for (int j = m - 3; j >= 0; --j) {
-            const double tj = tau[j];
-            if (tj == 0.0) continue;
-            const double* vj = A + (int64_t)j * m + j + 1;   // v_0 = 1 implicit
-            double s = V[(int64_t)(j + 1) * ldv + i];
-            for (int r = 1; r < m - j - 1; ++r) s = fma(vj[r], V[(int64_t)(j + 1 + r) * ldv + i], s);
-            s *= tj;
-            V[(int64_t)(j + 1) * ldv + i] -= s;
-            for (int r = 1; r < m - j - 1; ++r) V[(int64_t)(j + 1 + r) * ldv + i] -= s * vj[r];
-        }
-    }
-    __syncthreads();
 }
 
-__global__ void __launch_bounds__(NT) k_symeig(int m, int k, const double* __restrict__ Ain,
-                                               double* __restrict__ w, double* __restrict__ V,
-                                               double* __restrict__ scr) {
-    __shared__ double red[NWAVE + 1];
-    __shared__ double sh[4];
-    double* A = scr;
-    for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += NT) A[q] = Ain[q];
-    __syncthreads();
-    eig_lowest(m, k, A, w, V, k, scr + (int64_t)m * m, red, sh);
+// Householder reflectors (stored in A as described for tridiagonalize)
+// applied to the columns of V: V <- H_0 H_1 ... H_{m-3} V, one wave per
+// column, the reflector dot products reduced across the wave.
+__device__ void back_transform_col(int m, const double* A, const double* tau, double* v_col,
+                                   int ldv) {
+    const int lane = threadIdx.x & 63;
+    for (int j = m - 3; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        const double* vj = A + (int64_t)j * m + j + 1;   // v_0 = 1 implicit
+        const int len = m - j - 1;
+        double part = 0.0;
+        for (int r = lane; r < len; r += 64)
+            part = fma(r == 0 ? 1.0 : vj[r], v_col[(int64_t)(j + 1 + r) * ldv], part);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        const double sc = tj * part;
+        for (int r = lane; r < len; r += 64)
+            v_col[(int64_t)(j + 1 + r) * ldv] -= sc * (r == 0 ? 1.0 : vj[r]);
+    }
 }
 
 // --- Rayleigh-Ritz, step 1 (one workgroup): active set, Cholesky of the
-// basis Gram matrix (P dropped and retried once on failure), U^-1, and the
-// reduced G_A gathered to a dense m x m block.  info[0] = m (0 on breakdown).
+// basis Gram matrix (P dropped and retried once on failure), and the
+// reduced G_A gathered to a dense m x m block.  info[0] = m (0 on breakdown),
+// info[1..m] = the active column indices.
 __global__ void __launch_bounds__(NT)
 k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restrict__ GB,
-           int* __restrict__ act, double tol, double* __restrict__ U, double* __restrict__ Ui,
-           double* __restrict__ Am, int* __restrict__ info, int* status, int* counter) {
+           int* __restrict__ act, double tol, double* __restrict__ U, double* __restrict__ Am,
+           int* __restrict__ info, int* status, int* counter) {
     __shared__ int idx[MAXM];
     __shared__ int m_s, fail_s, has_p;
     const int tid = threadIdx.x;
@@ -387,16 +449,6 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
             if (counter) atomicAdd(counter, 1);
         }
         __syncthreads();
-    }
-    // U^-1 (upper), one column per thread; lower parts zero
-    for (int j = tid; j < m; j += NT) {
-        for (int a = j + 1; a < m; ++a) Ui[(int64_t)a * m + j] = 0.0;
-        Ui[(int64_t)j * m + j] = 1.0 / U[(int64_t)j * m + j];
-        for (int a = j - 1; a >= 0; --a) {
-            double s = 0.0;
-            for (int l = a + 1; l <= j; ++l) s = fma(U[(int64_t)a * m + l], Ui[(int64_t)l * m + j], s);
-            Ui[(int64_t)a * m + j] = -s / U[(int64_t)a * m + a];
-        }
     }
     for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
         const int a = (int)(q / m), b = (int)(q % m);
@@ -457,12 +509,37 @@ k_gemm64(const int* __restrict__ info, int n_fixed, int transA, const double* __
     }
 }
 
-// --- step 3 (one workgroup): symmetrise M, k smallest eigenpairs
+// --- step 2: U^-1 (upper triangular), one wave per column j: back
+// substitution from row j-1 up to row 0, each row's dot product split over
+// the lanes; the column being built lives in LDS.
+__global__ void __launch_bounds__(256)
+k_rr_inv(const int* __restrict__ info, const double* __restrict__ U, double* __restrict__ Ui) {
+    __shared__ double col[4][MAXM];
+    const int m = info[0];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + wave;
+    if (j >= m) return;
+    double* cj = col[wave];
+    if (lane == 0) cj[j] = 1.0 / U[(int64_t)j * m + j];
+    __builtin_amdgcn_wave_barrier();
+    for (int a = j - 1; a >= 0; --a) {
+        double part = 0.0;
+        for (int l = a + 1 + lane; l <= j; l += 64) part = fma(U[(int64_t)a * m + l], cj[l], part);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+        const double x = -part / U[(int64_t)a * m + a];
+        if (lane == 0) cj[a] = x;
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (int a = lane; a < m; a += 64) Ui[(int64_t)a * m + j] = a <= j ? cj[a] : 0.0;
+}
+
+// --- step 3a (one workgroup): symmetrise M and reduce it to tridiagonal form
 __global__ void __launch_bounds__(NT)
-k_rr_eig(int k, const int* __restrict__ info, double* __restrict__ M, double* __restrict__ theta,
-         double* __restrict__ Q, double* __restrict__ ews) {
+k_rr_tridiag(const int* __restrict__ info, double* __restrict__ M, double* __restrict__ dtau) {
     __shared__ double red[NWAVE + 1];
     __shared__ double sh[4];
+    __shared__ double vs[MAXM], ps[MAXM];
     const int m = info[0];
     if (m == 0) return;
     for (int64_t q = threadIdx.x; q < (int64_t)m * m; q += NT) {
@@ -474,7 +551,41 @@ k_rr_eig(int k, const int* __restrict__ info, double* __restrict__ M, double* __
         }
     }
     __syncthreads();
-    eig_lowest(m, k, M, theta, Q, k, ews, red, sh);
+    double* d = dtau;
+    double* e = d + MAXM;
+    double* tau = e + MAXM;
+    tridiagonalize(m, M, d, e, tau, vs, ps, red, sh);
+}
+
+__global__ void k_set_info(int* info, int m) {
+    if (threadIdx.x == 0) info[0] = m;
+}
+
+__global__ void k_copy_f64(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// --- step 3c: Householder back-transform of the k eigenvectors, one wave each
+__global__ void __launch_bounds__(256)
+k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
+          const double* __restrict__ dtau, double* __restrict__ Q) {
+    const int m = info[0];
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (m == 0 || i >= k) return;
+    back_transform_col(m, M, dtau + 2 * MAXM, Q + i, k);
+}
+
+// tridiagonalised M (in `M`, reflectors inside) + tri block -> k smallest
+// eigenpairs (w, and V = m x k eigenvectors of M)
+static void eig_pipeline(hipStream_t st, int k, const int* info, const double* M, double* tri,
+                         double* w, double* V, double* lu) {
+    hipLaunchKernelGGL(k_tri_params, dim3(1), dim3(NT), 0, st, info, tri);
+    hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, tri, w);
+    hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0, st, k, info, tri, w,
+                       V, k, lu);
+    hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k);
+    hipLaunchKernelGGL(k_rr_back, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, M, tri, V);
 }
 
 // --- step 5: scatter C_act (m x k) to the rows of the active columns (the
@@ -505,12 +616,14 @@ __global__ void k_rr_scatter(int k, int kp, const int* __restrict__ info,
 }  // namespace
 
 size_t symeig_scratch_elems(int m, int k) {
-    return (size_t)m * m + 5 * (size_t)m + k + 6 * (size_t)m * k + 64;
+    // matrix copy, d/e/tau/params, info, LU arrays
+    return (size_t)m * m + 3 * (size_t)MAXM + 8 + (MAXM + 64) / 2 + 5 * (size_t)MAXM * k + 64;
 }
 
 size_t rr_scratch_elems(int K3, int k) {
-    // U, Ui, Am, Tm/M (K3^2 each), Q and Cq (K3 x k), info (ints), eigensolver scratch
-    return 4 * (size_t)K3 * K3 + 2 * (size_t)K3 * k + (size_t)K3 + 64 + symeig_scratch_elems(K3, k);
+    // U, Ui, Am, Tm (K3^2 each), Q and Cq (K3 x k), d/e/tau/params, info, LU arrays
+    return 4 * (size_t)K3 * K3 + 2 * (size_t)K3 * k + 3 * (size_t)MAXM + 8 + (MAXM + 64) / 2 +
+           5 * (size_t)MAXM * k + 64;
 }
 
 sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
@@ -521,18 +634,21 @@ sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double*
     double* U = scratch;
     double* Ui = U + sq;
     double* Am = Ui + sq;
-    double* Tm = Am + sq;                    // A U^-1, then reused for M
+    double* Tm = Am + sq;                    // A U^-1
     double* Q = Tm + sq;                     // m x k
     double* Cq = Q + (size_t)K3 * k;         // m x k
-    int* info = reinterpret_cast<int*>(Cq + (size_t)K3 * k);
-    double* ews = Cq + (size_t)K3 * k + (K3 + 64) / 2 + 32;
+    double* dtau = Cq + (size_t)K3 * k;      // d, e, tau (3 x MAXM) + params
+    int* info = reinterpret_cast<int*>(dtau + 3 * MAXM + 8);
+    double* ews = dtau + 3 * MAXM + 8 + (MAXM + 64) / 2;   // inverse-iteration LU arrays
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_rr_setup, dim3(1), dim3(NT), 0, st, K3, kp, GA, GB, act, tol, U, Ui, Am,
-                       info, status, counter);
+    hipLaunchKernelGGL(k_rr_setup, dim3(1), dim3(NT), 0, st, K3, kp, GA, GB, act, tol, U, Am, info,
+                       status, counter);
+    hipLaunchKernelGGL(k_rr_inv, dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st, info, U, Ui);
     const dim3 gsq((unsigned)ceil_div(K3, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 0, Am, Ui, Tm);   // Tm = A U^-1
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 1, Ui, Tm, U);    // M = U^-T Tm (into U)
-    hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(NT), 0, st, k, info, U, theta, Q, ews);
+    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, info, U, dtau);
+    eig_pipeline(st, k, info, U, dtau, theta, Q, ews);
     const dim3 gk((unsigned)ceil_div(k, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, info, k, 0, Ui, Q, Cq);    // C = U^-1 Q
     hipLaunchKernelGGL(k_rr_zero, dim3((unsigned)ceil_div((int64_t)K3 * kp, 256)), dim3(256), 0, st,
@@ -545,7 +661,17 @@ sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double*
 
 sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
                         double* scratch) {
-    hipLaunchKernelGGL(k_symeig, dim3(1), dim3(NT), 0, ctx->stream, m, k, A, w, V, scratch);
+    if (m > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "symeig: m = %d > %d", m, MAXM);
+    hipStream_t st = ctx->stream;
+    double* M = scratch;
+    double* tri = M + (size_t)m * m;
+    int* info = reinterpret_cast<int*>(tri + 3 * MAXM + 8);
+    double* lu = tri + 3 * MAXM + 8 + (MAXM + 64) / 2;
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)ceil_div((int64_t)m * m, 256)), dim3(256), 0, st,
+                       (int64_t)m * m, A, M);
+    hipLaunchKernelGGL(k_set_info, dim3(1), dim3(64), 0, st, info, m);
+    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, info, M, tri);
+    eig_pipeline(st, k, info, M, tri, w, V, lu);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }
@@ -554,7 +680,7 @@ extern "C" sc_status sc_symeig_workspace(sc_ctx* ctx, int m, int k, size_t* byte
     if (!ctx || !bytes) return SC_E_INVAL;
     if (m <= 0 || k <= 0 || k > m || m > MAXM)
         return sc_fail(ctx, SC_E_INVAL, "symeig: need 0 < k <= m <= %d", MAXM);
-    *bytes = (symeig_scratch_elems(m, k) + (size_t)m * m) * sizeof(double) + 256;
+    *bytes = symeig_scratch_elems(m, k) * sizeof(double) + 256;
     return SC_OK;
 }
 

@@ -126,11 +126,13 @@ sc_status launch_spmm(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, const int3
 // BF16 and accumulates in FP32 on the matrix cores.
 struct GramPlan {
     int64_t n;
-    int c;          // columns of A and B (square Gram)
-    int chunks;     // row chunks (split-K)
-    int tiles;      // 64-wide tiles per side
+    int c;              // columns of A and B (square Gram)
+    int chunks;         // row chunks (split-K)
+    int64_t chunk_rows; // rows per chunk (multiple of 32)
+    int bt;             // workgroup output tile edge
+    int tiles;          // tiles per side
 };
-GramPlan gram_plan(int64_t n, int c);
+GramPlan gram_plan(int64_t n, int c, int elem_bytes);
 size_t gram_partial_elems(const GramPlan& p, int nout);
 template <class T>
 sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, const T* B1,
