@@ -155,6 +155,11 @@ typedef struct {
     int p_drops;           /* iterations in which the P block was dropped */
     int locked_cols;       /* W columns excluded in the last iteration */
     double max_relres;     /* of the returned block */
+    int w_drops;           /* W columns left out as numerically dependent
+                              (reduced-precision modes; always 0 in FP64) */
+    int gram_fallbacks;    /* iterations whose Gram matrices were recomputed with
+                              FP64 accumulation (reduced-precision modes) */
+    int restarts;          /* explicit restarts (reduced-precision modes) */
 } sc_lobpcg_info;
 
 sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobpcg_opts* opts,
@@ -171,6 +176,20 @@ sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobp
  *     FP64 (Cholesky of S'S; on failure P is dropped and the step redone);
  *     P <- [W P] C_WP, X <- X C_X + P (and the same for LX, LP).
  * Every CholQR equilibrates the columns before the Cholesky.
+ * Reduced precision (FP32, FP32_BF16GRAM): a W column whose CholQR pivot
+ * fails, or whose pivot in the Cholesky of S'S fails once P is out, is left
+ * out of the basis for that iteration (info.w_drops) instead of ending the
+ * solve.  The Gram matrices S'LS, S'S of an iteration are computed with
+ * FP32 accumulation (FP32_BF16GRAM: from BF16-rounded inputs) and S'S is
+ * first factored with a relative pivot floor matched to that rounding (1e-4
+ * for FP32, 2^-5 for BF16); where it fails, both are recomputed from the
+ * FP32 data widened to FP64 (exact products, FP64 accumulation) and the
+ * ordinary Rayleigh-Ritz runs on those (info.gram_fallbacks).  An iterate
+ * whose Ritz values leave [0, 2] by more than 1e-3, or with a relres above 1
+ * (impossible while LX = L X holds), shows that the recurrence for LX has
+ * drifted: it is not accepted as converged, and the next iteration restarts
+ * explicitly (X <- CholQR2(X), LX = L X, Rayleigh-Ritz on span(X), P
+ * emptied; info.restarts).  It counts as an iteration.
  *   val     float64 [nnz] (prec FP64) or float32 [nnz] (other precisions)
  *   X0      n x ldx start block (float64 for FP64, float32 otherwise); must
  *           have full column rank and finite entries
@@ -181,9 +200,9 @@ sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobp
  *   info    host, out
  * Synchronises once per iteration (convergence test).
  * Errors: SC_E_INVAL (sizes), SC_E_UNSUPPORTED (k > 256), SC_E_NUMERIC (NaN
- * or Inf in X0 or a residual), SC_E_BREAKDOWN (rank-deficient X0 or W, or
- * S'S not positive definite even without P).  On SC_E_BREAKDOWN X_out is
- * not written.
+ * or Inf in X0 or a residual), SC_E_BREAKDOWN (rank-deficient X0; in FP64
+ * also a rank-deficient W, or S'S not positive definite even without P).
+ * On SC_E_BREAKDOWN X_out is not written.
  */
 sc_status sc_lobpcg_solve(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                           const int32_t* col, const void* val, const sc_lobpcg_opts* opts,
@@ -199,11 +218,21 @@ sc_status sc_lobpcg_solve(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* ro
  *          Synchronises (convergence test).
  *   end:   writes X_out, theta and info.  Synchronises. */
 typedef struct sc_lobpcg_state sc_lobpcg_state;
+/* step_async: enqueues one iteration (and the copy of its convergence flags
+ *          to pinned host memory owned by the state) without waiting; at most
+ *          one iteration per state is in flight.
+ * step_poll: non-blocking; *ready = 0 while the enqueued iteration runs;
+ *          once it has finished, processes its flags (errors are reported
+ *          here) and sets *ready = 1 and *done.
+ * Several states, each on its own context and stream, can be in flight at
+ * once: their kernels overlap on the device. */
 sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                           const int32_t* col, const void* val, const sc_lobpcg_opts* opts,
                           const void* X0, void* ws, size_t ws_bytes, sc_lobpcg_state** state,
                           int* done);
 sc_status sc_lobpcg_step(sc_ctx* ctx, sc_lobpcg_state* state, int* done);
+sc_status sc_lobpcg_step_async(sc_ctx* ctx, sc_lobpcg_state* state);
+sc_status sc_lobpcg_step_poll(sc_ctx* ctx, sc_lobpcg_state* state, int* ready, int* done);
 sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* state, void* X_out, double* theta,
                         double* relres_hist, sc_lobpcg_info* info);
 

@@ -35,7 +35,8 @@ class sc_lobpcg_opts(C.Structure):
 
 class sc_lobpcg_info(C.Structure):
     _fields_ = [("iterations", _int), ("converged", _int), ("p_drops", _int),
-                ("locked_cols", _int), ("max_relres", _dbl)]
+                ("locked_cols", _int), ("max_relres", _dbl), ("w_drops", _int),
+                ("gram_fallbacks", _int), ("restarts", _int)]
 
 
 class sc_kmeans_opts(C.Structure):
@@ -66,6 +67,8 @@ SIGNATURES = {
     "sc_lobpcg_begin": (_int, [_p, _i64, _i64, _p, _p, _p, C.POINTER(sc_lobpcg_opts), _p, _p,
                                _size, C.POINTER(_p), C.POINTER(_int)]),
     "sc_lobpcg_step": (_int, [_p, _p, C.POINTER(_int)]),
+    "sc_lobpcg_step_async": (_int, [_p, _p]),
+    "sc_lobpcg_step_poll": (_int, [_p, _p, C.POINTER(_int), C.POINTER(_int)]),
     "sc_lobpcg_end": (_int, [_p, _p, _p, _p, _p, C.POINTER(sc_lobpcg_info)]),
     "sc_kmeans_workspace": (_int, [_p, _i64, _int, C.POINTER(sc_kmeans_opts), C.POINTER(_size)]),
     "sc_kmeans_assign": (_int, [_p, _i64, _int, _p, _i64, C.POINTER(sc_kmeans_opts), _p, _p, _p,

@@ -88,12 +88,14 @@ class DeviceCSR:
 
 
 def graph_build(ctx: Context, n: int, src: torch.Tensor, dst: torch.Tensor,
-                w: torch.Tensor | None = None, algebraic: bool = False) -> DeviceCSR:
+                w: torch.Tensor | None = None, algebraic: bool = False,
+                ws: torch.Tensor | None = None) -> DeviceCSR:
     dev = src.device
     m = int(src.numel())
     nb = C.c_size_t()
     ctx.check(lib().sc_graph_build_workspace(ctx.handle, n, m, C.byref(nb)), "sc_graph_build_workspace")
-    ws = ctx.workspace(nb.value)
+    if ws is None or ws.numel() < nb.value:
+        ws = ctx.workspace(nb.value)
     row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
     col = torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev)
     w_sym = torch.empty(max(2 * m, 1), dtype=torch.float64, device=dev) if algebraic else None
@@ -144,6 +146,9 @@ class LobpcgResult:
     p_drops: int
     locked_cols: int
     max_relres: float
+    w_drops: int = 0
+    gram_fallbacks: int = 0
+    restarts: int = 0
 
 
 def lobpcg_opts(k, maxit, tol, precision, ldx, lock_tol=0.0, chol_tol=0.0):
@@ -178,7 +183,8 @@ def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor
                                     C.byref(info), _ptr(ws), nb), "sc_lobpcg_solve")
     it = info.iterations
     return LobpcgResult(X_out, theta, None if hist is None else hist.reshape(maxit + 1, k)[: it + 1],
-                        it, bool(info.converged), info.p_drops, info.locked_cols, info.max_relres)
+                        it, bool(info.converged), info.p_drops, info.locked_cols, info.max_relres,
+                        info.w_drops, info.gram_fallbacks, info.restarts)
 
 
 def lobpcg_status(ctx: Context, g: DeviceCSR, val, X0, maxit, tol=0.0, precision="fp64") -> int:
@@ -237,11 +243,12 @@ def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.T
     return KmeansResult(labels, cent, inertia.value, iq.value, br.value)
 
 
-def symeig(ctx: Context, A: torch.Tensor, k: int):
+def symeig(ctx: Context, A: torch.Tensor, k: int, ws: torch.Tensor | None = None):
     m = A.shape[0]
     nb = C.c_size_t()
     ctx.check(lib().sc_symeig_workspace(ctx.handle, m, k, C.byref(nb)), "sc_symeig_workspace")
-    ws = ctx.workspace(nb.value)
+    if ws is None or ws.numel() < nb.value:
+        ws = ctx.workspace(nb.value)
     w = torch.empty(k, dtype=torch.float64, device=A.device)
     V = torch.empty((m, k), dtype=torch.float64, device=A.device)
     ctx.check(lib().sc_symeig(ctx.handle, m, k, _ptr(A), _ptr(w), _ptr(V), _ptr(ws), nb.value),

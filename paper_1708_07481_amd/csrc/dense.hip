@@ -21,6 +21,7 @@ namespace {
 //   float : v_mfma_f32_16x16x4_f32   (FP32 in, FP32 accumulate)
 //   double: v_mfma_f64_16x16x4_f64   (FP64 in, FP64 accumulate)
 //   bf16  : v_mfma_f32_16x16x32_bf16 (FP32 in, rounded to BF16 (RNE), FP32 accumulate)
+//   f32x64: v_mfma_f64_16x16x4_f64   (FP32 in, widened: exact products, FP64 accumulate)
 // ---------------------------------------------------------------------------
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 typedef double mf_d4 __attribute__((ext_vector_type(4)));
@@ -64,6 +65,22 @@ struct MfF64 {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
 };
+struct MfF32x64 {
+    using in_t = float;
+    using acc_t = mf_d4;
+    using frag_t = double;
+    static constexpr int KR = 4;
+    static constexpr int WT = 2;
+    __device__ static int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    __device__ static frag_t load(const float* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
+                                  int col, int c, int lane) {
+        const int64_t r = r0 + (lane >> 4);
+        return (r < r1 && col < c) ? (double)M[r * ld + col] : 0.0;
+    }
+    __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+};
 struct MfBF16 {
     using in_t = float;
     using acc_t = mf_f4;
@@ -92,7 +109,8 @@ __global__ void __launch_bounds__(256)
 k_gram_mfma(int64_t n, int c, int64_t chunk_rows, const typename MF::in_t* __restrict__ A, int64_t lda,
             const typename MF::in_t* __restrict__ B1, int64_t ldb1,
             const typename MF::in_t* __restrict__ B2, int64_t ldb2, double* __restrict__ partial,
-            int tiles) {
+            int tiles, const int* __restrict__ pred) {
+    if (pred && *pred == 0) return;
     constexpr int WT = MF::WT;
     constexpr int WTILE = 16 * WT;          // wave tile edge
     constexpr int BT = 2 * WTILE;           // workgroup tile edge
@@ -155,7 +173,9 @@ k_gram_mfma(int64_t n, int c, int64_t chunk_rows, const typename MF::in_t* __res
 
 // sum the chunk partials in chunk order; upper entries, mirrored
 __global__ void k_gram_reduce(int c, int chunks, int nout, const double* __restrict__ partial,
-                              double* __restrict__ G1, double* __restrict__ G2) {
+                              double* __restrict__ G1, double* __restrict__ G2,
+                              const int* __restrict__ pred) {
+    if (pred && *pred == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t cc2 = (int64_t)c * c;
     if (e >= cc2) return;
@@ -174,58 +194,78 @@ __global__ void k_gram_reduce(int c, int chunks, int nout, const double* __restr
 // Cholesky QR factor of a small Gram matrix (one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int CQ_TH = 256;
+// Ritz values further than this outside [0, 2] mark an inconsistent iterate
+constexpr double RESTART_THETA_SLACK = 1e-3;
 constexpr int CQ_MAX = 256;
 
 __global__ void __launch_bounds__(CQ_TH)
 k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, double tol,
                 double* __restrict__ T64, float* __restrict__ T32, double* __restrict__ scr,
-                int drop_on_fail, int require_all, int* status, int* counter) {
+                int mode, int* status, int* counter) {
     __shared__ int idx[CQ_MAX];
     __shared__ double d[CQ_MAX];
-    __shared__ int m_s, fail_s;
+    __shared__ int m_s, fail_s, fail_at;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        int m = 0, missing = 0;
-        for (int j = 0; j < c; ++j) {
-            const double g = G[(int64_t)j * c + j];
-            if (mask[j] && isfinite(g) && g > 0.0) {
-                idx[m] = j;
-                d[m] = sqrt(g);
-                ++m;
-            } else {
-                if (mask[j]) missing = 1;
-                mask[j] = 0;
-            }
-        }
-        m_s = m;
-        fail_s = (require_all && missing) ? 1 : 0;
-    }
-    __syncthreads();
-    const int m = m_s;
+    int m = 0;
     double* Gs = scr;                    // m x m equilibrated Gram
-    double* R = scr + (int64_t)m * m;    // m x m upper factor
-    double* Ri = R + (int64_t)m * m;     // m x m inverse
-    for (int e = tid; e < m * m; e += CQ_TH) {
-        const int a = e / m, b = e % m;
-        Gs[e] = G[(int64_t)idx[a] * c + idx[b]] / (d[a] * d[b]);
-        R[e] = 0.0;
-        Ri[e] = 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < m && !fail_s; ++j) {
+    double* R = nullptr;                 // m x m upper factor
+    double* Ri = nullptr;                // m x m inverse
+    // CQ_DROP_DEPENDENT removes one failing column per pass and refactors
+    for (int pass = 0; pass <= c; ++pass) {
         if (tid == 0) {
-            double s = Gs[(int64_t)j * m + j];
-            for (int l = 0; l < j; ++l) s = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + j], s);
-            if (!isfinite(s) || !(s > tol * Gs[(int64_t)j * m + j]) || !(s > 0.0)) fail_s = 1;
-            else R[(int64_t)j * m + j] = sqrt(s);
+            int mm = 0, missing = 0;
+            for (int j = 0; j < c; ++j) {
+                const double g = G[(int64_t)j * c + j];
+                if (mask[j] && isfinite(g) && g > 0.0) {
+                    idx[mm] = j;
+                    d[mm] = sqrt(g);
+                    ++mm;
+                } else {
+                    if (mask[j]) missing = 1;
+                    mask[j] = 0;
+                }
+            }
+            m_s = mm;
+            fail_s = (mode == CQ_REQUIRE_ALL && missing) ? 1 : 0;
+            fail_at = -1;
         }
         __syncthreads();
-        if (fail_s) break;
-        const double rjj = R[(int64_t)j * m + j];
-        for (int b = j + 1 + tid; b < m; b += CQ_TH) {
-            double t = Gs[(int64_t)j * m + b];
-            for (int l = 0; l < j; ++l) t = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + b], t);
-            R[(int64_t)j * m + b] = t / rjj;
+        m = m_s;
+        R = scr + (int64_t)m * m;
+        Ri = R + (int64_t)m * m;
+        for (int e = tid; e < m * m; e += CQ_TH) {
+            const int a = e / m, b = e % m;
+            Gs[e] = G[(int64_t)idx[a] * c + idx[b]] / (d[a] * d[b]);
+            R[e] = 0.0;
+            Ri[e] = 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < m && !fail_s; ++j) {
+            if (tid == 0) {
+                double s = Gs[(int64_t)j * m + j];
+                for (int l = 0; l < j; ++l) s = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + j], s);
+                if (!isfinite(s) || !(s > tol * Gs[(int64_t)j * m + j]) || !(s > 0.0)) {
+                    fail_s = 1;
+                    fail_at = j;
+                } else {
+                    R[(int64_t)j * m + j] = sqrt(s);
+                }
+            }
+            __syncthreads();
+            if (fail_s) break;
+            const double rjj = R[(int64_t)j * m + j];
+            for (int b = j + 1 + tid; b < m; b += CQ_TH) {
+                double t = Gs[(int64_t)j * m + b];
+                for (int l = 0; l < j; ++l) t = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + b], t);
+                R[(int64_t)j * m + b] = t / rjj;
+            }
+            __syncthreads();
+        }
+        if (!fail_s || mode != CQ_DROP_DEPENDENT) break;
+        // the failing column is (numerically) in the span of the earlier ones
+        if (tid == 0) {
+            mask[idx[fail_at]] = 0;
+            if (counter) atomicAdd(counter, 1);
         }
         __syncthreads();
     }
@@ -235,7 +275,7 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
             T32[e] = 0.0f;
         }
         if (tid == 0) {
-            if (drop_on_fail) {
+            if (mode == CQ_DROP_ALL) {
                 for (int j = 0; j < c; ++j) mask[j] = 0;
                 atomicOr(status, DEV_P_DROPPED);
                 if (counter) atomicAdd(counter, 1);
@@ -392,11 +432,14 @@ k_residual(int64_t n, int kp, int k, T* __restrict__ S, const T* __restrict__ LS
 __global__ void __launch_bounds__(256)
 k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ partial, double lock_tol,
                     double* __restrict__ relres, double* __restrict__ hist_row, int* __restrict__ wmask,
-                    int* status, double* out_max, int* out_all_locked) {
+                    int* status, double* out_max, int* out_all_locked,
+                    const double* __restrict__ theta, int* __restrict__ out_restart) {
     __shared__ double mx[256];
     __shared__ int locked_all[256];
+    __shared__ int bad[256];
     double my_max = 0.0;
     int my_all = 1;
+    int my_bad = 0;
     for (int j = threadIdx.x; j < kp; j += 256) {
         double rr = 0.0, xx = 0.0;
         for (int b = 0; b < nblocks; ++b) {
@@ -410,6 +453,13 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
             if (hist_row) hist_row[j] = rel;
             const int active = rel > lock_tol;
             wmask[j] = active;
+            // a consistent iterate has theta in [0, 2] (spectrum of L) and
+            // ||Lx - theta x|| <= 2 ||x||, i.e. relres <= 1
+            if (out_restart) {
+                const double th = theta[j];
+                if (!(th >= -RESTART_THETA_SLACK && th <= 2.0 + RESTART_THETA_SLACK) || rel > 1.0)
+                    my_bad = 1;
+            }
             my_all &= !active;
             my_max = fmax(my_max, rel);
         } else {
@@ -419,16 +469,19 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
     }
     mx[threadIdx.x] = my_max;
     locked_all[threadIdx.x] = my_all;
+    bad[threadIdx.x] = my_bad;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = 0.0;
-        int a = 1;
+        int a = 1, b = 0;
         for (int t = 0; t < 256; ++t) {
             m = fmax(m, mx[t]);
             a &= locked_all[t];
+            b |= bad[t];
         }
         *out_max = m;
         *out_all_locked = a;
+        if (out_restart) *out_restart = b;
     }
 }
 
@@ -437,12 +490,13 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-GramPlan gram_plan(int64_t n, int c, int elem_bytes) {
+GramPlan gram_plan(int64_t n, int c, int gmode_bytes) {
     GramPlan p;
     p.n = n;
     p.c = c;
-    // workgroup tile edge: 128 (FP32 / BF16 matrix-core path), 64 (FP64)
-    p.bt = elem_bytes == 8 ? 64 : 128;
+    // workgroup tile edge: 128 (FP32 / BF16 matrix-core path), 64 (FP64
+    // accumulation: FP64 data, or FP32 data widened)
+    p.bt = gmode_bytes == 8 ? 64 : 128;
     p.tiles = (int)ceil_div(c, p.bt);
     const int upper = p.tiles * (p.tiles + 1) / 2;
     // enough workgroups to fill 256 CUs several times, each chunk >= 512 rows
@@ -458,55 +512,57 @@ size_t gram_partial_elems(const GramPlan& p, int nout) {
     return (size_t)p.chunks * nout * (size_t)p.c * p.c;
 }
 
+template <class MF>
+static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, int64_t lda,
+                    const typename MF::in_t* B1, int64_t ldb1, const typename MF::in_t* B2,
+                    int64_t ldb2, double* partial, const int* pred) {
+    const int upper = p.tiles * (p.tiles + 1) / 2;
+    dim3 grid(upper, p.chunks);
+    if (B2)
+        hipLaunchKernelGGL((k_gram_mfma<MF, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                           p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles, pred);
+    else
+        hipLaunchKernelGGL((k_gram_mfma<MF, false>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                           p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles, pred);
+}
+
 template <class T>
 sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, const T* B1,
                       int64_t ldb1, const T* B2, int64_t ldb2, double* partial, double* G1,
-                      double* G2, int bf16) {
-    const int upper = p.tiles * (p.tiles + 1) / 2;
-    dim3 grid(upper, p.chunks);
+                      double* G2, int gmode, const int* pred) {
     if constexpr (sizeof(T) == 8) {
-        if (B2)
-            hipLaunchKernelGGL((k_gram_mfma<MfF64, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
-        else
-            hipLaunchKernelGGL((k_gram_mfma<MfF64, false>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                               p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
-    } else if (bf16) {
-        if (B2)
-            hipLaunchKernelGGL((k_gram_mfma<MfBF16, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
-        else
-            hipLaunchKernelGGL((k_gram_mfma<MfBF16, false>), grid, dim3(256), 0, ctx->stream, p.n,
-                               p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+        gram_go<MfF64>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
     } else {
-        if (B2)
-            hipLaunchKernelGGL((k_gram_mfma<MfF32, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                               p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles);
+        const int bt = gmode == GRAM_F32_EXACT ? 64 : 128;
+        if (p.bt != bt) return sc_fail(ctx, SC_E_INVAL, "gram: plan tile %d, kernel tile %d", p.bt, bt);
+        if (gmode == GRAM_BF16)
+            gram_go<MfBF16>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
+        else if (gmode == GRAM_F32_EXACT)
+            gram_go<MfF32x64>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
         else
-            hipLaunchKernelGGL((k_gram_mfma<MfF32, false>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                               p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles);
+            gram_go<MfF32>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
     }
     SC_CHECK_LAUNCH(ctx);
     const int64_t cc2 = (int64_t)p.c * p.c;
     hipLaunchKernelGGL(k_gram_reduce, dim3(ceil_div(cc2, 256)), dim3(256), 0, ctx->stream, p.c,
-                       p.chunks, B2 ? 2 : 1, partial, G1, G2);
+                       p.chunks, B2 ? 2 : 1, partial, G1, G2, pred);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }
 
 template sc_status launch_gram<double>(sc_ctx*, const GramPlan&, const double*, int64_t,
                                        const double*, int64_t, const double*, int64_t, double*,
-                                       double*, double*, int);
+                                       double*, double*, int, const int*);
 template sc_status launch_gram<float>(sc_ctx*, const GramPlan&, const float*, int64_t,
                                       const float*, int64_t, const float*, int64_t, double*,
-                                      double*, double*, int);
+                                      double*, double*, int, const int*);
 
 sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, double tol,
-                               double* T64, float* T32, double* scratch, int drop_on_fail,
+                               double* T64, float* T32, double* scratch, int mode,
                                int* status, int* counter) {
     if (c > CQ_MAX) return sc_fail(ctx, SC_E_UNSUPPORTED, "cholqr: %d columns > %d", c, CQ_MAX);
     hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(CQ_TH), 0, ctx->stream, c, G, mask, tol, T64,
-                       T32, scratch, drop_on_fail, drop_on_fail ? 0 : 1, status, counter);
+                       T32, scratch, mode, status, counter);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }
@@ -583,10 +639,11 @@ template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, float*, co
 
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, const double* partial,
                                    double lock_tol, double* relres, double* hist_row, int* wmask,
-                                   int* status, double* out_max, int* out_all_locked) {
+                                   int* status, double* out_max, int* out_all_locked,
+                                   const double* theta, int* out_restart) {
     hipLaunchKernelGGL(k_residual_finalize, dim3(1), dim3(256), 0, ctx->stream, nblocks, kp, k,
                        partial, lock_tol, relres, hist_row, wmask, status, out_max,
-                       out_all_locked);
+                       out_all_locked, theta, out_restart);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }

@@ -7,6 +7,7 @@
 // Workspace layout: S = [X W P] and LS = [LX LW LP], each n x 3kp row-major
 // (kp = k rounded up to a multiple of 4; pad columns stay zero), the Gram
 // matrices, the small factors, and the per-iteration residual history.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -69,15 +70,30 @@ struct sc_lobpcg_state {
     double *GA, *GB, *Gpart, *Gw, *Gwpart, *T64, *C64, *theta, *relres, *res_part, *cq_scr,
         *rr_scr, *hist, *out_max;
     float *T32, *C32;
-    int *act, *status, *pdrops, *all_locked;
-    GramPlan plan3{}, plank{};
+    // status block (8 ints): [0] flags, [1] P drops, [2] all columns locked,
+    // [3] W columns dropped as dependent, [4] Gram recomputations with FP64
+    // accumulation, [5] Gram-precision probe flag of the current iteration,
+    // [6] inconsistent-iterate flag of the last residual
+    int *act, *status, *pdrops, *all_locked, *wdrops, *gram_fallbacks, *gflag, *restart_flag;
+    GramPlan plan3{}, plan3x{}, plank{};
     int res_blocks = 0;
     // progress
     int t = 0;
     int has_p = 0;
     int converged = 0;
     int done = 0;
+    int need_restart = 0;
+    int restarts = 0;
     double max_relres = 0.0;
+    // asynchronous iteration: convergence flags land in `readback` (pinned
+    // host memory of this solve); `ready` is recorded after the copy
+    char* readback = nullptr;
+    hipEvent_t ready = nullptr;
+    int in_flight = 0;
+    ~sc_lobpcg_state() {
+        if (ready) (void)hipEventDestroy(ready);
+        if (readback) (void)hipHostFree(readback);
+    }
 };
 
 static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, sc_lobpcg_state& s) {
@@ -89,10 +105,12 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.S = c.take<char>((size_t)n * K3 * es);
     s.LS = c.take<char>((size_t)n * K3 * es);
     s.plan3 = gram_plan(n, K3, (int)es);
+    s.plan3x = gram_plan(n, K3, 8);          // FP32 data widened to FP64 (fallback)
     s.plank = gram_plan(n, kp, (int)es);
     s.GA = c.take<double>((size_t)K3 * K3);
     s.GB = c.take<double>((size_t)K3 * K3);
-    s.Gpart = c.take<double>(gram_partial_elems(s.plan3, 2));
+    s.Gpart = c.take<double>(std::max(gram_partial_elems(s.plan3, 2),
+                                      gram_partial_elems(s.plan3x, 2)));
     s.Gw = c.take<double>((size_t)kp * kp);
     s.Gwpart = c.take<double>(gram_partial_elems(s.plank, 1));
     s.T64 = c.take<double>((size_t)kp * kp);
@@ -108,9 +126,13 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.hist = c.take<double>((size_t)(maxit + 1) * kp);
     s.out_max = c.take<double>(1);
     s.act = c.take<int>(K3);
-    s.status = c.take<int>(4);
+    s.status = c.take<int>(8);
     s.pdrops = s.status + 1;
     s.all_locked = s.status + 2;
+    s.wdrops = s.status + 3;
+    s.gram_fallbacks = s.status + 4;
+    s.gflag = s.status + 5;
+    s.restart_flag = s.status + 6;
     return c.size();
 }
 
@@ -140,6 +162,14 @@ extern "C" sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz,
 
 namespace {
 
+// Relative pivot floors for the Cholesky factor of a basis Gram matrix
+// computed from BF16-rounded inputs (eight BF16 unit roundoffs, 2^-8 each)
+// or with FP32 accumulation (about fifty times the accumulated FP32 rounding
+// of a row chunk).  Below them a pivot is not resolved by the Gram matrix's
+// own rounding error.
+constexpr double BF16_PIVOT_TOL = 1.0 / 32.0;
+constexpr double FP32_PIVOT_TOL = 1e-4;
+
 template <class T>
 struct Solver {
     static T* S(sc_lobpcg_state* s) { return static_cast<T*>(s->S); }
@@ -147,30 +177,64 @@ struct Solver {
     static const T* val(sc_lobpcg_state* s) { return static_cast<const T*>(s->val); }
 
     // W/X/P block CholQR with mask `m` (kp columns at column offset `off`)
-    static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int drop) {
+    static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int mode,
+                            int* counter) {
         const int64_t ld = s->K3;
         T* V = S(s) + off;
         ProfScope ps(ctx, SC_KIND_CHOLQR);
-        SC_TRY(launch_gram<T>(ctx, s->plank, V, ld, V, ld, nullptr, 0, s->Gwpart, s->Gw, nullptr, 0));
+        SC_TRY(launch_gram<T>(ctx, s->plank, V, ld, V, ld, nullptr, 0, s->Gwpart, s->Gw, nullptr,
+                              GRAM_NATIVE));
         SC_TRY(launch_cholqr_factor(ctx, s->kp, s->Gw, s->act + off, s->chol_tol, s->T64, s->T32,
-                                    s->cq_scr, drop, s->status, drop ? s->pdrops : nullptr));
+                                    s->cq_scr, mode, s->status, counter));
         SC_TRY(launch_apply_right<T>(ctx, s->n, s->kp, V, ld, with_L ? LS(s) + off : nullptr, ld,
                                      s->T64, s->T32));
         return SC_OK;
     }
 
+    // G_A = S'LS, G_B = S'S, Rayleigh-Ritz, block update.
+    // FP64: Gram in FP64, the Rayleigh-Ritz rules of the plain method.
+    // FP32 / FP32_BF16GRAM: the Gram matrices come from FP32 (or BF16-rounded)
+    // data with FP32 accumulation; the set-up first probes S'S with a pivot
+    // floor matched to that rounding.  Where the basis is too ill-conditioned
+    // for it, S'LS and S'S of this iteration are recomputed from the same data
+    // widened to FP64 (exact products, FP64 accumulation) and the ordinary
+    // set-up (P-drop rule, dependent W columns left out) runs on those.  The
+    // recomputation is predicated on a device flag: no host round trip.
     static sc_status rr_and_update(sc_ctx* ctx, sc_lobpcg_state* s) {
         const int64_t ld = s->K3;
-        const int bf16 = s->prec == SC_PREC_FP32_BF16GRAM;
-        {
-            ProfScope ps(ctx, SC_KIND_GRAM);
-            SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
-                                  s->GB, bf16));
-        }
-        {
+        if (s->prec == SC_PREC_FP64) {
+            {
+                ProfScope ps(ctx, SC_KIND_GRAM);
+                SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
+                                      s->GB, GRAM_NATIVE));
+            }
             ProfScope ps(ctx, SC_KIND_RR);
             SC_TRY(launch_rayleigh_ritz(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
-                                        s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops));
+                                        s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops,
+                                        nullptr));
+        } else {
+            const int bf16 = s->prec == SC_PREC_FP32_BF16GRAM;
+            {
+                ProfScope ps(ctx, SC_KIND_GRAM);
+                SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
+                                      s->GB, bf16 ? GRAM_BF16 : GRAM_NATIVE));
+            }
+            {
+                ProfScope ps(ctx, SC_KIND_RR);
+                SC_TRY(launch_rr_setup(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act,
+                                       bf16 ? BF16_PIVOT_TOL : FP32_PIVOT_TOL, s->rr_scr, s->status,
+                                       s->pdrops, nullptr, s->gflag, s->gram_fallbacks, nullptr));
+            }
+            {
+                ProfScope ps(ctx, SC_KIND_GRAM);
+                SC_TRY(launch_gram<T>(ctx, s->plan3x, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
+                                      s->GB, GRAM_F32_EXACT, s->gflag));
+            }
+            ProfScope ps(ctx, SC_KIND_RR);
+            SC_TRY(launch_rr_setup(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
+                                   s->rr_scr, s->status, s->pdrops, s->gflag, nullptr, nullptr,
+                                   s->wdrops));
+            SC_TRY(launch_rr_solve(ctx, s->K3, s->kp, s->k, s->C64, s->C32, s->theta, s->rr_scr));
         }
         ProfScope ps(ctx, SC_KIND_UPDATE);
         SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, S(s), ld, s->C64, s->C32));
@@ -178,8 +242,9 @@ struct Solver {
         return SC_OK;
     }
 
-    // residual of the current iterate, history row t, W mask; one sync
-    static sc_status residual(sc_ctx* ctx, sc_lobpcg_state* s) {
+    // residual of the current iterate, history row t, W mask, and the copy of
+    // the convergence flags to the solve's pinned readback buffer
+    static sc_status residual_enqueue(sc_ctx* ctx, sc_lobpcg_state* s) {
         int nb = 0;
         {
             ProfScope ps(ctx, SC_KIND_RESIDUAL);
@@ -188,27 +253,51 @@ struct Solver {
             SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->lock_tol,
                                             s->relres, s->hist + (int64_t)s->t * s->kp,
                                             s->act + s->kp, s->status, s->out_max,
-                                            s->all_locked));
+                                            s->all_locked, s->theta,
+                                            s->prec == SC_PREC_FP64 ? nullptr : s->restart_flag));
         }
-        char* h = static_cast<char*>(ctx->stage);
-        SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, 4 * sizeof(int), hipMemcpyDeviceToHost,
+        char* h = s->readback;
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, 8 * sizeof(int), hipMemcpyDeviceToHost,
                                          ctx->stream));
-        SC_CHECK_HIP(ctx, hipMemcpyAsync(h + 16, s->out_max, sizeof(double), hipMemcpyDeviceToHost,
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(h + 32, s->out_max, sizeof(double), hipMemcpyDeviceToHost,
                                          ctx->stream));
-        SC_CHECK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        SC_CHECK_HIP(ctx, hipEventRecord(s->ready, ctx->stream));
+        s->in_flight = 1;
+        return SC_OK;
+    }
+
+    // the readback has landed: convergence test and error flags
+    static sc_status residual_process(sc_ctx* ctx, sc_lobpcg_state* s) {
+        s->in_flight = 0;
         prof_drain(ctx, false);
-        const int* st = reinterpret_cast<const int*>(h);
+        const char* h = s->readback;
+        int st[8];
+        memcpy(st, h, sizeof st);
         if (st[0] & DEV_BREAKDOWN)
             return sc_fail(ctx, SC_E_BREAKDOWN,
-                           "lobpcg: Cholesky breakdown (rank-deficient block or Gram matrix)");
+                           "lobpcg: Cholesky QR breakdown (rank-deficient X or W block) at "
+                           "iteration %d", s->t);
+        if (st[0] & DEV_BREAKDOWN_RR)
+            return sc_fail(ctx, SC_E_BREAKDOWN,
+                           "lobpcg: Rayleigh-Ritz breakdown (basis Gram matrix not positive "
+                           "definite without P) at iteration %d", s->t);
         if (st[0] & DEV_NUMERIC)
             return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in a residual");
         double mx;
-        memcpy(&mx, h + 16, sizeof(double));
+        memcpy(&mx, h + 32, sizeof(double));
         s->max_relres = mx;
-        s->converged = (mx <= s->tol) || st[2];
+        // reduced precision: an inconsistent iterate (LX drifted from L X) is
+        // never reported as converged; the next iteration restarts from X
+        s->need_restart = s->prec != SC_PREC_FP64 && st[6] != 0;
+        s->converged = !s->need_restart && ((mx <= s->tol) || st[2]);
         s->done = s->converged || s->t >= s->maxit;
         return SC_OK;
+    }
+
+    static sc_status residual(sc_ctx* ctx, sc_lobpcg_state* s) {
+        SC_TRY(residual_enqueue(ctx, s));
+        SC_CHECK_HIP(ctx, hipEventSynchronize(s->ready));
+        return residual_process(ctx, s);
     }
 
     static sc_status begin(sc_ctx* ctx, sc_lobpcg_state* s, const void* X0) {
@@ -217,7 +306,7 @@ struct Solver {
         const int64_t words = (int64_t)s->n * s->K3 * (int64_t)sizeof(T) / 4;
         hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->S, words);
         hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->LS, words);
-        hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->status, (int64_t)4);
+        hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->status, (int64_t)8);
         SC_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL((k_load_block<T, T>), dim3(ceil_div(s->n * s->kp, 256)), dim3(256), 0, st,
                            s->n, s->k, s->kp, static_cast<const T*>(X0), s->ldx, S(s), ld, s->status);
@@ -231,7 +320,7 @@ struct Solver {
         // X <- CholQR2(X0)
         for (int rep = 0; rep < 2; ++rep) {
             hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->kp, s->k);
-            SC_TRY(cholqr(ctx, s, 0, 0, 0));
+            SC_TRY(cholqr(ctx, s, 0, 0, CQ_REQUIRE_ALL, nullptr));
         }
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
@@ -248,13 +337,49 @@ struct Solver {
     }
 
     static sc_status step(sc_ctx* ctx, sc_lobpcg_state* s) {
+        SC_TRY(step_enqueue(ctx, s));
+        SC_CHECK_HIP(ctx, hipEventSynchronize(s->ready));
+        return residual_process(ctx, s);
+    }
+
+    // explicit restart: X <- CholQR2(X), LX = L X (a fresh product instead of
+    // the recurrence), Rayleigh-Ritz on span(X) alone, P emptied
+    static sc_status restart_enqueue(sc_ctx* ctx, sc_lobpcg_state* s) {
+        hipStream_t st = ctx->stream;
+        const int64_t ld = s->K3;
+        s->need_restart = 0;
+        s->restarts += 1;
+        for (int rep = 0; rep < 2; ++rep) {
+            hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->kp, s->k);
+            SC_TRY(cholqr(ctx, s, 0, 0, CQ_REQUIRE_ALL, nullptr));
+        }
+        {
+            ProfScope ps(ctx, SC_KIND_SPMM);
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+        }
+        hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
+        SC_CHECK_LAUNCH(ctx);
+        SC_TRY(rr_and_update(ctx, s));
+        s->has_p = 0;
+        s->t += 1;
+        return residual_enqueue(ctx, s);
+    }
+
+    // one iteration enqueued on the context's stream, ending with the readback
+    static sc_status step_enqueue(sc_ctx* ctx, sc_lobpcg_state* s) {
+        if (s->need_restart) return restart_enqueue(ctx, s);
         hipStream_t st = ctx->stream;
         const int64_t ld = s->K3;
         const int kp = s->kp;
         // X stays fully active; the W mask was set by the residual step
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, kp, s->k);
         SC_CHECK_LAUNCH(ctx);
-        SC_TRY(cholqr(ctx, s, kp, 0, 0));
+        // a rank-deficient residual block: an error in FP64 (the plain
+        // method), dependent columns left out in the reduced-precision modes
+        if (s->prec == SC_PREC_FP64)
+            SC_TRY(cholqr(ctx, s, kp, 0, CQ_REQUIRE_ALL, nullptr));
+        else
+            SC_TRY(cholqr(ctx, s, kp, 0, CQ_DROP_DEPENDENT, s->wdrops));
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
             SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s) + kp, ld,
@@ -263,12 +388,11 @@ struct Solver {
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
                            s->has_p ? s->k : 0);
         SC_CHECK_LAUNCH(ctx);
-        if (s->has_p) SC_TRY(cholqr(ctx, s, 2 * kp, 1, 1));
+        if (s->has_p) SC_TRY(cholqr(ctx, s, 2 * kp, 1, CQ_DROP_ALL, s->pdrops));
         SC_TRY(rr_and_update(ctx, s));
         s->has_p = 1;
         s->t += 1;
-        SC_TRY(residual(ctx, s));
-        return SC_OK;
+        return residual_enqueue(ctx, s);
     }
 
     static sc_status finish(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
@@ -286,7 +410,7 @@ struct Solver {
         std::vector<double> h((size_t)rows * s->kp);
         SC_CHECK_HIP(ctx, hipMemcpyAsync(h.data(), s->hist, h.size() * sizeof(double),
                                          hipMemcpyDeviceToHost, st));
-        int cnt[4];
+        int cnt[8];
         SC_CHECK_HIP(ctx, hipMemcpyAsync(cnt, s->status, sizeof cnt, hipMemcpyDeviceToHost, st));
         SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
         if (relres_hist)
@@ -300,6 +424,9 @@ struct Solver {
             for (int j = 0; j < s->k; ++j) locked += h[(size_t)s->t * s->kp + j] <= s->lock_tol;
             info->locked_cols = locked;
             info->max_relres = s->max_relres;
+            info->w_drops = cnt[3];
+            info->gram_fallbacks = cnt[4];
+            info->restarts = s->restarts;
         }
         return SC_OK;
     }
@@ -311,6 +438,14 @@ sc_status dispatch_begin(sc_ctx* ctx, sc_lobpcg_state* s, const void* X0) {
 }
 sc_status dispatch_step(sc_ctx* ctx, sc_lobpcg_state* s) {
     return s->prec == SC_PREC_FP64 ? Solver<double>::step(ctx, s) : Solver<float>::step(ctx, s);
+}
+sc_status dispatch_step_enqueue(sc_ctx* ctx, sc_lobpcg_state* s) {
+    return s->prec == SC_PREC_FP64 ? Solver<double>::step_enqueue(ctx, s)
+                                   : Solver<float>::step_enqueue(ctx, s);
+}
+sc_status dispatch_process(sc_ctx* ctx, sc_lobpcg_state* s) {
+    return s->prec == SC_PREC_FP64 ? Solver<double>::residual_process(ctx, s)
+                                   : Solver<float>::residual_process(ctx, s);
 }
 sc_status dispatch_finish(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
                           double* relres_hist, sc_lobpcg_info* info) {
@@ -350,6 +485,9 @@ extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const 
     s->lock_tol = opts->lock_tol > 0 ? opts->lock_tol : (f64 ? 1e-13 : 1e-6);
     s->chol_tol = opts->chol_tol > 0 ? opts->chol_tol : (f64 ? 1e-14 : 1e-6);
     sc_status st = hipSetDevice(ctx->device) == hipSuccess ? SC_OK : SC_E_HIP;
+    if (st == SC_OK && (hipHostMalloc((void**)&s->readback, 64, hipHostMallocDefault) != hipSuccess ||
+                        hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess))
+        st = sc_fail(ctx, SC_E_HIP, "lobpcg: cannot create the readback buffer or event");
     if (st == SC_OK) st = dispatch_begin(ctx, s, X0);
     if (st != SC_OK) {
         delete s;
@@ -362,7 +500,37 @@ extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const 
 
 extern "C" sc_status sc_lobpcg_step(sc_ctx* ctx, sc_lobpcg_state* s, int* done) {
     if (!ctx || !s) return SC_E_INVAL;
-    if (!s->done) SC_TRY(dispatch_step(ctx, s));
+    if (s->in_flight) {
+        SC_CHECK_HIP(ctx, hipEventSynchronize(s->ready));
+        SC_TRY(dispatch_process(ctx, s));
+    } else if (!s->done) {
+        SC_TRY(dispatch_step(ctx, s));
+    }
+    if (done) *done = s->done;
+    return SC_OK;
+}
+
+extern "C" sc_status sc_lobpcg_step_async(sc_ctx* ctx, sc_lobpcg_state* s) {
+    if (!ctx || !s) return SC_E_INVAL;
+    if (s->in_flight) return sc_fail(ctx, SC_E_INVAL, "lobpcg: an iteration is already in flight");
+    if (s->done) return SC_OK;
+    return dispatch_step_enqueue(ctx, s);
+}
+
+extern "C" sc_status sc_lobpcg_step_poll(sc_ctx* ctx, sc_lobpcg_state* s, int* ready, int* done) {
+    if (!ctx || !s) return SC_E_INVAL;
+    int rdy = 1;
+    if (s->in_flight) {
+        const hipError_t q = hipEventQuery(s->ready);
+        if (q == hipErrorNotReady) {
+            rdy = 0;
+        } else if (q != hipSuccess) {
+            return sc_fail(ctx, SC_E_HIP, "lobpcg: hipEventQuery failed: %s", hipGetErrorString(q));
+        } else {
+            SC_TRY(dispatch_process(ctx, s));
+        }
+    }
+    if (ready) *ready = rdy;
     if (done) *done = s->done;
     return SC_OK;
 }
@@ -370,6 +538,7 @@ extern "C" sc_status sc_lobpcg_step(sc_ctx* ctx, sc_lobpcg_state* s, int* done) 
 extern "C" sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* s, void* X_out, double* theta,
                                    double* relres_hist, sc_lobpcg_info* info) {
     if (!ctx || !s) return SC_E_INVAL;
+    if (s->in_flight) (void)hipEventSynchronize(s->ready);
     sc_status st = dispatch_finish(ctx, s, X_out, theta, relres_hist, info);
     delete s;
     return st;

@@ -276,6 +276,10 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
     }
     if (r0 == 0.0) r0 = tiny;
     AT(U0, m - 1) = r0;
+    // the last row has no superdiagonal entries; they are still read (times
+    // zero) by the back substitution, so they must not hold stale NaN / Inf
+    AT(U1, m - 1) = 0.0;
+    AT(U2, m - 1) = 0.0;
     double* z = V + i;      // column i, row stride ldv
     for (int r = 0; r < m; ++r)
         z[(int64_t)r * ldv] =
@@ -390,18 +394,22 @@ __device__ void back_transform_col(int m, const double* A, const double* tau, do
 __global__ void __launch_bounds__(NT)
 k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restrict__ GB,
            int* __restrict__ act, double tol, double* __restrict__ U, double* __restrict__ Am,
-           int* __restrict__ info, int* status, int* counter) {
+           int* __restrict__ info, int* status, int* counter, const int* __restrict__ pred,
+           int* __restrict__ probe, int* __restrict__ probe_counter, int* __restrict__ wcounter) {
     __shared__ int idx[MAXM];
-    __shared__ int m_s, fail_s, has_p;
+    __shared__ int m_s, fail_s, fail_at, has_p;
+    if (pred && *pred == 0) return;
     const int tid = threadIdx.x;
     int m = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    // each failed attempt removes P, or (with wcounter) one dependent W column
+    for (int attempt = 0; attempt < K3 + 2; ++attempt) {
         if (tid == 0) {
             int mm = 0;
             for (int j = 0; j < K3; ++j)
                 if (act[j]) idx[mm++] = j;
             m_s = mm;
             fail_s = 0;
+            fail_at = -1;
         }
         __syncthreads();
         m = m_s;
@@ -415,8 +423,12 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
             if (tid == 0) {
                 const double s = U[(int64_t)j * m + j];
                 const double g = GB[(int64_t)idx[j] * K3 + idx[j]];
-                if (!isfinite(s) || !(s > tol * g) || !(s > 0.0)) fail_s = 1;
-                else U[(int64_t)j * m + j] = sqrt(s);
+                if (!isfinite(s) || !(s > tol * g) || !(s > 0.0)) {
+                    fail_s = 1;
+                    fail_at = j;
+                } else {
+                    U[(int64_t)j * m + j] = sqrt(s);
+                }
             }
             __syncthreads();
             if (fail_s) break;
@@ -431,30 +443,53 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
             __syncthreads();
         }
         if (!fail_s) break;
+        if (probe) {
+            // the basis Gram matrix is too ill-conditioned for its precision
+            if (tid == 0) {
+                *probe = 1;
+                if (probe_counter) atomicAdd(probe_counter, 1);
+                info[0] = 0;
+            }
+            return;
+        }
         if (tid == 0) {
             has_p = 0;
             for (int j = 2 * kp; j < K3; ++j) has_p |= act[j];
         }
         __syncthreads();
-        if (!has_p || attempt == 1) {
+        if (has_p) {
+            for (int j = 2 * kp + tid; j < K3; j += NT) act[j] = 0;
             if (tid == 0) {
-                atomicOr(status, DEV_BREAKDOWN);
-                info[0] = 0;
+                atomicOr(status, DEV_P_DROPPED);
+                if (counter) atomicAdd(counter, 1);
             }
-            return;
+            __syncthreads();
+            continue;
         }
-        for (int j = 2 * kp + tid; j < K3; j += NT) act[j] = 0;
+        const int col = fail_at >= 0 ? idx[fail_at] : -1;
+        if (wcounter && col >= kp && col < 2 * kp) {
+            // W column numerically inside the span of the earlier basis vectors
+            if (tid == 0) {
+                act[col] = 0;
+                atomicAdd(wcounter, 1);
+            }
+            __syncthreads();
+            continue;
+        }
         if (tid == 0) {
-            atomicOr(status, DEV_P_DROPPED);
-            if (counter) atomicAdd(counter, 1);
+            atomicOr(status, DEV_BREAKDOWN_RR);
+            info[0] = 0;
         }
-        __syncthreads();
+        return;
     }
     for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
         const int a = (int)(q / m), b = (int)(q % m);
         Am[q] = GA[(int64_t)idx[a] * K3 + idx[b]];
     }
-    if (tid == 0) info[0] = m;
+    if (tid == 0) {
+        info[0] = m;
+        if (probe) *probe = 0;
+    }
     for (int j = tid; j < m; j += NT) info[1 + j] = idx[j];
 }
 
@@ -626,37 +661,62 @@ size_t rr_scratch_elems(int K3, int k) {
            5 * (size_t)MAXM * k + 64;
 }
 
-sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
-                               const double* GB, int* act, double tol, double* C64, float* C32,
-                               double* theta, double* scratch, int* status, int* counter) {
+struct RrScratch {
+    double *U, *Ui, *Am, *Tm, *Q, *Cq, *dtau, *ews;
+    int* info;
+    RrScratch(double* scratch, int K3, int k) {
+        const size_t sq = (size_t)K3 * K3;
+        U = scratch;
+        Ui = U + sq;
+        Am = Ui + sq;
+        Tm = Am + sq;                         // A U^-1
+        Q = Tm + sq;                          // m x k
+        Cq = Q + (size_t)K3 * k;              // m x k
+        dtau = Cq + (size_t)K3 * k;           // d, e, tau (3 x MAXM) + params
+        info = reinterpret_cast<int*>(dtau + 3 * MAXM + 8);
+        ews = dtau + 3 * MAXM + 8 + (MAXM + 64) / 2;   // inverse-iteration LU arrays
+    }
+};
+
+sc_status launch_rr_setup(sc_ctx* ctx, int K3, int kp, int k, const double* GA, const double* GB,
+                          int* act, double tol, double* scratch, int* status, int* counter,
+                          const int* pred, int* probe, int* probe_counter, int* wcounter) {
     if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
-    const size_t sq = (size_t)K3 * K3;
-    double* U = scratch;
-    double* Ui = U + sq;
-    double* Am = Ui + sq;
-    double* Tm = Am + sq;                    // A U^-1
-    double* Q = Tm + sq;                     // m x k
-    double* Cq = Q + (size_t)K3 * k;         // m x k
-    double* dtau = Cq + (size_t)K3 * k;      // d, e, tau (3 x MAXM) + params
-    int* info = reinterpret_cast<int*>(dtau + 3 * MAXM + 8);
-    double* ews = dtau + 3 * MAXM + 8 + (MAXM + 64) / 2;   // inverse-iteration LU arrays
+    RrScratch w(scratch, K3, k);
+    hipLaunchKernelGGL(k_rr_setup, dim3(1), dim3(NT), 0, ctx->stream, K3, kp, GA, GB, act, tol, w.U,
+                       w.Am, w.info, status, counter, pred, probe, probe_counter, wcounter);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
+sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float* C32,
+                          double* theta, double* scratch) {
+    if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
+    RrScratch w(scratch, K3, k);
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_rr_setup, dim3(1), dim3(NT), 0, st, K3, kp, GA, GB, act, tol, U, Am, info,
-                       status, counter);
-    hipLaunchKernelGGL(k_rr_inv, dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st, info, U, Ui);
+    hipLaunchKernelGGL(k_rr_inv, dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st, w.info, w.U, w.Ui);
     const dim3 gsq((unsigned)ceil_div(K3, 64), (unsigned)ceil_div(K3, 64));
-    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 0, Am, Ui, Tm);   // Tm = A U^-1
-    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, info, 0, 1, Ui, Tm, U);    // M = U^-T Tm (into U)
-    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, info, U, dtau);
-    eig_pipeline(st, k, info, U, dtau, theta, Q, ews);
+    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 0, w.Am, w.Ui, w.Tm);  // Tm = A U^-1
+    hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 1, w.Ui, w.Tm, w.U);   // M = U^-T Tm
+    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, w.info, w.U, w.dtau);
+    eig_pipeline(st, k, w.info, w.U, w.dtau, theta, w.Q, w.ews);
     const dim3 gk((unsigned)ceil_div(k, 64), (unsigned)ceil_div(K3, 64));
-    hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, info, k, 0, Ui, Q, Cq);    // C = U^-1 Q
+    hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, w.info, k, 0, w.Ui, w.Q, w.Cq);    // C = U^-1 Q
     hipLaunchKernelGGL(k_rr_zero, dim3((unsigned)ceil_div((int64_t)K3 * kp, 256)), dim3(256), 0, st,
                        K3, kp, k, C64, C32, theta);
     hipLaunchKernelGGL(k_rr_scatter, dim3((unsigned)ceil_div((int64_t)K3 * k, 256)), dim3(256), 0,
-                       st, k, kp, info, Cq, C64, C32);
+                       st, k, kp, w.info, w.Cq, C64, C32);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
+}
+
+sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
+                               const double* GB, int* act, double tol, double* C64, float* C32,
+                               double* theta, double* scratch, int* status, int* counter,
+                               int* wcounter) {
+    SC_TRY(launch_rr_setup(ctx, K3, kp, k, GA, GB, act, tol, scratch, status, counter, nullptr,
+                           nullptr, nullptr, wcounter));
+    return launch_rr_solve(ctx, K3, kp, k, C64, C32, theta, scratch);
 }
 
 sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,

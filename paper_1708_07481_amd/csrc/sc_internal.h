@@ -68,6 +68,7 @@ enum : int {
     DEV_NUMERIC = 2,        // NaN or Inf
     DEV_BREAKDOWN = 4,      // unrecoverable Cholesky failure
     DEV_P_DROPPED = 8,      // P dropped in this iteration (informational)
+    DEV_BREAKDOWN_RR = 16,  // basis Gram matrix of the Rayleigh-Ritz step not positive definite
 };
 
 // Bump allocator over a caller-provided workspace.  With base == nullptr it
@@ -132,19 +133,31 @@ struct GramPlan {
     int bt;             // workgroup output tile edge
     int tiles;          // tiles per side
 };
-GramPlan gram_plan(int64_t n, int c, int elem_bytes);
+// Gram precision for FP32 data: native FP32 MFMA, BF16-rounded inputs, or
+// widened to FP64 (exact products, FP64 accumulation).  FP64 data always
+// accumulates in FP64.
+enum { GRAM_NATIVE = 0, GRAM_BF16 = 1, GRAM_F32_EXACT = 2 };
+// plan for `accum_bytes` = 8 (FP64 accumulation: FP64 data or GRAM_F32_EXACT)
+// or 4 (GRAM_NATIVE / GRAM_BF16 on FP32 data)
+GramPlan gram_plan(int64_t n, int c, int accum_bytes);
 size_t gram_partial_elems(const GramPlan& p, int nout);
+// G1 = A'B1 (and G2 = A'B2), split over row chunks; with `pred` non-null the
+// launches do nothing when *pred == 0.
 template <class T>
 sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, const T* B1,
                       int64_t ldb1, const T* B2, int64_t ldb2, double* partial, double* G1,
-                      double* G2, int bf16);
+                      double* G2, int gmode, const int* pred = nullptr);
 
 // Small-matrix Cholesky QR factor: from the c x c FP64 Gram G and the
 // active-column mask, T = D^-1 R^-1 (zero rows/cols for inactive columns).
-// On Cholesky failure: drop_on_fail ? (T = 0, mask = 0, status |= P_DROPPED,
-// counter[0]++) : status |= BREAKDOWN.
+// On a failing pivot, by mode:
+//   CQ_REQUIRE_ALL     status |= BREAKDOWN (also when an active column is zero);
+//   CQ_DROP_ALL        T = 0, mask = 0, status |= P_DROPPED, counter[0]++;
+//   CQ_DROP_DEPENDENT  the failing column leaves the mask (counter[0]++) and
+//                      the factorisation is redone without it.
+enum { CQ_REQUIRE_ALL = 0, CQ_DROP_ALL = 1, CQ_DROP_DEPENDENT = 2 };
 sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, double tol,
-                               double* T64, float* T32, double* scratch, int drop_on_fail,
+                               double* T64, float* T32, double* scratch, int mode,
                                int* status, int* counter);
 // V <- V T (and V2 <- V2 T) on n x c row blocks, in place.
 template <class T>
@@ -159,17 +172,34 @@ template <class T>
 sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* LS, int64_t ld,
                           const double* theta, double* partial, int* nblocks_out);
 // Finalise: relres, history row, W mask, flags; out[0] = max relres,
-// out_flags[0] = all columns locked.
+// out_flags[0] = all columns locked.  With out_restart non-null it is set to
+// 1 when the iterate is inconsistent (a Ritz value outside [0, 2] by more than
+// 1e-3, or relres > 1, impossible when LX = L X), else 0.
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k,
                                    const double* partial, double lock_tol, double* relres,
                                    double* hist_row, int* wmask, int* status, double* out_max,
-                                   int* out_all_locked);
+                                   int* out_all_locked, const double* theta, int* out_restart);
 
 // Rayleigh-Ritz (FP64) on the active columns: C (K3 x kp), theta (kp).
+// Split in two: the set-up (active set, Cholesky of G_B with the P-drop
+// rule, reduced G_A) and the solve (reduced eigenproblem, C, theta).
+//   pred   (device int or null): the set-up does nothing when *pred == 0;
+//   probe  (device int or null): probing set-up, tolerance `tol` without the
+//          P-drop rule; on a failing pivot it sets *probe = 1 (and
+//          probe_counter[0]++) and leaves m = 0, else *probe = 0;
+//   wcounter (device int or null): when the factorisation fails without P,
+//          the failing W column leaves the basis (wcounter[0]++) and the
+//          factorisation is redone, instead of a breakdown.
 size_t rr_scratch_elems(int K3, int k);
+sc_status launch_rr_setup(sc_ctx* ctx, int K3, int kp, int k, const double* GA, const double* GB,
+                          int* act, double tol, double* scratch, int* status, int* counter,
+                          const int* pred, int* probe, int* probe_counter, int* wcounter);
+sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float* C32,
+                          double* theta, double* scratch);
 sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
                                const double* GB, int* act, double tol, double* C64, float* C32,
-                               double* theta, double* scratch, int* status, int* counter);
+                               double* theta, double* scratch, int* status, int* counter,
+                               int* wcounter);
 sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
                         double* scratch);
 size_t symeig_scratch_elems(int m, int k);

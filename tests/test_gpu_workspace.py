@@ -1,0 +1,89 @@
+"""Results must not depend on what the caller's workspace held before the
+call: every entry point is run twice on the same input, once with a zeroed
+workspace and once with one filled with 0xFF bytes (NaN in every float lane,
+-1 in every integer), and the outputs must agree bitwise.  A serving loop
+recycles freed workspaces of other solves, so stale contents are the normal
+case there."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1708_07481_amd import api
+from synth import dcsbm, gaussian_block, kmeans_draws
+
+from tests.gpu_common import gpu_ctx, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _ws(nbytes, byte):
+    return torch.full((max(int(nbytes), 256),), byte, dtype=torch.uint8, device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def graph():
+    ctx = gpu_ctx()
+    g0 = dcsbm(3000, 12, 20.0, 0.8, seed=4)
+    g = api.graph_build(ctx, g0.n, to_dev(g0.src), to_dev(g0.dst))
+    return ctx, g0, g
+
+
+def test_graph_build_workspace_independent(graph):
+    ctx, g0, _ = graph
+    import ctypes as C
+    from paper_1708_07481_amd._lib import lib
+    nb = C.c_size_t()
+    ctx.check(lib().sc_graph_build_workspace(ctx.handle, g0.n, g0.m, C.byref(nb)), "ws")
+    out = []
+    for byte in (0, 0xFF):
+        g = api.graph_build(ctx, g0.n, to_dev(g0.src), to_dev(g0.dst), ws=_ws(nb.value, byte))
+        out.append((g.nnz, host(g.row_ptr), host(g.col), host(g.degree)))
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_bf16gram"])
+def test_lobpcg_workspace_independent(graph, prec):
+    ctx, g0, g = graph
+    k = 12
+    v64, v32, _ = api.laplacian_csr(ctx, g, True, True)
+    val = v64 if prec == "fp64" else v32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    X0 = to_dev(gaussian_block(g0.n, k, 4), dt)
+    opts = api.lobpcg_opts(k, 15, 0.0, prec, k)
+    nb = api.lobpcg_workspace(ctx, g0.n, g.nnz, opts)
+    res = [api.lobpcg_solve(ctx, g, val, X0, 15, 0.0, prec, ws=_ws(nb, byte)) for byte in (0, 0xFF)]
+    assert res[0].iterations == res[1].iterations
+    assert np.array_equal(host(res[0].theta), host(res[1].theta))
+    assert np.array_equal(host(res[0].X), host(res[1].X))
+
+
+def test_kmeans_workspace_independent(graph):
+    ctx, g0, g = graph
+    import ctypes as C
+    from paper_1708_07481_amd._lib import lib, sc_kmeans_opts
+    X = to_dev(np.random.default_rng(2).standard_normal((g0.n, 12)))
+    draws = to_dev(kmeans_draws(5, 12, 2).view(np.int64))
+    o = sc_kmeans_opts(12, 5, 100, 1, 0)
+    nb = C.c_size_t()
+    ctx.check(lib().sc_kmeans_workspace(ctx.handle, g0.n, 12, C.byref(o), C.byref(nb)), "ws")
+    r = [api.kmeans_assign(ctx, X, 12, draws, ws=_ws(nb.value, byte)) for byte in (0, 0xFF)]
+    assert np.array_equal(host(r[0].labels), host(r[1].labels))
+    assert r[0].inertia_q == r[1].inertia_q and r[0].best_restart == r[1].best_restart
+    assert np.array_equal(host(r[0].centroids), host(r[1].centroids))
+
+
+def test_symeig_workspace_independent():
+    ctx = gpu_ctx()
+    import ctypes as C
+    from paper_1708_07481_amd._lib import lib
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((90, 90))
+    A = A + A.T
+    nb = C.c_size_t()
+    ctx.check(lib().sc_symeig_workspace(ctx.handle, 90, 20, C.byref(nb)), "ws")
+    r = [api.symeig(ctx, to_dev(A), 20, ws=_ws(nb.value, byte)) for byte in (0, 0xFF)]
+    assert np.array_equal(host(r[0][0]), host(r[1][0]))
+    assert np.array_equal(host(r[0][1]), host(r[1][1]))
+    assert np.all(np.isfinite(host(r[1][1])))
