@@ -191,6 +191,11 @@ def main():
     ap.add_argument("--stages", type=int, default=10)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
+                    help="override the workload's precision")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, run a plain 512 MiB device copy three times "
+                         "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -210,7 +215,7 @@ def main():
 
     cfg = config(args.config)
     restarts = args.restarts if args.restarts is not None else cfg["restarts"]
-    prec = cfg["precision"]
+    prec = args.precision or cfg["precision"]
     fp64 = prec == "fp64"
     n, k = cfg["n"], cfg["k"]
     log(f"generating {args.config}: n={n} blocks={cfg['blocks']} k={k} precision={prec}")
@@ -290,6 +295,8 @@ def main():
         "lobpcg_iterations": res.iterations,
         "converged": res.converged,
         "max_relres": res.max_relres,
+        "solver_events": {"p_drops": res.p_drops, "w_drops": res.w_drops,
+                          "gram_fallbacks": res.gram_fallbacks, "restarts": res.restarts},
         "iterations_per_s": round(iters_total / (lob_ms * 1e-3), 3) if lob_ms > 0 else None,
         "spmm_hbm_gbs_algorithmic": round(achieved, 1),
         "phase_ms_per_step": {kk: round(v["total_ms"] / args.steps, 3) for kk, v in prof.items()},
@@ -301,6 +308,13 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "traffic": spmm_traffic(args.config, alg_bytes)},
     }
+    if args.calibrate_copy:
+        x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         try:
