@@ -172,6 +172,47 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def compare_fp64(args, api, ctx, cfg, n, k, src, dst, X0h, draws, res, km, t_mixed, truth):
+    """The same graph and start block in FP64: timing and the differences."""
+    import numpy as np
+    import torch
+    from paper_1708_07481_amd.metrics import partition_scores
+    X0 = torch.from_numpy(X0h).to(src.device)
+
+    def step():
+        gd = api.graph_build(ctx, n, src, dst)
+        v64, _, _ = api.laplacian_csr(ctx, gd, True, False)
+        r = api.lobpcg_solve(ctx, gd, v64, X0, cfg["maxit"], cfg["tol"], "fp64")
+        kk = api.kmeans_assign(ctx, r.X, k, draws, max_iter=100)
+        return r, kk
+
+    log("fp64 comparison run ...")
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r64, k64 = step()
+    torch.cuda.synchronize()
+    t64 = (time.perf_counter() - t0) / args.steps
+    th64 = r64.theta.cpu().numpy()
+    th = res.theta.cpu().numpy()
+    Xr = res.X.double()
+    Xo = r64.X
+    A = Xr - Xo @ (Xo.T @ Xr)
+    sine = float(torch.linalg.eigvalsh(A.T @ A).max().clamp(min=0).sqrt())
+    s64 = partition_scores(truth, k64.labels.cpu().numpy())
+    sm = partition_scores(truth, km.labels.cpu().numpy())
+    return {"fp64_s": round(t64, 4), "mixed_s": round(t_mixed, 4),
+            "speedup": round(t64 / t_mixed, 3),
+            "fp64_iterations": r64.iterations, "mixed_iterations": res.iterations,
+            "theta_max_abs_err": float(np.max(np.abs(th - th64))),
+            "theta_max_rel_err": float(np.max(np.abs(th - th64) / np.maximum(np.abs(th64), 1e-12))),
+            "subspace_sine": sine,
+            "PM_fp64": round(s64["PM"], 5), "PM_mixed": round(sm["PM"], 5),
+            "labels_agree_fraction": float(partition_scores(k64.labels.cpu().numpy(),
+                                                            km.labels.cpu().numpy())["PM"])}
+
+
 def _clone(r, **kw):
     import dataclasses
     return dataclasses.replace(r, **kw)
@@ -193,6 +234,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")
+    ap.add_argument("--compare", action="store_true",
+                    help="also solve the same graph from the same start block in FP64 and report "
+                         "speedup, eigenvalue error, subspace sine and accuracy of both")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run a plain 512 MiB device copy three times "
                          "(reference kernel for the HBM byte counters)")
@@ -308,6 +352,22 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "traffic": spmm_traffic(args.config, alg_bytes)},
     }
+    # Gram products of the Rayleigh-Ritz step (S'LS and S'S, one pair per RR)
+    gram = prof.get("gram")
+    if gram:
+        n_rr = (res.iterations + 1 + res.restarts) * args.steps
+        gram_ms = gram["total_ms"] / n_rr
+        K3 = 3 * ((k + 3) // 4 * 4)
+        gflop = 2.0 * n * K3 * (K3 + 1) / 1e9      # two symmetric K3 x K3 outputs
+        peak = 78.6 if fp64 else (2500.0 if prec == "fp32_bf16gram" else 157.3)
+        out["rooflines_other"] = [{
+            "kernel": "gram (S'LS and S'S)", "bound": "mfma", "unit": "TFLOP/s",
+            "achieved": round(gflop / gram_ms, 2), "peak": peak,
+            "frac": round(gflop / gram_ms / peak, 4), "ms_per_rr": round(gram_ms, 3),
+            "algorithmic_gflop": round(gflop, 1)}]
+    if args.compare and not fp64:
+        out["precision_comparison"] = compare_fp64(args, api, ctx, cfg, n, k, src, dst, X0h, draws,
+                                                   res, km, total / args.steps, g0.truth)
     if args.calibrate_copy:
         x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
