@@ -6,6 +6,7 @@
 // Reductions over the n rows are split into row chunks whose FP64 partial
 // results are summed in chunk order by a second kernel, so every result is
 // deterministic (no floating-point atomics).
+#include "chol.h"
 #include "sc_internal.h"
 
 namespace {
@@ -193,7 +194,7 @@ __global__ void k_gram_reduce(int c, int chunks, int nout, const double* __restr
 // ---------------------------------------------------------------------------
 // Cholesky QR factor of a small Gram matrix (one workgroup).
 // ---------------------------------------------------------------------------
-constexpr int CQ_TH = 256;
+constexpr int CQ_TH = 1024;
 // Ritz values further than this outside [0, 2] mark an inconsistent iterate
 constexpr double RESTART_THETA_SLACK = 1e-3;
 constexpr int CQ_MAX = 256;
@@ -205,10 +206,10 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
     __shared__ int idx[CQ_MAX];
     __shared__ double d[CQ_MAX];
     __shared__ int m_s, fail_s, fail_at;
+    __shared__ CholLds L;
     const int tid = threadIdx.x;
     int m = 0;
-    double* Gs = scr;                    // m x m equilibrated Gram
-    double* R = nullptr;                 // m x m upper factor
+    double* R = scr;                     // m x m equilibrated Gram, factored in place
     double* Ri = nullptr;                // m x m inverse
     // CQ_DROP_DEPENDENT removes one failing column per pass and refactors
     for (int pass = 0; pass <= c; ++pass) {
@@ -231,36 +232,19 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
         }
         __syncthreads();
         m = m_s;
-        R = scr + (int64_t)m * m;
         Ri = R + (int64_t)m * m;
+        if (fail_s) break;
         for (int e = tid; e < m * m; e += CQ_TH) {
             const int a = e / m, b = e % m;
-            Gs[e] = G[(int64_t)idx[a] * c + idx[b]] / (d[a] * d[b]);
-            R[e] = 0.0;
-            Ri[e] = 0.0;
+            R[e] = G[(int64_t)idx[a] * c + idx[b]] / (d[a] * d[b]);
         }
         __syncthreads();
-        for (int j = 0; j < m && !fail_s; ++j) {
-            if (tid == 0) {
-                double s = Gs[(int64_t)j * m + j];
-                for (int l = 0; l < j; ++l) s = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + j], s);
-                if (!isfinite(s) || !(s > tol * Gs[(int64_t)j * m + j]) || !(s > 0.0)) {
-                    fail_s = 1;
-                    fail_at = j;
-                } else {
-                    R[(int64_t)j * m + j] = sqrt(s);
-                }
-            }
-            __syncthreads();
-            if (fail_s) break;
-            const double rjj = R[(int64_t)j * m + j];
-            for (int b = j + 1 + tid; b < m; b += CQ_TH) {
-                double t = Gs[(int64_t)j * m + b];
-                for (int l = 0; l < j; ++l) t = fma(-R[(int64_t)l * m + j], R[(int64_t)l * m + b], t);
-                R[(int64_t)j * m + b] = t / rjj;
-            }
-            __syncthreads();
+        const int fa = chol_blocked<CQ_TH>(m, R, tol, L);
+        if (tid == 0) {
+            fail_s = fa >= 0;
+            fail_at = fa;
         }
+        __syncthreads();
         if (!fail_s || mode != CQ_DROP_DEPENDENT) break;
         // the failing column is (numerically) in the span of the earlier ones
         if (tid == 0) {
@@ -285,16 +269,8 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
         }
         return;
     }
-    // R^-1 by back substitution, one column per thread
-    for (int j = tid; j < m; j += CQ_TH) {
-        Ri[(int64_t)j * m + j] = 1.0 / R[(int64_t)j * m + j];
-        for (int a = j - 1; a >= 0; --a) {
-            double s = 0.0;
-            for (int l = a + 1; l <= j; ++l) s = fma(R[(int64_t)a * m + l], Ri[(int64_t)l * m + j], s);
-            Ri[(int64_t)a * m + j] = -s / R[(int64_t)a * m + a];
-        }
-    }
-    __syncthreads();
+    // R^-1, one wave per column (columns in LDS, reusing the panel buffer)
+    tri_inv_upper<CQ_TH>(m, R, Ri, &L.panel[0][0]);
     for (int e = tid; e < c * c; e += CQ_TH) {
         T64[e] = 0.0;
         T32[e] = 0.0f;

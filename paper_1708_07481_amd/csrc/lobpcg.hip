@@ -234,7 +234,8 @@ struct Solver {
             SC_TRY(launch_rr_setup(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
                                    s->rr_scr, s->status, s->pdrops, s->gflag, nullptr, nullptr,
                                    s->wdrops));
-            SC_TRY(launch_rr_solve(ctx, s->K3, s->kp, s->k, s->C64, s->C32, s->theta, s->rr_scr));
+            SC_TRY(launch_rr_solve(ctx, s->K3, s->kp, s->k, s->C64, s->C32, s->theta, s->rr_scr,
+                                   s->status));
         }
         ProfScope ps(ctx, SC_KIND_UPDATE);
         SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, S(s), ld, s->C64, s->C32));
@@ -281,6 +282,8 @@ struct Solver {
             return sc_fail(ctx, SC_E_BREAKDOWN,
                            "lobpcg: Rayleigh-Ritz breakdown (basis Gram matrix not positive "
                            "definite without P) at iteration %d", s->t);
+        if (st[0] & DEV_SYNC_TIMEOUT)
+            return sc_fail(ctx, SC_E_HIP, "lobpcg: a grid-barrier wait timed out");
         if (st[0] & DEV_NUMERIC)
             return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in a residual");
         double mx;

@@ -16,6 +16,7 @@
 // The matrices live in a global scratch area (L2 resident at these sizes).
 #include <float.h>
 
+#include "chol.h"
 #include "sc_internal.h"
 
 namespace {
@@ -398,6 +399,7 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
            int* __restrict__ probe, int* __restrict__ probe_counter, int* __restrict__ wcounter) {
     __shared__ int idx[MAXM];
     __shared__ int m_s, fail_s, fail_at, has_p;
+    __shared__ CholLds L;
     if (pred && *pred == 0) return;
     const int tid = threadIdx.x;
     int m = 0;
@@ -418,30 +420,13 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
             U[q] = GB[(int64_t)idx[a] * K3 + idx[b]];
         }
         __syncthreads();
-        // right-looking Cholesky B = U'U in place (upper triangle)
-        for (int j = 0; j < m; ++j) {
-            if (tid == 0) {
-                const double s = U[(int64_t)j * m + j];
-                const double g = GB[(int64_t)idx[j] * K3 + idx[j]];
-                if (!isfinite(s) || !(s > tol * g) || !(s > 0.0)) {
-                    fail_s = 1;
-                    fail_at = j;
-                } else {
-                    U[(int64_t)j * m + j] = sqrt(s);
-                }
-            }
-            __syncthreads();
-            if (fail_s) break;
-            const double rjj = U[(int64_t)j * m + j];
-            for (int b = j + 1 + tid; b < m; b += NT) U[(int64_t)j * m + b] /= rjj;
-            __syncthreads();
-            const int len = m - j - 1;
-            for (int64_t q = tid; q < (int64_t)len * len; q += NT) {
-                const int a = j + 1 + (int)(q / len), b = j + 1 + (int)(q % len);
-                if (b >= a) U[(int64_t)a * m + b] -= U[(int64_t)j * m + a] * U[(int64_t)j * m + b];
-            }
-            __syncthreads();
+        // B = U'U in place (upper triangle), blocked
+        const int fa = chol_blocked<NT>(m, U, tol, L);
+        if (tid == 0) {
+            fail_s = fa >= 0;
+            fail_at = fa;
         }
+        __syncthreads();
         if (!fail_s) break;
         if (probe) {
             // the basis Gram matrix is too ill-conditioned for its precision
@@ -592,6 +577,150 @@ k_rr_tridiag(const int* __restrict__ info, double* __restrict__ M, double* __res
     tridiagonalize(m, M, d, e, tau, vs, ps, red, sh);
 }
 
+// --- step 3a on many workgroups (cooperative launch): the same Householder
+// reduction, with the symmetric product p = tau A22 v and the rank-2 update
+// spread over every wave of the grid (one wave per row, lanes along the row)
+// and two grid barriers per column.  Every workgroup computes the reflector
+// redundantly from the same row, so all take identical control flow.
+constexpr int TD_NT = 256;
+constexpr int TD_WAVES = TD_NT / 64;
+constexpr int TD_GRID = 32;
+// bound on the spin of one barrier wait (each spin sleeps ~128 clocks); a
+// wait that reaches it raises DEV_SYNC_TIMEOUT and the kernel runs to its end
+constexpr unsigned long long TD_SPIN_LIMIT = 1ull << 26;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double block_sum_td(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < TD_WAVES; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// grid barrier: bar[0] arrivals, bar[1] generation (both zero at launch)
+__device__ inline void grid_sync(unsigned* bar, unsigned& gen, int* status) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned g = gen;
+        if (atomicAdd(bar, 1u) == gridDim.x - 1) {
+            atomicExch(bar, 0u);
+            __threadfence();
+            atomicAdd(bar + 1, 1u);
+        } else {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > TD_SPIN_LIMIT) {
+                    atomicOr(status, DEV_SYNC_TIMEOUT);
+                    break;
+                }
+            }
+        }
+        gen = g + 1;
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(TD_NT)
+k_tridiag_coop(const int* __restrict__ info, double* __restrict__ M, double* __restrict__ dtau,
+               double* __restrict__ P, unsigned* __restrict__ bar, int* status) {
+    __shared__ double vs[MAXM], ws[MAXM];
+    __shared__ double red[TD_WAVES];
+    const int m = info[0];
+    if (m == 0) return;
+    unsigned gen = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * TD_WAVES + wave, GW = gridDim.x * TD_WAVES;
+    // symmetrise; the pair (a, b), a < b, belongs to the wave of row a
+    for (int a = gw; a < m; a += GW)
+        for (int b = a + 1 + lane; b < m; b += 64) {
+            const double sv = 0.5 * (M[(int64_t)a * m + b] + M[(int64_t)b * m + a]);
+            M[(int64_t)a * m + b] = sv;
+            M[(int64_t)b * m + a] = sv;
+        }
+    grid_sync(bar, gen, status);
+    double* d = dtau;
+    double* e = d + MAXM;
+    double* tau = e + MAXM;
+    for (int j = 0; j + 2 < m; ++j) {
+        const int len = m - j - 1;
+        const double* x = M + (int64_t)j * m + j + 1;
+        double part = 0.0;
+        for (int r = 1 + threadIdx.x; r < len; r += TD_NT) part = fma(x[r], x[r], part);
+        const double sigma = block_sum_td(part, red);
+        const double x0 = x[0];
+        double tj, v0, ej;
+        if (sigma == 0.0) {
+            tj = 0.0;
+            ej = x0;
+            v0 = 1.0;
+        } else {
+            const double mu = sqrt(x0 * x0 + sigma);
+            v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+            tj = 2.0 * v0 * v0 / (sigma + v0 * v0);
+            ej = mu;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            d[j] = M[(int64_t)j * m + j];
+            e[j] = ej;
+            tau[j] = tj;
+        }
+        if (tj == 0.0) continue;          // same decision in every workgroup
+        for (int r = threadIdx.x; r < len; r += TD_NT) vs[r] = r == 0 ? 1.0 : x[r] / v0;
+        __syncthreads();
+        for (int r = gw; r < len; r += GW) {
+            const double* row = M + (int64_t)(j + 1 + r) * m + (j + 1);
+            double sacc = 0.0;
+            for (int c = lane; c < len; c += 64) sacc = fma(row[c], vs[c], sacc);
+            sacc = wave_sum(sacc);
+            if (lane == 0) P[r] = tj * sacc;
+        }
+        grid_sync(bar, gen, status);
+        part = 0.0;
+        for (int r = threadIdx.x; r < len; r += TD_NT) {
+            const double pr = P[r];
+            ws[r] = pr;
+            part = fma(pr, vs[r], part);
+        }
+        const double K = 0.5 * tj * block_sum_td(part, red);
+        for (int r = threadIdx.x; r < len; r += TD_NT) ws[r] = ws[r] - K * vs[r];
+        __syncthreads();
+        for (int r = gw; r < len; r += GW) {
+            double* row = M + (int64_t)(j + 1 + r) * m + (j + 1);
+            const double vr = vs[r], wr = ws[r];
+            for (int c = lane; c < len; c += 64) row[c] -= vr * ws[c] + wr * vs[c];
+        }
+        // the reflector is kept in row j (not read again by the reduction)
+        if (blockIdx.x == 0)
+            for (int r = 1 + threadIdx.x; r < len; r += TD_NT) M[(int64_t)j * m + j + 1 + r] = vs[r];
+        grid_sync(bar, gen, status);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (m >= 2) {
+            d[m - 2] = M[(int64_t)(m - 2) * m + (m - 2)];
+            e[m - 2] = M[(int64_t)(m - 2) * m + (m - 1)];
+            tau[m - 2] = 0.0;
+        }
+        d[m - 1] = M[(int64_t)(m - 1) * m + (m - 1)];
+        tau[m - 1] = 0.0;
+    }
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
 __global__ void k_set_info(int* info, int m) {
     if (threadIdx.x == 0) info[0] = m;
 }
@@ -609,6 +738,25 @@ k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (m == 0 || i >= k) return;
     back_transform_col(m, M, dtau + 2 * MAXM, Q + i, k);
+}
+
+// reduction to tridiagonal form: the cooperative kernel when the matrix is
+// large enough to feed many workgroups (m_max >= 128), else one workgroup.
+// `P` holds >= m_max doubles, `bar` two unsigned ints.
+static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, double* M,
+                                       double* tri, double* P, unsigned* bar, int* status) {
+    hipStream_t st = ctx->stream;
+    if (m_max >= 128) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
+        void* args[] = {(void*)&info, (void*)&M, (void*)&tri, (void*)&P, (void*)&bar, (void*)&status};
+        const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tridiag_coop, dim3(TD_GRID),
+                                                        dim3(TD_NT), args, 0, st);
+        if (e == hipSuccess) return SC_OK;
+        (void)hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, info, M, tri);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
 }
 
 // tridiagonalised M (in `M`, reflectors inside) + tri block -> k smallest
@@ -664,6 +812,7 @@ size_t rr_scratch_elems(int K3, int k) {
 struct RrScratch {
     double *U, *Ui, *Am, *Tm, *Q, *Cq, *dtau, *ews;
     int* info;
+    unsigned* bar;                            // grid-barrier words (in the tail slack)
     RrScratch(double* scratch, int K3, int k) {
         const size_t sq = (size_t)K3 * K3;
         U = scratch;
@@ -675,6 +824,7 @@ struct RrScratch {
         dtau = Cq + (size_t)K3 * k;           // d, e, tau (3 x MAXM) + params
         info = reinterpret_cast<int*>(dtau + 3 * MAXM + 8);
         ews = dtau + 3 * MAXM + 8 + (MAXM + 64) / 2;   // inverse-iteration LU arrays
+        bar = reinterpret_cast<unsigned*>(ews + 5 * (size_t)MAXM * k);
     }
 };
 
@@ -690,7 +840,7 @@ sc_status launch_rr_setup(sc_ctx* ctx, int K3, int kp, int k, const double* GA, 
 }
 
 sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float* C32,
-                          double* theta, double* scratch) {
+                          double* theta, double* scratch, int* status) {
     if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
     RrScratch w(scratch, K3, k);
     hipStream_t st = ctx->stream;
@@ -698,7 +848,7 @@ sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float
     const dim3 gsq((unsigned)ceil_div(K3, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 0, w.Am, w.Ui, w.Tm);  // Tm = A U^-1
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 1, w.Ui, w.Tm, w.U);   // M = U^-T Tm
-    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, w.info, w.U, w.dtau);
+    SC_TRY(tridiagonalize_launch(ctx, K3, w.info, w.U, w.dtau, w.Tm, w.bar, status));   // Tm is free here
     eig_pipeline(st, k, w.info, w.U, w.dtau, theta, w.Q, w.ews);
     const dim3 gk((unsigned)ceil_div(k, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, w.info, k, 0, w.Ui, w.Q, w.Cq);    // C = U^-1 Q
@@ -716,7 +866,7 @@ sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double*
                                int* wcounter) {
     SC_TRY(launch_rr_setup(ctx, K3, kp, k, GA, GB, act, tol, scratch, status, counter, nullptr,
                            nullptr, nullptr, wcounter));
-    return launch_rr_solve(ctx, K3, kp, k, C64, C32, theta, scratch);
+    return launch_rr_solve(ctx, K3, kp, k, C64, C32, theta, scratch, status);
 }
 
 sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, double* V,
@@ -727,12 +877,19 @@ sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, d
     double* tri = M + (size_t)m * m;
     int* info = reinterpret_cast<int*>(tri + 3 * MAXM + 8);
     double* lu = tri + 3 * MAXM + 8 + (MAXM + 64) / 2;
+    unsigned* bar = reinterpret_cast<unsigned*>(lu + 5 * (size_t)MAXM * k);
+    int* flags = reinterpret_cast<int*>(bar + 2);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 4);
     hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)ceil_div((int64_t)m * m, 256)), dim3(256), 0, st,
                        (int64_t)m * m, A, M);
     hipLaunchKernelGGL(k_set_info, dim3(1), dim3(64), 0, st, info, m);
-    hipLaunchKernelGGL(k_rr_tridiag, dim3(1), dim3(NT), 0, st, info, M, tri);
+    SC_TRY(tridiagonalize_launch(ctx, m, info, M, tri, lu, bar, flags));
     eig_pipeline(st, k, info, M, tri, w, V, lu);
     SC_CHECK_LAUNCH(ctx);
+    int h = 0;
+    SC_CHECK_HIP(ctx, hipMemcpyAsync(&h, flags, sizeof h, hipMemcpyDeviceToHost, st));
+    SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
+    if (h & DEV_SYNC_TIMEOUT) return sc_fail(ctx, SC_E_HIP, "symeig: grid barrier wait timed out");
     return SC_OK;
 }
 

@@ -69,6 +69,7 @@ enum : int {
     DEV_BREAKDOWN = 4,      // unrecoverable Cholesky failure
     DEV_P_DROPPED = 8,      // P dropped in this iteration (informational)
     DEV_BREAKDOWN_RR = 16,  // basis Gram matrix of the Rayleigh-Ritz step not positive definite
+    DEV_SYNC_TIMEOUT = 32,  // a grid-barrier wait of a cooperative kernel exceeded its bound
 };
 
 // Bump allocator over a caller-provided workspace.  With base == nullptr it
@@ -195,7 +196,7 @@ sc_status launch_rr_setup(sc_ctx* ctx, int K3, int kp, int k, const double* GA, 
                           int* act, double tol, double* scratch, int* status, int* counter,
                           const int* pred, int* probe, int* probe_counter, int* wcounter);
 sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float* C32,
-                          double* theta, double* scratch);
+                          double* theta, double* scratch, int* status);
 sc_status launch_rayleigh_ritz(sc_ctx* ctx, int K3, int kp, int k, const double* GA,
                                const double* GB, int* act, double tol, double* C64, float* C32,
                                double* theta, double* scratch, int* status, int* counter,
