@@ -35,8 +35,9 @@ template <class TX>
 __global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx,
                           int normalize, double* __restrict__ Y, double* __restrict__ Yt,
                           unsigned long long* m2bits, int* status) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i0 < n;
+    const int64_t i = live ? i0 : n - 1;      // idle lanes repeat the last row, write nothing
     const TX* x = X + i * ldx;
     double s = 0.0;
     bool bad = false;
@@ -45,18 +46,27 @@ __global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t 
         bad |= !isfinite(xd);
         s = fma(xd, xd, s);
     }
-    if (bad) atomicOr(status, DEV_NUMERIC);
+    if (bad && live) atomicOr(status, DEV_NUMERIC);
     const double nrm = sqrt(s);
     double s2 = 0.0;
     for (int d = 0; d < dim; ++d) {
         double y = (double)x[d];
         if (normalize) y = nrm > 0.0 ? y / nrm : 0.0;
-        Y[i * dim + d] = y;
-        Yt[(int64_t)d * n + i] = y;
+        if (live) {
+            Y[i * dim + d] = y;
+            Yt[(int64_t)d * n + i] = y;
+        }
         s2 = fma(y, y, s2);
     }
-    // non-negative doubles order like their bit patterns
-    atomicMax(m2bits, (unsigned long long)__double_as_longlong(s2));
+    // non-negative doubles order like their bit patterns: wave maximum, one
+    // atomic per wave
+    unsigned long long b = (unsigned long long)__double_as_longlong(s2);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(b, o, 64);
+        b = t > b ? t : b;
+    }
+    if ((threadIdx.x & 63) == 0) atomicMax(m2bits, b);
 }
 
 // centre j of every restart r from a chosen row (grid: R blocks)
@@ -94,7 +104,7 @@ __global__ void k_seed_pick(int64_t n, int dim, int K, int j, const double* __re
 // For every point and every restart: D2 <- dist(y_i, c_j) (j == 0) or
 // min(D2, dist(y_i, c_j)); then the integer weights.  One pass over Y serves
 // up to RB restarts.
-constexpr int RB = 8;
+constexpr int RB = 16;
 __global__ void __launch_bounds__(TH)
 k_seed_d2(int64_t n, int dim, int K, int j, int R, const double* __restrict__ Yt,
           const double* __restrict__ C, double* __restrict__ D2, uint64_t* __restrict__ wq,
@@ -423,17 +433,32 @@ k_centroids(int dim, int K, int R, const double* __restrict__ Y,
 __global__ void k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
                            const double* __restrict__ C, const int32_t* __restrict__ lab,
                            double* __restrict__ D2) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    const int r = (int)(e / n);
-    const int64_t i = e % n;
-    const double* c = C + ((int64_t)r * K + lab[e]) * dim;
-    double acc = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        const double diff = Yt[(int64_t)d * n + i] - c[d];
-        acc = fma(diff, diff, acc);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // one pass over the point's coordinates serves up to RB restarts
+    for (int r0 = 0; r0 < R; r0 += RB) {
+        const double* c[RB];
+        double acc[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int r = min(r0 + q, R - 1);
+            c[q] = C + ((int64_t)r * K + lab[(int64_t)r * n + i]) * dim;
+            acc[q] = 0.0;
+        }
+        for (int d = 0; d < dim; ++d) {
+            const double y = Yt[(int64_t)d * n + i];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                if (r0 + q < R) {
+                    const double diff = y - c[q][d];
+                    acc[q] = fma(diff, diff, acc[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+            if (r0 + q < R) D2[(int64_t)(r0 + q) * n + i] = acc[q];
     }
-    D2[e] = acc;
 }
 
 // integer inertia per restart: block sums (exact) then one atomic per block
@@ -721,7 +746,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                                              hipMemcpyHostToDevice, st));
     }
     // exact distances to the final centres, integer inertia, best restart
-    hipLaunchKernelGGL(k_final_d2, gnr, dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C, w.lab, w.D2);
+    hipLaunchKernelGGL(k_final_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C,
+                       w.lab, w.D2);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st, n,
                        w.D2, shift, w.q);
