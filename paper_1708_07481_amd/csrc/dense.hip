@@ -46,6 +46,10 @@ struct MfF32 {
         const int64_t r = r0 + (lane >> 4);
         return (r < r1 && col < c) ? M[r * ld + col] : 0.0f;
     }
+    // fragment from an LDS tile T[k][col] (row stride ls)
+    __device__ static frag_t lds(const float* T, int ls, int k, int col, int lane) {
+        return T[(k + (lane >> 4)) * ls + col];
+    }
     __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
@@ -78,6 +82,9 @@ struct MfF32x64 {
         const int64_t r = r0 + (lane >> 4);
         return (r < r1 && col < c) ? (double)M[r * ld + col] : 0.0;
     }
+    __device__ static frag_t lds(const float* T, int ls, int k, int col, int lane) {
+        return (double)T[(k + (lane >> 4)) * ls + col];
+    }
     __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
@@ -98,6 +105,13 @@ struct MfBF16 {
             const int64_t r = rb + t;
             f[t] = to_bf16_rne((r < r1 && col < c) ? M[r * ld + col] : 0.0f);
         }
+        return f;
+    }
+    __device__ static frag_t lds(const float* T, int ls, int k, int col, int lane) {
+        frag_t f;
+        const int kb = k + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) f[t] = to_bf16_rne(T[(kb + t) * ls + col]);
         return f;
     }
     __device__ static acc_t mma(frag_t a, frag_t b, acc_t acc) {
@@ -165,6 +179,143 @@ k_gram_mfma(int64_t n, int c, int64_t chunk_rows, const typename MF::in_t* __res
             for (int v = 0; v < 4; ++v) {
                 const int a = ca + 16 * p + MF::out_row(lane, v);
                 const int b = cb + 16 * q + lc;
+                if (a < c && b < c) {
+                    p1[(int64_t)a * c + b] = (double)acc1[p][q][v];
+                    if (TWO) p2[(int64_t)a * c + b] = (double)acc2[p][q][v];
+                }
+            }
+}
+
+// The same products for FP32 data with the operand tiles staged through LDS:
+// per chunk of GL_KC rows, the A columns [ca, ca + BT) and the B columns
+// [cb, cb + BT) are loaded with 16-byte coalesced loads into registers one
+// chunk ahead (rows beyond the chunk or columns beyond c as zeros), stored to
+// LDS, and the waves read their MFMA fragments from LDS.  Rows are padded to BT + 16 floats (bank spread of the 4-row fragment
+// reads).  Needs 16-byte aligned operands and row strides.
+constexpr int GL_KC = 32;
+
+template <int BT>
+struct GramStage {
+    static constexpr int LS = BT + 16;
+    static constexpr int V4 = BT / 4;                      // float4 per staged row
+    static constexpr int PER = GL_KC * V4 / 256;            // float4 per thread
+    float4 v[PER];
+    // global -> registers (issued ahead of the compute on the previous chunk)
+    __device__ void load(const float* __restrict__ M, int64_t ld, int64_t row, int64_t r1, int col0,
+                         int c) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = threadIdx.x + 256 * u;
+            const int rr = q / V4, cc = 4 * (q % V4);
+            const int64_t r = row + rr;
+            const int col = col0 + cc;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < r1) {
+                const float* src = M + r * ld + col;
+                if (col + 3 < c) {
+                    x = *reinterpret_cast<const float4*>(src);
+                } else {
+                    if (col < c) x.x = src[0];
+                    if (col + 1 < c) x.y = src[1];
+                    if (col + 2 < c) x.z = src[2];
+                }
+            }
+            v[u] = x;
+        }
+    }
+    // registers -> LDS tile T[rr][cc] (LS and cc are multiples of 4)
+    __device__ void store(float* T) const {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int q = threadIdx.x + 256 * u;
+            const int rr = q / V4, cc = 4 * (q % V4);
+            *reinterpret_cast<float4*>(T + rr * LS + cc) = v[u];
+        }
+    }
+};
+
+template <class MF, bool TWO>
+__global__ void __launch_bounds__(256)
+k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
+           const float* __restrict__ B1, int64_t ldb1, const float* __restrict__ B2, int64_t ldb2,
+           double* __restrict__ partial, int tiles, const int* __restrict__ pred) {
+    if (pred && *pred == 0) return;
+    constexpr int WT = MF::WT;
+    constexpr int WTILE = 16 * WT;
+    constexpr int BT = 2 * WTILE;
+    constexpr int LS = BT + 16;
+    __shared__ __attribute__((aligned(16))) float As[GL_KC * LS];
+    __shared__ __attribute__((aligned(16))) float B1s[GL_KC * LS];
+    __shared__ __attribute__((aligned(16))) float B2s[TWO ? GL_KC * LS : 4];
+    int t = blockIdx.x, ti = 0;
+    while (t >= tiles - ti) {
+        t -= tiles - ti;
+        ++ti;
+    }
+    const int tj = ti + t;
+    const int chunk = blockIdx.y;
+    const int64_t r0 = (int64_t)chunk * chunk_rows;
+    const int64_t r1 = min<int64_t>(n, r0 + chunk_rows);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ca = ti * BT, cb = tj * BT;
+    const int wa = (wave >> 1) * WTILE, wb = (wave & 1) * WTILE;
+    using acc_t = typename MF::acc_t;
+    acc_t acc1[WT][WT], acc2[WT][WT];
+#pragma unroll
+    for (int p = 0; p < WT; ++p)
+#pragma unroll
+        for (int q = 0; q < WT; ++q) {
+            acc1[p][q] = acc_t{0, 0, 0, 0};
+            acc2[p][q] = acc_t{0, 0, 0, 0};
+        }
+    const int lc = lane & 15;
+    GramStage<BT> ga, gb1, gb2;
+    if (r0 < r1) {
+        ga.load(A, lda, r0, r1, ca, c);
+        gb1.load(B1, ldb1, r0, r1, cb, c);
+        if (TWO) gb2.load(B2, ldb2, r0, r1, cb, c);
+    }
+    for (int64_t row = r0; row < r1; row += GL_KC) {
+        __syncthreads();
+        ga.store(As);
+        gb1.store(B1s);
+        if (TWO) gb2.store(B2s);
+        __syncthreads();
+        if (row + GL_KC < r1) {                 // next chunk in flight during this one's MFMAs
+            ga.load(A, lda, row + GL_KC, r1, ca, c);
+            gb1.load(B1, ldb1, row + GL_KC, r1, cb, c);
+            if (TWO) gb2.load(B2, ldb2, row + GL_KC, r1, cb, c);
+        }
+#pragma unroll 2
+        for (int k = 0; k < GL_KC; k += MF::KR) {
+            typename MF::frag_t fa[WT], fb1[WT], fb2[WT];
+#pragma unroll
+            for (int p = 0; p < WT; ++p) fa[p] = MF::lds(As, LS, k, wa + 16 * p + lc, lane);
+#pragma unroll
+            for (int q = 0; q < WT; ++q) {
+                fb1[q] = MF::lds(B1s, LS, k, wb + 16 * q + lc, lane);
+                if (TWO) fb2[q] = MF::lds(B2s, LS, k, wb + 16 * q + lc, lane);
+            }
+#pragma unroll
+            for (int p = 0; p < WT; ++p)
+#pragma unroll
+                for (int q = 0; q < WT; ++q) {
+                    acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
+                    if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
+                }
+        }
+    }
+    const int64_t cc2 = (int64_t)c * c;
+    double* p1 = partial + (int64_t)chunk * (TWO ? 2 : 1) * cc2;
+    double* p2 = p1 + cc2;
+#pragma unroll
+    for (int p = 0; p < WT; ++p)
+#pragma unroll
+        for (int q = 0; q < WT; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = ca + wa + 16 * p + MF::out_row(lane, v);
+                const int b = cb + wb + 16 * q + lc;
                 if (a < c && b < c) {
                     p1[(int64_t)a * c + b] = (double)acc1[p][q][v];
                     if (TWO) p2[(int64_t)a * c + b] = (double)acc2[p][q][v];
@@ -405,6 +556,23 @@ k_residual(int64_t n, int kp, int k, T* __restrict__ S, const T* __restrict__ LS
     }
 }
 
+// per-column totals of the block partials, in place into block 0's slots:
+// workgroup (j, t) sums partial[b][t][j] over the blocks b (fixed tree order)
+__global__ void __launch_bounds__(256)
+k_residual_colsum(int nblocks, int kp, double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int j = blockIdx.x, t = blockIdx.y;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partial[((int64_t)b * 2 + t) * kp + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)t * kp + j] = red[0];
+}
+
 __global__ void __launch_bounds__(256)
 k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ partial, double lock_tol,
                     double* __restrict__ relres, double* __restrict__ hist_row, int* __restrict__ wmask,
@@ -488,12 +656,29 @@ size_t gram_partial_elems(const GramPlan& p, int nout) {
     return (size_t)p.chunks * nout * (size_t)p.c * p.c;
 }
 
+static bool aligned16(const void* ptr, int64_t ld, size_t es) {
+    return ptr == nullptr || (((uintptr_t)ptr % 16) == 0 && ((size_t)ld * es) % 16 == 0);
+}
+
 template <class MF>
 static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, int64_t lda,
                     const typename MF::in_t* B1, int64_t ldb1, const typename MF::in_t* B2,
                     int64_t ldb2, double* partial, const int* pred) {
     const int upper = p.tiles * (p.tiles + 1) / 2;
     dim3 grid(upper, p.chunks);
+    if constexpr (sizeof(typename MF::in_t) == 4) {
+        constexpr size_t es = sizeof(float);
+        if (aligned16(A, lda, es) && aligned16(B1, ldb1, es) && aligned16(B2, ldb2, es)) {
+            if (B2)
+                hipLaunchKernelGGL((k_gram_lds<MF, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
+                                   p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles, pred);
+            else
+                hipLaunchKernelGGL((k_gram_lds<MF, false>), grid, dim3(256), 0, ctx->stream, p.n,
+                                   p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles,
+                                   pred);
+            return;
+        }
+    }
     if (B2)
         hipLaunchKernelGGL((k_gram_mfma<MF, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
                            p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles, pred);
@@ -613,10 +798,15 @@ template sc_status launch_residual<double>(sc_ctx*, int64_t, int, int, double*, 
 template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, float*, const float*, int64_t,
                                           const double*, double*, int*);
 
-sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, const double* partial,
+sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, double* partial,
                                    double lock_tol, double* relres, double* hist_row, int* wmask,
                                    int* status, double* out_max, int* out_all_locked,
                                    const double* theta, int* out_restart) {
+    if (nblocks > 1) {
+        hipLaunchKernelGGL(k_residual_colsum, dim3(kp, 2), dim3(256), 0, ctx->stream, nblocks, kp,
+                           partial);
+        nblocks = 1;
+    }
     hipLaunchKernelGGL(k_residual_finalize, dim3(1), dim3(256), 0, ctx->stream, nblocks, kp, k,
                        partial, lock_tol, relres, hist_row, wmask, status, out_max,
                        out_all_locked, theta, out_restart);

@@ -31,42 +31,72 @@ constexpr double BOUND_TINY = 1e-150;    // absolute slack for zero distances
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Row norms and the normalised rows, Y (row-major) and Yt (dimension-major).
+// A workgroup takes TH rows; the rows are staged through LDS in chunks of RN_DC
+// dimensions (coalesced loads and stores), while each thread accumulates its
+// own row's sum of squares in dimension order.  The chunks are read twice:
+// once for the norm, once for the quotients.
+constexpr int RN_DC = 16;
 template <class TX>
-__global__ void k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx,
-                          int normalize, double* __restrict__ Y, double* __restrict__ Yt,
-                          unsigned long long* m2bits, int* status) {
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i0 < n;
-    const int64_t i = live ? i0 : n - 1;      // idle lanes repeat the last row, write nothing
-    const TX* x = X + i * ldx;
+__global__ void __launch_bounds__(TH)
+k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normalize,
+          double* __restrict__ Y, double* __restrict__ Yt, unsigned long long* m2bits,
+          int* status) {
+    __shared__ double xs[RN_DC][TH + 1];
+    const int64_t row0 = (int64_t)blockIdx.x * TH;
+    const int t = threadIdx.x;
+    const bool live = row0 + t < n;
     double s = 0.0;
     bool bad = false;
-    for (int d = 0; d < dim; ++d) {
-        const double xd = (double)x[d];
-        bad |= !isfinite(xd);
-        s = fma(xd, xd, s);
+    for (int pass = 0; pass < 2; ++pass) {
+        const double nrm = sqrt(s);
+        double s2 = 0.0;
+        for (int d0 = 0; d0 < dim; d0 += RN_DC) {
+            const int nd = min(RN_DC, dim - d0);
+            for (int q = t; q < TH * RN_DC; q += TH) {
+                const int r = q / RN_DC, dd = q % RN_DC;
+                const int64_t i = row0 + r;
+                xs[dd][r] = (i < n && dd < nd) ? (double)X[i * ldx + d0 + dd] : 0.0;
+            }
+            __syncthreads();
+            if (pass == 0) {
+                for (int dd = 0; dd < nd; ++dd) {
+                    const double xd = xs[dd][t];
+                    bad |= !isfinite(xd);
+                    s = fma(xd, xd, s);
+                }
+            } else {
+                for (int dd = 0; dd < nd; ++dd) {
+                    double y = xs[dd][t];
+                    if (normalize) y = nrm > 0.0 ? y / nrm : 0.0;
+                    xs[dd][t] = y;
+                    s2 = fma(y, y, s2);
+                }
+                __syncthreads();
+                for (int q = t; q < TH * RN_DC; q += TH) {     // dimension-major: rows fastest
+                    const int dd = q / TH, r = q % TH;
+                    if (dd < nd && row0 + r < n) Yt[(int64_t)(d0 + dd) * n + row0 + r] = xs[dd][r];
+                }
+                for (int q = t; q < TH * RN_DC; q += TH) {     // row-major: dimensions fastest
+                    const int r = q / RN_DC, dd = q % RN_DC;
+                    if (dd < nd && row0 + r < n) Y[(row0 + r) * dim + d0 + dd] = xs[dd][r];
+                }
+            }
+            __syncthreads();
+        }
+        if (pass == 1) {
+            // non-negative doubles order like their bit patterns: wave maximum,
+            // one atomic per wave
+            unsigned long long b = live ? (unsigned long long)__double_as_longlong(s2) : 0ull;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long u = __shfl_xor(b, o, 64);
+                b = u > b ? u : b;
+            }
+            if ((t & 63) == 0) atomicMax(m2bits, b);
+        }
     }
     if (bad && live) atomicOr(status, DEV_NUMERIC);
-    const double nrm = sqrt(s);
-    double s2 = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        double y = (double)x[d];
-        if (normalize) y = nrm > 0.0 ? y / nrm : 0.0;
-        if (live) {
-            Y[i * dim + d] = y;
-            Yt[(int64_t)d * n + i] = y;
-        }
-        s2 = fma(y, y, s2);
-    }
-    // non-negative doubles order like their bit patterns: wave maximum, one
-    // atomic per wave
-    unsigned long long b = (unsigned long long)__double_as_longlong(s2);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long t = __shfl_xor(b, o, 64);
-        b = t > b ? t : b;
-    }
-    if ((threadIdx.x & 63) == 0) atomicMax(m2bits, b);
 }
 
 // centre j of every restart r from a chosen row (grid: R blocks)

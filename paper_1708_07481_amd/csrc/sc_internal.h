@@ -172,12 +172,13 @@ sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, T* S, int64_t ld, 
 template <class T>
 sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* LS, int64_t ld,
                           const double* theta, double* partial, int* nblocks_out);
-// Finalise: relres, history row, W mask, flags; out[0] = max relres,
-// out_flags[0] = all columns locked.  With out_restart non-null it is set to
+// Finalise: column totals of the block partials (in place), then relres,
+// history row, W mask, flags; out[0] = max relres, out_flags[0] = all columns
+// locked.  With out_restart non-null it is set to
 // 1 when the iterate is inconsistent (a Ritz value outside [0, 2] by more than
 // 1e-3, or relres > 1, impossible when LX = L X), else 0.
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k,
-                                   const double* partial, double lock_tol, double* relres,
+                                   double* partial, double lock_tol, double* relres,
                                    double* hist_row, int* wmask, int* status, double* out_max,
                                    int* out_all_locked, const double* theta, int* out_restart);
 
