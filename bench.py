@@ -337,6 +337,7 @@ def main():
                                 f"restarts={restarts}"),
                    "name": args.config, "n": n, "nnz": gd.nnz, "k": k},
         "lobpcg_iterations": res.iterations,
+        "kmeans_lloyd_iterations": km.lloyd_iterations,
         "converged": res.converged,
         "max_relres": res.max_relres,
         "solver_events": {"p_drops": res.p_drops, "w_drops": res.w_drops,

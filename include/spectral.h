@@ -268,14 +268,15 @@ sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_o
  *   init_centroids float64 [K * dim] (device) or NULL; requires restarts = 1
  *   labels   int32 [n] (out); centroids float64 [K * dim] (out)
  *   inertia  host out (sum of squared distances, FP64), inertia_q host out
- *            (integer inertia), best_restart host out; each may be NULL.
+ *            (integer inertia), best_restart host out, lloyd_iterations host
+ *            out (centroid updates of the slowest restart); each may be NULL.
  * Synchronises once per Lloyd iteration.
  */
 sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx,
                            const sc_kmeans_opts* opts, const uint64_t* draws,
                            const double* init_centroids, int32_t* labels, double* centroids,
                            double* inertia, uint64_t* inertia_q, int* best_restart,
-                           void* ws, size_t ws_bytes);
+                           int* lloyd_iterations, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
  * Kernel timing on the context's stream (HIP events around every launch of

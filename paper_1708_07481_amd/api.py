@@ -211,6 +211,7 @@ class KmeansResult:
     inertia: float
     inertia_q: int
     best_restart: int
+    lloyd_iterations: int = 0
 
 
 def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.Tensor | None,
@@ -236,11 +237,12 @@ def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.T
     inertia = C.c_double()
     iq = C.c_uint64()
     br = C.c_int()
+    its = C.c_int()
     ctx.check(lib().sc_kmeans_assign(ctx.handle, n, dim, _ptr(X), X.stride(0), C.byref(opts),
                                      _ptr(draws), _ptr(init_centroids), _ptr(labels), _ptr(cent),
-                                     C.byref(inertia), C.byref(iq), C.byref(br), _ptr(ws),
-                                     nb.value), "sc_kmeans_assign")
-    return KmeansResult(labels, cent, inertia.value, iq.value, br.value)
+                                     C.byref(inertia), C.byref(iq), C.byref(br), C.byref(its),
+                                     _ptr(ws), nb.value), "sc_kmeans_assign")
+    return KmeansResult(labels, cent, inertia.value, iq.value, br.value, its.value)
 
 
 def symeig(ctx: Context, A: torch.Tensor, k: int, ws: torch.Tensor | None = None):

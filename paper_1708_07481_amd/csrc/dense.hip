@@ -728,6 +728,134 @@ sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, d
     return SC_OK;
 }
 
+// FP32 row-block products on the matrix cores: the same contract as
+// k_rowgemm (sections [a0,a1) and [b0,b1) of each row times rows of M, in
+// place), as a tall GEMM with v_mfma_f32_16x16x4_f32.  A workgroup owns
+// RG_BM rows; each of its four waves 16 * RG_WR rows and all NC 16-column
+// output tiles.  K is staged through LDS in chunks of RG_KC: the V chunk with
+// 16-byte loads (row stride RG_KC + 2 floats, so the 16-row fragment reads
+// fall in distinct banks) and the matching rows of M.  Section b is reduced
+// first: its sum alone goes to the o2 columns (which must not overlap
+// [a0, a1)); section a is then added and the total goes to the o1 columns.
+constexpr int RG_WR = 2;
+constexpr int RG_BM = 4 * 16 * RG_WR;
+constexpr int RG_KC = 32;
+
+template <int NC>
+__global__ void __launch_bounds__(256)
+k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
+               const float* __restrict__ M, int ldm, int nout, int o1, int o2) {
+    constexpr int VS = RG_KC + 2;
+    constexpr int MS = 16 * NC + ((NC % 2 == 0) ? 16 : 0);
+    __shared__ __attribute__((aligned(16))) float Vs[RG_BM * VS];
+    __shared__ __attribute__((aligned(16))) float Ms[RG_KC * MS];
+    const int64_t row0 = (int64_t)blockIdx.x * RG_BM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr0 = wave * 16 * RG_WR;
+    const int l16 = lane & 15, lk = lane >> 4;
+    mf_f4 acc[RG_WR][NC];
+#pragma unroll
+    for (int w = 0; w < RG_WR; ++w)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) acc[w][j] = mf_f4{0.f, 0.f, 0.f, 0.f};
+    // staging registers: the next chunk's V tile (float4) and M rows, loaded
+    // while the current chunk is on the matrix cores
+    constexpr int PV = RG_BM * (RG_KC / 4) / 256;
+    constexpr int PM = (RG_KC * 16 * NC + 255) / 256;
+    float4 rv[PV];
+    float rm[PM];
+    auto load = [&](int kc, int kn) {
+#pragma unroll
+        for (int u = 0; u < PV; ++u) {
+            const int q = tid + 256 * u;
+            const int r = q / (RG_KC / 4), c4 = 4 * (q % (RG_KC / 4));
+            const int64_t row = row0 + r;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row < n) {
+                const float* src = V + row * ld + kc + c4;
+                if (c4 + 3 < kn) {
+                    x = *reinterpret_cast<const float4*>(src);
+                } else {
+                    if (c4 < kn) x.x = src[0];
+                    if (c4 + 1 < kn) x.y = src[1];
+                    if (c4 + 2 < kn) x.z = src[2];
+                }
+            }
+            rv[u] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < PM; ++u) {
+            const int q = tid + 256 * u;
+            const int k = q / (16 * NC), j = q % (16 * NC);
+            rm[u] = (q < RG_KC * 16 * NC && k < kn && j < nout) ? M[(int64_t)(kc + k) * ldm + j] : 0.0f;
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int u = 0; u < PV; ++u) {
+            const int q = tid + 256 * u;
+            const int r = q / (RG_KC / 4), c4 = 4 * (q % (RG_KC / 4));
+            float* dst = Vs + r * VS + c4;
+            *reinterpret_cast<float2*>(dst) = make_float2(rv[u].x, rv[u].y);
+            *reinterpret_cast<float2*>(dst + 2) = make_float2(rv[u].z, rv[u].w);
+        }
+#pragma unroll
+        for (int u = 0; u < PM; ++u) {
+            const int q = tid + 256 * u;
+            if (q < RG_KC * 16 * NC) Ms[(q / (16 * NC)) * MS + q % (16 * NC)] = rm[u];
+        }
+    };
+    auto section = [&](int lo, int hi) {
+        if (lo < hi) load(lo, min(RG_KC, hi - lo));
+        for (int kc = lo; kc < hi; kc += RG_KC) {
+            __syncthreads();
+            stage();
+            __syncthreads();
+            if (kc + RG_KC < hi) load(kc + RG_KC, min(RG_KC, hi - kc - RG_KC));
+#pragma unroll 2
+            for (int kk = 0; kk < RG_KC; kk += 4) {
+                float af[RG_WR], bf[NC];
+#pragma unroll
+                for (int w = 0; w < RG_WR; ++w) af[w] = Vs[(wr0 + 16 * w + l16) * VS + kk + lk];
+#pragma unroll
+                for (int j = 0; j < NC; ++j) bf[j] = Ms[(kk + lk) * MS + 16 * j + l16];
+#pragma unroll
+                for (int w = 0; w < RG_WR; ++w)
+#pragma unroll
+                    for (int j = 0; j < NC; ++j)
+                        acc[w][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[w], bf[j], acc[w][j], 0, 0, 0);
+            }
+        }
+    };
+    auto store = [&](int o) {
+#pragma unroll
+        for (int w = 0; w < RG_WR; ++w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + wr0 + 16 * w + 4 * lk + v;
+                if (row >= n) continue;
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    const int col = 16 * j + l16;
+                    if (col < nout) V[row * ld + o + col] = acc[w][j][v];
+                }
+            }
+    };
+    if (b1 > b0) {
+        section(b0, b1);
+        if (o2 >= 0) store(o2);
+    }
+    section(a0, a1);
+    store(o1);
+}
+
+template <int NC>
+static void rowgemm_mfma_go(sc_ctx* ctx, int64_t n, float* V, int64_t ld, int a0, int a1, int b0,
+                            int b1, const float* M, int ldm, int nout, int o1, int o2) {
+    hipLaunchKernelGGL((k_rowgemm_mfma<NC>), dim3((unsigned)ceil_div(n, RG_BM)), dim3(256), 0,
+                       ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+}
+
 template <class T, int NC>
 static void rowgemm_go(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
                        const T* M, int ldm, int nout, int o1, int o2) {
@@ -741,6 +869,24 @@ template <class T>
 static sc_status rowgemm(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
                          const T* M, int ldm, int nout, int o1, int o2) {
     const int nc = (nout + 15) / 16;
+    if constexpr (sizeof(T) == 4) {
+        // matrix-core path: 16-byte aligned rows and section starts
+        if (((uintptr_t)V % 16) == 0 && ld % 4 == 0 && a0 % 4 == 0 && b0 % 4 == 0 && nout <= 256) {
+            switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
+                case 1: rowgemm_mfma_go<1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 2: rowgemm_mfma_go<2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 3: rowgemm_mfma_go<3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 4: rowgemm_mfma_go<4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 6: rowgemm_mfma_go<6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 8: rowgemm_mfma_go<8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 10: rowgemm_mfma_go<10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 12: rowgemm_mfma_go<12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                default: rowgemm_mfma_go<16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+            }
+            SC_CHECK_LAUNCH(ctx);
+            return SC_OK;
+        }
+    }
     switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
         case 1: rowgemm_go<T, 1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
         case 2: rowgemm_go<T, 2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;

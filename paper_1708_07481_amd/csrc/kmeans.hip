@@ -658,8 +658,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                                       int64_t ldx, const sc_kmeans_opts* opts,
                                       const uint64_t* draws, const double* init_centroids,
                                       int32_t* labels, double* centroids, double* inertia,
-                                      uint64_t* inertia_q, int* best_restart, void* ws,
-                                      size_t ws_bytes) {
+                                      uint64_t* inertia_q, int* best_restart,
+                                      int* lloyd_iterations, void* ws, size_t ws_bytes) {
     if (!ctx) return SC_E_INVAL;
     SC_TRY(km_validate(ctx, n, dim, opts));
     if (ldx < dim) return sc_fail(ctx, SC_E_INVAL, "kmeans: need ldx >= dim");
@@ -735,8 +735,10 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     SC_CHECK_LAUNCH(ctx);
     const int bits = ceil_log2_u64((uint64_t)R * K);
     int n_active = R;
+    int iterations = 0;
     std::vector<int> ch(R);
     for (int it = 1; it <= opts->max_iter && n_active > 0; ++it) {
+        iterations = it;
         // centroid update from the stable member lists
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.Cold, w.C, cent_bytes, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, K, R, w.lab, w.keys, w.vals);
@@ -804,5 +806,6 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (inertia) *inertia = inert;
     if (inertia_q) *inertia_q = qh[best];
     if (best_restart) *best_restart = best;
+    if (lloyd_iterations) *lloyd_iterations = iterations;
     return SC_OK;
 }
