@@ -109,3 +109,30 @@ def test_pure_assignment_with_given_centroids(orc):
     km = orc.kmeans(X, 4, init_centroids=C, max_iter=0, normalize=False)
     d = ((X[:, None, :] - C[None]) ** 2).sum(-1)
     assert np.array_equal(km.labels, np.argmin(d, axis=1))
+
+
+@pytest.mark.parametrize("sizes", [(1000, 257, 256), (255, 513, 1)])
+def test_centroid_is_exact_mean_of_large_clusters(orc, sizes):
+    """Centroids are member means.  Coordinates are multiples of 2^-10 below
+    2^4, so every partial sum is exact whatever the grouping: the centroid
+    must equal the exact rational mean rounded once (by the division).  A
+    block of members dropped or added twice by the blocked summation, or a
+    member counted in the wrong cluster, changes the result."""
+    from fractions import Fraction
+    rng = np.random.default_rng(7)
+    centres = np.array([[100.0, 0.0, 0.0], [0.0, 100.0, 0.0], [0.0, 0.0, 100.0]])
+    pts, truth = [], []
+    for j, s in enumerate(sizes):
+        off = rng.integers(-8192, 8192, size=(s, 3)) / 1024.0
+        pts.append(centres[j] + off)
+        truth += [j] * s
+    X = np.concatenate(pts)
+    perm = rng.permutation(X.shape[0])
+    X, truth = X[perm], np.array(truth)[perm]
+    r = orc.kmeans(X, 3, init_centroids=centres, max_iter=1, normalize=False)
+    assert np.array_equal(r.labels, truth)
+    for j in range(3):
+        mem = X[truth == j]
+        for d in range(3):
+            exact = sum(Fraction(float(v)) for v in mem[:, d]) / len(mem)
+            assert r.centroids[j, d] == float(exact), (j, d)
