@@ -100,9 +100,9 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
 }
 
 // centre j of every restart r from a chosen row (grid: R blocks)
-__global__ void k_seed_pick(int64_t n, int dim, int K, int j, const double* __restrict__ Y,
+__global__ void k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict__ Y,
                             const uint64_t* __restrict__ draws, const uint64_t* __restrict__ pref,
-                            double* __restrict__ C) {
+                            double* __restrict__ C, double* __restrict__ ccur) {
     __shared__ int64_t pick;
     const int r = blockIdx.x;
     if (threadIdx.x == 0) {
@@ -128,7 +128,11 @@ __global__ void k_seed_pick(int64_t n, int dim, int K, int j, const double* __re
     }
     __syncthreads();
     double* c = C + ((int64_t)r * K + j) * dim;
-    for (int d = threadIdx.x; d < dim; d += blockDim.x) c[d] = Y[pick * dim + d];
+    for (int d = threadIdx.x; d < dim; d += blockDim.x) {
+        const double v = Y[pick * dim + d];
+        c[d] = v;
+        ccur[(int64_t)d * Rpad + r] = v;      // this round's centres, dimension-major
+    }
 }
 
 // For every point and every restart: D2 <- dist(y_i, c_j) (j == 0) or
@@ -136,8 +140,8 @@ __global__ void k_seed_pick(int64_t n, int dim, int K, int j, const double* __re
 // up to RB restarts.
 constexpr int RB = 16;
 __global__ void __launch_bounds__(TH)
-k_seed_d2(int64_t n, int dim, int K, int j, int R, const double* __restrict__ Yt,
-          const double* __restrict__ C, double* __restrict__ D2, uint64_t* __restrict__ wq,
+k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
+          const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ wq,
           int shift) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -147,10 +151,11 @@ k_seed_d2(int64_t n, int dim, int K, int j, int R, const double* __restrict__ Yt
         for (int q = 0; q < RB; ++q) acc[q] = 0.0;
         for (int d = 0; d < dim; ++d) {
             const double y = Yt[(int64_t)d * n + i];
+            const double* cd = ccur + (int64_t)d * Rpad + r0;     // wave-uniform, contiguous
 #pragma unroll
             for (int q = 0; q < RB; ++q) {
                 if (r0 + q < R) {
-                    const double diff = y - C[((int64_t)(r0 + q) * K + j) * dim + d];
+                    const double diff = y - cd[q];
                     acc[q] = fma(diff, diff, acc[q]);
                 }
             }
@@ -425,26 +430,87 @@ __global__ void k_segments(int64_t len, const uint64_t* __restrict__ keys, int64
     if (p + 1 == len || keys[p + 1] != k) seg[2 * k + 1] = p + 1;
 }
 
-// centroid (r, j), dimension d: members in ascending vertex order.  Only
-// clusters whose member list changed since their last update are summed
+// Centroid update.  The members of cluster (r, j), in ascending vertex order
+// (the stable sort by label keeps vertex order), are cut into consecutive
+// blocks of KM_BLOCK; each block is summed in order from 0.0 by one thread per
+// dimension, then the block sums are added in order and divided by the count.
+// Only clusters whose member list changed since their last update are summed
 // again (an unchanged list gives a bitwise identical sum).
+constexpr int KM_BLOCK = 256;
+
+__device__ inline bool km_needs_update(int64_t rj, int K, const int* active, const int* dirty,
+                                       const int64_t* seg) {
+    return active[rj / K] && dirty[rj] && seg[2 * rj + 1] > seg[2 * rj];
+}
+
+// blocks per cluster (0 when the cluster is not recomputed)
+__global__ void k_block_counts(int K, int R, const int64_t* __restrict__ seg,
+                               const int* __restrict__ active, const int* __restrict__ dirty,
+                               int* __restrict__ nblk) {
+    const int64_t rj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rj >= (int64_t)R * K) return;
+    const int64_t cnt = seg[2 * rj + 1] - seg[2 * rj];
+    nblk[rj] = km_needs_update(rj, K, active, dirty, seg) ? (int)((cnt + KM_BLOCK - 1) / KM_BLOCK) : 0;
+}
+
+// exclusive scan of the block counts (one workgroup); boff[m] = total
 __global__ void __launch_bounds__(TH)
-k_centroids(int dim, int K, int R, const double* __restrict__ Y,
-            const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
-            const int* __restrict__ active, const int* __restrict__ dirty, double* __restrict__ C) {
+k_block_offsets(int m, const int* __restrict__ nblk, int* __restrict__ boff) {
+    __shared__ int part[TH];
+    const int per = (m + TH - 1) / TH;
+    const int lo = min(m, (int)threadIdx.x * per), hi = min(m, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += nblk[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < TH; ++t) {
+            const int v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+        boff[m] = acc;
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int i = lo; i < hi; ++i) {
+        boff[i] = acc;
+        acc += nblk[i];
+    }
+}
+
+// block list: slot -> (cluster, block index)
+__global__ void k_block_list(int m, const int* __restrict__ nblk, const int* __restrict__ boff,
+                             int* __restrict__ brj, int* __restrict__ bidx) {
+    const int rj = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rj >= m) return;
+    const int o = boff[rj];
+    for (int b = 0; b < nblk[rj]; ++b) {
+        brj[o + b] = rj;
+        bidx[o + b] = b;
+    }
+}
+
+// block sums: thread (slot, d), dimensions fastest (a member row is read
+// contiguously by consecutive threads)
+__global__ void __launch_bounds__(TH)
+k_centroid_blocks(int dim, int m, const double* __restrict__ Y, const uint32_t* __restrict__ members,
+                  const int64_t* __restrict__ seg, const int* __restrict__ boff,
+                  const int* __restrict__ brj, const int* __restrict__ bidx,
+                  double* __restrict__ bsum) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)R * K * dim) return;
+    const int64_t slot = e / dim;
+    if (slot >= boff[m]) return;
     const int d = (int)(e % dim);
-    const int64_t rj = e / dim;
-    const int r = (int)(rj / K);
-    if (!active[r] || !dirty[rj]) return;
-    const int64_t lo = seg[2 * rj], hi = seg[2 * rj + 1];
-    const int64_t cnt = hi - lo;
-    if (cnt <= 0) return;
+    const int rj = brj[slot];
+    const int64_t lo = seg[2 * (int64_t)rj] + (int64_t)bidx[slot] * KM_BLOCK;
+    const int64_t hi = min(seg[2 * (int64_t)rj + 1], lo + KM_BLOCK);
     const uint32_t* mem = members + lo;
+    const int64_t cnt = hi - lo;
     double s = 0.0;
     int64_t p = 0;
-    constexpr int U = 8;
+    constexpr int U = 16;
     for (; p + U <= cnt; p += U) {
         uint32_t id[U];
         double v[U];
@@ -456,7 +522,25 @@ k_centroids(int dim, int K, int R, const double* __restrict__ Y,
         for (int q = 0; q < U; ++q) s += v[q];
     }
     for (; p < cnt; ++p) s += Y[(int64_t)mem[p] * dim + d];
-    C[e] = s / (double)cnt;
+    bsum[slot * dim + d] = s;
+}
+
+// centroid (r, j), dimension d: block sums in order, divided by the count
+__global__ void __launch_bounds__(TH)
+k_centroid_total(int dim, int K, int R, const int64_t* __restrict__ seg,
+                 const int* __restrict__ active, const int* __restrict__ dirty,
+                 const int* __restrict__ nblk, const int* __restrict__ boff,
+                 const double* __restrict__ bsum, double* __restrict__ C) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)R * K * dim) return;
+    const int d = (int)(e % dim);
+    const int64_t rj = e / dim;
+    if (!km_needs_update(rj, K, active, dirty, seg)) return;
+    const int64_t cnt = seg[2 * rj + 1] - seg[2 * rj];
+    const int64_t o = boff[rj];
+    double c = 0.0;
+    for (int b = 0; b < nblk[rj]; ++b) c += bsum[(o + b) * dim + d];
+    C[e] = c / (double)cnt;
 }
 
 // exact squared distance of every point to its assigned centre
@@ -568,8 +652,11 @@ struct KmWs {
     uint64_t *wq, *scan_tmp, *keys, *keys_alt, *radix_tmp;
     uint32_t *vals, *vals_alt, *pts;
     int32_t* lab;
-    int *changed, *active, *cnt, *status, *dirty;
+    int *changed, *active, *cnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
     int64_t* seg;
+    double *bsum, *ccur;
+    int64_t max_blocks;
+    int Rpad;
     unsigned long long *m2, *q;
 };
 
@@ -603,6 +690,15 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.status = c.take<int>(1);
     w.dirty = c.take<int>((size_t)R * K);
     w.seg = c.take<int64_t>(2 * (size_t)R * K);
+    // blocks of all clusters: sum over clusters of ceil(count / KM_BLOCK)
+    w.max_blocks = (int64_t)R * ceil_div(n, KM_BLOCK) + (int64_t)R * K;
+    w.nblk = c.take<int>((size_t)R * K);
+    w.boff = c.take<int>((size_t)R * K + 1);
+    w.brj = c.take<int>((size_t)w.max_blocks);
+    w.bidx = c.take<int>((size_t)w.max_blocks);
+    w.bsum = c.take<double>((size_t)w.max_blocks * dim);
+    w.Rpad = (R + RB - 1) / RB * RB;
+    w.ccur = c.take<double>((size_t)w.Rpad * dim);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
     return c.size();
@@ -712,12 +808,12 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     } else {
         uint64_t* pref = w.keys;            // prefix sums of the weights (scan output)
         for (int j = 0; j < K; ++j) {
-            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Y, draws, pref,
-                               w.C);
+            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Rpad, w.Y,
+                               draws, pref, w.C, w.ccur);
             SC_CHECK_LAUNCH(ctx);
             if (j + 1 == K) break;
-            hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, j, R,
-                               w.Yt, w.C, w.D2, w.wq, shift);
+            hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, R, w.Rpad,
+                               j, w.Yt, w.ccur, w.D2, w.wq, shift);
             SC_CHECK_LAUNCH(ctx);
             SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
         }
@@ -747,8 +843,19 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div(2 * (int64_t)R * K, TH)), dim3(TH), 0, st, w.seg,
                            2 * (int64_t)R * K);
         hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, nr, w.keys, w.seg);
-        hipLaunchKernelGGL(k_centroids, gcent, dim3(TH), 0, st, dim, K, R, w.Y, w.vals, w.seg,
-                           w.active, w.dirty, w.C);
+        {
+            const int m = R * K;
+            hipLaunchKernelGGL(k_block_counts, dim3(ceil_div(m, TH)), dim3(TH), 0, st, K, R, w.seg,
+                               w.active, w.dirty, w.nblk);
+            hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(TH), 0, st, m, w.nblk, w.boff);
+            hipLaunchKernelGGL(k_block_list, dim3(ceil_div(m, TH)), dim3(TH), 0, st, m, w.nblk,
+                               w.boff, w.brj, w.bidx);
+            hipLaunchKernelGGL(k_centroid_blocks, dim3((unsigned)ceil_div(w.max_blocks * dim, TH)),
+                               dim3(TH), 0, st, dim, m, w.Y, w.vals, w.seg, w.boff, w.brj, w.bidx,
+                               w.bsum);
+            hipLaunchKernelGGL(k_centroid_total, gcent, dim3(TH), 0, st, dim, K, R, w.seg, w.active,
+                               w.dirty, w.nblk, w.boff, w.bsum, w.C);
+        }
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
                            R * K);
         hipLaunchKernelGGL(k_delta, dim3(R), dim3(TH), 0, st, K, dim, w.C, w.Cold, w.active, w.delta,
