@@ -412,22 +412,29 @@ k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, double* __restrict__
     }
 }
 
-__global__ void k_label_keys(int64_t n, int K, int R, const int32_t* __restrict__ lab,
-                             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+// sort keys of the active restarts: the label, with the vertex index as value
+// (restart r occupies positions [r n, (r + 1) n) of both arrays)
+__global__ void k_label_keys(int64_t n, int R, const int* __restrict__ active,
+                             const int32_t* __restrict__ lab, uint64_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R) return;
-    const int r = (int)(e / n);
-    keys[e] = (uint64_t)((int64_t)r * K + lab[e]);
+    if (e >= n * R || !active[e / n]) return;
+    keys[e] = (uint64_t)lab[e];
     vals[e] = (uint32_t)(e % n);
 }
 
-// segment [start, end) of every key in the sorted list (empty keys: 0, 0)
-__global__ void k_segments(int64_t len, const uint64_t* __restrict__ keys, int64_t* __restrict__ seg) {
+// segment [start, end) of every (restart, label) in the per-restart sorted
+// lists (empty: 0, 0); positions are global (r n + p)
+__global__ void k_segments(int64_t n, int K, int R, const int* __restrict__ active,
+                           const uint64_t* __restrict__ keys, int64_t* __restrict__ seg) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= len) return;
+    if (p >= n * R) return;
+    const int64_t r = p / n, q = p - r * n;
+    if (!active[r]) return;
     const uint64_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) seg[2 * k] = p;
-    if (p + 1 == len || keys[p + 1] != k) seg[2 * k + 1] = p + 1;
+    const int64_t g = r * K + (int64_t)k;
+    if (q == 0 || keys[p - 1] != k) seg[2 * g] = p;
+    if (q + 1 == n || keys[p + 1] != k) seg[2 * g + 1] = p + 1;
 }
 
 // Centroid update.  The members of cluster (r, j), in ascending vertex order
@@ -829,7 +836,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
                        R * K, 1);
     SC_CHECK_LAUNCH(ctx);
-    const int bits = ceil_log2_u64((uint64_t)R * K);
+    const int bits = ceil_log2_u64((uint64_t)K);
     int n_active = R;
     int iterations = 0;
     std::vector<int> ch(R);
@@ -837,12 +844,17 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         iterations = it;
         // centroid update from the stable member lists
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.Cold, w.C, cent_bytes, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, K, R, w.lab, w.keys, w.vals);
+        hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, R, w.active, w.lab, w.keys, w.vals);
         SC_CHECK_LAUNCH(ctx);
-        SC_TRY(radix_sort_pairs(ctx, w.keys, w.vals, w.keys_alt, w.vals_alt, nr, bits, w.radix_tmp));
+        // stable sort by label of each active restart's own range
+        for (int r = 0; r < R; ++r)
+            if (act_h[r])
+                SC_TRY(radix_sort_pairs(ctx, w.keys + (int64_t)r * n, w.vals + (int64_t)r * n,
+                                        w.keys_alt + (int64_t)r * n, w.vals_alt + (int64_t)r * n, n,
+                                        bits, w.radix_tmp));
         hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div(2 * (int64_t)R * K, TH)), dim3(TH), 0, st, w.seg,
                            2 * (int64_t)R * K);
-        hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, nr, w.keys, w.seg);
+        hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, n, K, R, w.active, w.keys, w.seg);
         {
             const int m = R * K;
             hipLaunchKernelGGL(k_block_counts, dim3(ceil_div(m, TH)), dim3(TH), 0, st, K, R, w.seg,

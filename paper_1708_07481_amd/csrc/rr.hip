@@ -320,10 +320,13 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
 // Vectors of a cluster are orthonormalised in index order; vector q is
 // projected against all earlier members at once (classical Gram-Schmidt,
 // applied twice) and normalised.  Clusters are independent: workgroup g takes
-// clusters g, g + gridDim, ...
+// clusters g, g + gridDim, ...  A cluster is first copied to the scratch Wt
+// with each vector contiguous (V itself is row-major, one row per entry), so
+// every dot product and update reads consecutive addresses; it is copied back
+// at the end.  Wt holds >= k * m doubles (vector q at Wt + q m).
 __global__ void __launch_bounds__(NT)
 k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
-          const double* __restrict__ w, double* __restrict__ V, int ldv) {
+          const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ Wt) {
     __shared__ double red[NWAVE + 1];
     __shared__ double dots[MAXM];
     const int m = info[0];
@@ -335,32 +338,43 @@ k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
         int c1 = c0 + 1;
         while (c1 < k && w[c1] - w[c1 - 1] <= ctol) ++c1;
         if (c1 - c0 > 1 && cl % gridDim.x == blockIdx.x) {
+            const int cs = c1 - c0;
+            for (int e = tid; e < cs * m; e += NT) {
+                const int r = e / cs, q = c0 + e % cs;      // consecutive threads: one row of V
+                Wt[(int64_t)q * m + r] = V[(int64_t)r * ldv + q];
+            }
+            __syncthreads();
             for (int q = c0; q < c1; ++q) {
+                double* vq = Wt + (int64_t)q * m;
                 for (int pass = 0; pass < 2 && q > c0; ++pass) {
                     // dots with the earlier members, one wave per member
                     for (int pp = c0 + wave; pp < q; pp += NWAVE) {
+                        const double* vp = Wt + (int64_t)pp * m;
                         double part = 0.0;
-                        for (int r = lane; r < m; r += 64)
-                            part = fma(V[(int64_t)r * ldv + pp], V[(int64_t)r * ldv + q], part);
+                        for (int r = lane; r < m; r += 64) part = fma(vp[r], vq[r], part);
 #pragma unroll
                         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
                         if (lane == 0) dots[pp - c0] = part;
                     }
                     __syncthreads();
                     for (int r = tid; r < m; r += NT) {
-                        double x = V[(int64_t)r * ldv + q];
-                        for (int pp = c0; pp < q; ++pp) x = fma(-dots[pp - c0], V[(int64_t)r * ldv + pp], x);
-                        V[(int64_t)r * ldv + q] = x;
+                        double x = vq[r];
+                        for (int pp = c0; pp < q; ++pp) x = fma(-dots[pp - c0], Wt[(int64_t)pp * m + r], x);
+                        vq[r] = x;
                     }
                     __syncthreads();
                 }
                 double part = 0.0;
-                for (int r = tid; r < m; r += NT)
-                    part = fma(V[(int64_t)r * ldv + q], V[(int64_t)r * ldv + q], part);
+                for (int r = tid; r < m; r += NT) part = fma(vq[r], vq[r], part);
                 const double inv = 1.0 / sqrt(block_sum(part, red));
-                for (int r = tid; r < m; r += NT) V[(int64_t)r * ldv + q] *= inv;
+                for (int r = tid; r < m; r += NT) vq[r] *= inv;
                 __syncthreads();
             }
+            for (int e = tid; e < cs * m; e += NT) {
+                const int r = e / cs, q = c0 + e % cs;
+                V[(int64_t)r * ldv + q] = Wt[(int64_t)q * m + r];
+            }
+            __syncthreads();
         }
         c0 = c1;
     }
@@ -767,7 +781,8 @@ static void eig_pipeline(hipStream_t st, int k, const int* info, const double* M
     hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, tri, w);
     hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0, st, k, info, tri, w,
                        V, k, lu);
-    hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k);
+    // the inverse-iteration LU arrays (5 MAXM k doubles) are free again: cluster scratch
+    hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k, lu);
     hipLaunchKernelGGL(k_rr_back, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, M, tri, V);
 }
 
