@@ -149,15 +149,31 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
         double acc[RB];
 #pragma unroll
         for (int q = 0; q < RB; ++q) acc[q] = 0.0;
-        for (int d = 0; d < dim; ++d) {
-            const double y = Yt[(int64_t)d * n + i];
-            const double* cd = ccur + (int64_t)d * Rpad + r0;     // wave-uniform, contiguous
+        // all RB accumulators, no predicates: ccur is zero beyond restart R, and
+        // those lanes' sums are never stored (wide uniform loads, pipelined)
+        constexpr int DU = 8;                 // coordinates loaded ahead of their use
+        int d = 0;
+        for (; d + DU <= dim; d += DU) {
+            double y[DU];
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                if (r0 + q < R) {
-                    const double diff = y - cd[q];
+            for (int u = 0; u < DU; ++u) y[u] = Yt[(int64_t)(d + u) * n + i];
+#pragma unroll
+            for (int u = 0; u < DU; ++u) {
+                const double* cd = ccur + (int64_t)(d + u) * Rpad + r0;   // wave-uniform, contiguous
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const double diff = y[u] - cd[q];
                     acc[q] = fma(diff, diff, acc[q]);
                 }
+            }
+        }
+        for (; d < dim; ++d) {
+            const double y = Yt[(int64_t)d * n + i];
+            const double* cd = ccur + (int64_t)d * Rpad + r0;
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const double diff = y - cd[q];
+                acc[q] = fma(diff, diff, acc[q]);
             }
         }
 #pragma unroll
@@ -814,6 +830,9 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.C, init_centroids, cent_bytes, hipMemcpyDeviceToDevice, st));
     } else {
         uint64_t* pref = w.keys;            // prefix sums of the weights (scan output)
+        // this round's centres of restarts >= R stay 0.0
+        hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div((int64_t)w.Rpad * dim, TH)), dim3(TH), 0, st,
+                           reinterpret_cast<int64_t*>(w.ccur), (int64_t)w.Rpad * dim);
         for (int j = 0; j < K; ++j) {
             hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Rpad, w.Y,
                                draws, pref, w.C, w.ccur);
