@@ -39,7 +39,7 @@ struct MfF32 {
     using acc_t = mf_f4;
     using frag_t = float;
     static constexpr int KR = 4;
-    static constexpr int WT = 4;
+    static constexpr int WT = 5;
     __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
     __device__ static frag_t load(const float* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
                                   int col, int c, int lane) {
@@ -94,7 +94,7 @@ struct MfBF16 {
     using acc_t = mf_f4;
     using frag_t = mf_bf8;
     static constexpr int KR = 32;
-    static constexpr int WT = 4;
+    static constexpr int WT = 5;
     __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
     __device__ static frag_t load(const float* __restrict__ M, int64_t ld, int64_t r0, int64_t r1,
                                   int col, int c, int lane) {
@@ -638,9 +638,10 @@ GramPlan gram_plan(int64_t n, int c, int gmode_bytes) {
     GramPlan p;
     p.n = n;
     p.c = c;
-    // workgroup tile edge: 128 (FP32 / BF16 matrix-core path), 64 (FP64
+    // workgroup tile edge: 160 (FP32 / BF16 matrix-core path: 2 x 2 waves of
+    // 5 x 5 MFMA tiles, so k = 160 and 3k = 480 need no padding), 64 (FP64
     // accumulation: FP64 data, or FP32 data widened)
-    p.bt = gmode_bytes == 8 ? 64 : 128;
+    p.bt = gmode_bytes == 8 ? 64 : 160;
     p.tiles = (int)ceil_div(c, p.bt);
     const int upper = p.tiles * (p.tiles + 1) / 2;
     // enough workgroups to fill 256 CUs several times, each chunk >= 512 rows
@@ -694,7 +695,7 @@ sc_status launch_gram(sc_ctx* ctx, const GramPlan& p, const T* A, int64_t lda, c
     if constexpr (sizeof(T) == 8) {
         gram_go<MfF64>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
     } else {
-        const int bt = gmode == GRAM_F32_EXACT ? 64 : 128;
+        const int bt = gmode == GRAM_F32_EXACT ? 64 : 160;
         if (p.bt != bt) return sc_fail(ctx, SC_E_INVAL, "gram: plan tile %d, kernel tile %d", p.bt, bt);
         if (gmode == GRAM_BF16)
             gram_go<MfBF16>(ctx, p, A, lda, B1, ldb1, B2, ldb2, partial, pred);
