@@ -142,7 +142,7 @@ constexpr int RB = 16;
 __global__ void __launch_bounds__(TH)
 k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
           const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ wq,
-          int shift) {
+          int shift, int32_t* __restrict__ lab, double* __restrict__ sec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int r0 = 0; r0 < R; r0 += RB) {
@@ -176,17 +176,45 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
                 acc[q] = fma(diff, diff, acc[q]);
             }
         }
+        // D2 = least distance so far (the seeding weights); lab / sec = its
+        // centre and the second least distance, which after the last centre
+        // are the first assignment (ties to the lowest centre)
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
             if (r0 + q < R) {
                 const int64_t e = (int64_t)(r0 + q) * n + i;
-                double v = D2[e];
-                if (j == 0 || acc[q] < v) v = acc[q];
+                const double a = acc[q];
+                double v;
+                if (j == 0) {
+                    v = a;
+                    sec[e] = INFINITY;
+                    lab[e] = 0;
+                } else {
+                    v = D2[e];
+                    if (a < v) {
+                        sec[e] = v;
+                        v = a;
+                        lab[e] = j;
+                    } else if (a < sec[e]) {
+                        sec[e] = a;
+                    }
+                }
                 D2[e] = v;
                 wq[e] = (uint64_t)floor(ldexp(v, shift));
             }
         }
     }
+}
+
+// first assignment from the seeding's distances: Hamerly bounds from the
+// least (D2) and second least (sec, stored in lb) distance
+__global__ void k_first_bounds(int64_t nr, const double* __restrict__ D2, double* __restrict__ ub,
+                               double* __restrict__ lb) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nr) return;
+    ub[e] = sqrt(D2[e]) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+    const double s = lb[e];
+    lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
 }
 
 // Ct[r][d][j] = C[r][j][d] for j < K; columns K <= j < Kpad hold +inf, a
@@ -837,21 +865,27 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Rpad, w.Y,
                                draws, pref, w.C, w.ccur);
             SC_CHECK_LAUNCH(ctx);
-            if (j + 1 == K) break;
+            // distances to centre j (also after the last one: they complete the
+            // first assignment)
             hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, R, w.Rpad,
-                               j, w.Yt, w.ccur, w.D2, w.wq, shift);
+                               j, w.Yt, w.ccur, w.D2, w.wq, shift, w.lab, w.lb);
             SC_CHECK_LAUNCH(ctx);
-            SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
+            if (j + 1 < K) SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
         }
     }
     const dim3 gcent((unsigned)ceil_div((int64_t)R * K * dim, TH));
     const int Kpad = assign_kpad(K);
     const dim3 gcentp((unsigned)ceil_div((int64_t)R * Kpad * dim, TH));
-    // first assignment: every point of every restart
+    // first assignment: every point of every restart (after a seeding, the
+    // seeding rounds already hold the exact least and second least distances)
     hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C, w.Ct);
-    hipLaunchKernelGGL(k_fill_lists, gnr, dim3(TH), 0, st, n, R, w.pts, w.cnt);
-    SC_CHECK_LAUNCH(ctx);
-    assign(ctx, n, dim, K, R, w, 1);
+    if (init_centroids) {
+        hipLaunchKernelGGL(k_fill_lists, gnr, dim3(TH), 0, st, n, R, w.pts, w.cnt);
+        SC_CHECK_LAUNCH(ctx);
+        assign(ctx, n, dim, K, R, w, 1);
+    } else {
+        hipLaunchKernelGGL(k_first_bounds, gnr, dim3(TH), 0, st, nr, w.D2, w.ub, w.lb);
+    }
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
                        R * K, 1);
     SC_CHECK_LAUNCH(ctx);
