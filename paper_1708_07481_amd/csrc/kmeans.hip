@@ -139,17 +139,20 @@ __global__ void k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const do
 // min(D2, dist(y_i, c_j)); then the integer weights.  One pass over Y serves
 // up to RB restarts.
 constexpr int RB = 16;
+// WB restarts per pass over the points (WB <= RB; the launch picks the
+// smallest width covering the restarts, so no accumulator is wasted)
+template <int WB>
 __global__ void __launch_bounds__(TH)
 k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
           const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ wq,
           int shift, int32_t* __restrict__ lab, double* __restrict__ sec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    for (int r0 = 0; r0 < R; r0 += RB) {
-        double acc[RB];
+    for (int r0 = 0; r0 < R; r0 += WB) {
+        double acc[WB];
 #pragma unroll
-        for (int q = 0; q < RB; ++q) acc[q] = 0.0;
-        // all RB accumulators, no predicates: ccur is zero beyond restart R, and
+        for (int q = 0; q < WB; ++q) acc[q] = 0.0;
+        // all WB accumulators, no predicates: ccur is zero beyond restart R, and
         // those lanes' sums are never stored (wide uniform loads, pipelined)
         constexpr int DU = 8;                 // coordinates loaded ahead of their use
         int d = 0;
@@ -161,7 +164,7 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
             for (int u = 0; u < DU; ++u) {
                 const double* cd = ccur + (int64_t)(d + u) * Rpad + r0;   // wave-uniform, contiguous
 #pragma unroll
-                for (int q = 0; q < RB; ++q) {
+                for (int q = 0; q < WB; ++q) {
                     const double diff = y[u] - cd[q];
                     acc[q] = fma(diff, diff, acc[q]);
                 }
@@ -171,7 +174,7 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
             const double y = Yt[(int64_t)d * n + i];
             const double* cd = ccur + (int64_t)d * Rpad + r0;
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
+            for (int q = 0; q < WB; ++q) {
                 const double diff = y - cd[q];
                 acc[q] = fma(diff, diff, acc[q]);
             }
@@ -180,7 +183,7 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
         // centre and the second least distance, which after the last centre
         // are the first assignment (ties to the lowest centre)
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
+        for (int q = 0; q < WB; ++q) {
             if (r0 + q < R) {
                 const int64_t e = (int64_t)(r0 + q) * n + i;
                 const double a = acc[q];
@@ -595,17 +598,20 @@ k_centroid_total(int dim, int K, int R, const int64_t* __restrict__ seg,
 }
 
 // exact squared distance of every point to its assigned centre
-__global__ void k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
-                           const double* __restrict__ C, const int32_t* __restrict__ lab,
-                           double* __restrict__ D2) {
+template <int WB>
+__global__ void __launch_bounds__(TH)
+k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
+           const double* __restrict__ C, const int32_t* __restrict__ lab,
+           double* __restrict__ D2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // one pass over the point's coordinates serves up to RB restarts
-    for (int r0 = 0; r0 < R; r0 += RB) {
-        const double* c[RB];
-        double acc[RB];
+    // one pass over the point's coordinates serves up to WB restarts; lanes of
+    // restarts >= R repeat restart R - 1 and are not stored (no predicates)
+    for (int r0 = 0; r0 < R; r0 += WB) {
+        const double* c[WB];
+        double acc[WB];
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
+        for (int q = 0; q < WB; ++q) {
             const int r = min(r0 + q, R - 1);
             c[q] = C + ((int64_t)r * K + lab[(int64_t)r * n + i]) * dim;
             acc[q] = 0.0;
@@ -613,15 +619,13 @@ __global__ void k_final_d2(int64_t n, int dim, int K, int R, const double* __res
         for (int d = 0; d < dim; ++d) {
             const double y = Yt[(int64_t)d * n + i];
 #pragma unroll
-            for (int q = 0; q < RB; ++q) {
-                if (r0 + q < R) {
-                    const double diff = y - c[q][d];
-                    acc[q] = fma(diff, diff, acc[q]);
-                }
+            for (int q = 0; q < WB; ++q) {
+                const double diff = y - c[q][d];
+                acc[q] = fma(diff, diff, acc[q]);
             }
         }
 #pragma unroll
-        for (int q = 0; q < RB; ++q)
+        for (int q = 0; q < WB; ++q)
             if (r0 + q < R) D2[(int64_t)(r0 + q) * n + i] = acc[q];
     }
 }
@@ -775,6 +779,22 @@ void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
                        w.changed, w.dirty, first);
 }
 
+template <int WB>
+void seed_d2_go(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
+    hipLaunchKernelGGL((k_seed_d2<WB>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, dim, R,
+                       Rpad, j, w.Yt, w.ccur, w.D2, w.wq, shift, w.lab, w.lb);
+}
+
+void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
+    if (R <= 1) seed_d2_go<1>(ctx, n, dim, R, Rpad, j, w, shift);
+    else if (R <= 2) seed_d2_go<2>(ctx, n, dim, R, Rpad, j, w, shift);
+    else if (R <= 4) seed_d2_go<4>(ctx, n, dim, R, Rpad, j, w, shift);
+    else if (R <= 8) seed_d2_go<8>(ctx, n, dim, R, Rpad, j, w, shift);
+    else if (R <= 10) seed_d2_go<10>(ctx, n, dim, R, Rpad, j, w, shift);
+    else if (R <= 12) seed_d2_go<12>(ctx, n, dim, R, Rpad, j, w, shift);
+    else seed_d2_go<16>(ctx, n, dim, R, Rpad, j, w, shift);
+}
+
 void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
     switch (assign_width(K)) {
         case 2: launch_assign<2>(ctx, n, dim, K, R, w, first); break;
@@ -867,8 +887,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             SC_CHECK_LAUNCH(ctx);
             // distances to centre j (also after the last one: they complete the
             // first assignment)
-            hipLaunchKernelGGL(k_seed_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, R, w.Rpad,
-                               j, w.Yt, w.ccur, w.D2, w.wq, shift, w.lab, w.lb);
+            seed_d2(ctx, n, dim, R, w.Rpad, j, w, shift);
             SC_CHECK_LAUNCH(ctx);
             if (j + 1 < K) SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
         }
@@ -950,8 +969,15 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                                              hipMemcpyHostToDevice, st));
     }
     // exact distances to the final centres, integer inertia, best restart
-    hipLaunchKernelGGL(k_final_d2, dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R, w.Yt, w.C,
-                       w.lab, w.D2);
+    if (R <= 4)
+        hipLaunchKernelGGL((k_final_d2<4>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
+                           w.Yt, w.C, w.lab, w.D2);
+    else if (R <= 10)
+        hipLaunchKernelGGL((k_final_d2<10>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
+                           w.Yt, w.C, w.lab, w.D2);
+    else
+        hipLaunchKernelGGL((k_final_d2<16>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
+                           w.Yt, w.C, w.lab, w.D2);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st, n,
                        w.D2, shift, w.q);
