@@ -16,6 +16,7 @@
 // centre displacements).  The bounds are inflated by a relative margin far
 // above the rounding error of the distance chain, so a skipped point's
 // computed argmin is exactly the one a full scan would give.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -350,6 +351,231 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
         ub[e] = sqrt(b) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
         lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
     }
+}
+
+// Half the separation of every centre pair, hd[r][a][j] <= ||c_a - c_j|| / 2
+// (deflated by the bound margin; 0 on the diagonal), from the transposed
+// centroid table.  Elkan's lemma: a point with ||y - c_a|| <= ub < hd[a][j]
+// is strictly nearer to c_a than to c_j.
+__global__ void __launch_bounds__(TH)
+k_half_sep(int K, int Kpad, int dim, const double* __restrict__ Ct, const int* __restrict__ active,
+           double* __restrict__ hd) {
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int64_t e = (int64_t)blockIdx.x * TH + threadIdx.x;
+    if (e >= (int64_t)K * K) return;
+    const int a = (int)(e / K), j = (int)(e % K);
+    const double* ct = Ct + (int64_t)r * dim * Kpad;
+    double s = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        const double t = ct[(int64_t)d * Kpad + a] - ct[(int64_t)d * Kpad + j];
+        s = fma(t, t, s);
+    }
+    hd[(int64_t)r * K * K + e] = a == j ? 0.0 : 0.5 * sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+}
+
+// sort keys of a scan list: the point's current label, with the point as value
+__global__ void k_list_keys(int64_t n, int c, const int32_t* __restrict__ lab,
+                            const uint32_t* __restrict__ pts, uint64_t* __restrict__ keys) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < c) keys[q] = (uint64_t)lab[pts[q]];
+}
+
+// Lloyd scan of the listed points with Elkan pruning.  Each wave owns 64
+// consecutive list entries; a long list is ordered by current label, so a
+// wave's points share one or a few labels.
+//   1. The exact distance to the assigned centre a gives a tight bound u.
+//   2. A centre j with u < hd[a][j] cannot be nearer than c_a.  A point that
+//      cannot rule out more than PR_WIDE centres is "narrow"; a wider one is
+//      handed to the full scan (appended to the list fl), and so is every
+//      point of a short, unordered list.
+//   3. The wave scans the union of its narrow points' remaining candidates, in
+//      ascending order, JB at a time.
+// Rows are staged in LDS PR_DC dimensions at a time (the next chunk is loaded
+// into registers while the current one is used); centre coordinates come from
+// the transposed table.  Every distance is the full fma chain in dimension
+// order, and a ruled-out centre is strictly farther than c_a, so the argmin
+// (lowest index on ties) equals a full scan's.  The new lower bound covers the
+// ruled-out centres by the triangle inequality,
+// ||y - c_j|| >= 2 hd[a][j] - ||y - c_a||.
+constexpr int PR_DC = 8;
+constexpr int PR_KMAX = 1024;
+constexpr int PR_WIDE = 16;
+constexpr int PR_SORT_MIN = 2048;       // lists at least this long are ordered by label
+
+__device__ inline void pr_load(double (&v)[PR_DC], const double* __restrict__ Y,
+                               const uint32_t* pidw, int dim, int d0, int lane) {
+#pragma unroll
+    for (int t = 0; t < PR_DC; ++t) {
+        const int q = t * 64 + lane;
+        const int p = q / PR_DC, dd = q % PR_DC;
+        v[t] = d0 + dd < dim ? Y[(int64_t)pidw[p] * dim + d0 + dd] : 0.0;
+    }
+}
+
+__device__ inline void pr_store(double (*ys)[65], const double (&v)[PR_DC], int lane) {
+#pragma unroll
+    for (int t = 0; t < PR_DC; ++t) {
+        const int q = t * 64 + lane;
+        ys[q % PR_DC][q / PR_DC] = v[t];
+    }
+}
+
+template <int JB>
+__global__ void __launch_bounds__(TH)
+k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
+                const double* __restrict__ Ct, const double* __restrict__ hd,
+                const uint32_t* __restrict__ pts, const int* __restrict__ cnt,
+                const int* __restrict__ active, int32_t* __restrict__ lab, double* __restrict__ ub,
+                double* __restrict__ lb, int* __restrict__ changed, int* __restrict__ dirty,
+                uint32_t* __restrict__ fl, int* __restrict__ fcnt) {
+    constexpr int NW = TH / 64;
+    __shared__ double ys[NW][PR_DC][65];
+    __shared__ uint32_t pid[NW][64];
+    __shared__ uint16_t cand[NW][PR_KMAX];
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int c = cnt[r];
+    const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int q0 = (blockIdx.x * NW + wave) * 64;
+    if (q0 >= c) return;                    // wave-uniform; no workgroup barrier below
+    const int np = min(64, c - q0);
+    const bool live = lane < np;
+    const uint32_t i = pts[(int64_t)r * n + q0 + min(lane, np - 1)];
+    const int64_t e = (int64_t)r * n + i;
+    const bool ordered = c >= PR_SORT_MIN;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    if (!ordered) {
+        // short list: every point goes to the full scan
+        const unsigned long long mask = __ballot(live);
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&fcnt[r], (int)__popcll(mask));
+        base = __shfl(base, 0);
+        if (live) fl[(int64_t)r * n + base + __popcll(mask & lanes_below)] = i;
+        return;
+    }
+    pid[wave][lane] = i;
+    const int a = lab[e];
+    const double* Ctr = Ct + (int64_t)r * dim * Kpad;
+    __builtin_amdgcn_wave_barrier();
+    // 1. exact distance to the assigned centre
+    double own = 0.0;
+    {
+        const double* ca = Ctr + a;
+        double v[PR_DC];
+        pr_load(v, Y, pid[wave], dim, 0, lane);
+        for (int d0 = 0; d0 < dim; d0 += PR_DC) {
+            pr_store(ys[wave], v, lane);
+            if (d0 + PR_DC < dim) pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+            __builtin_amdgcn_wave_barrier();
+            const int nd = min(PR_DC, dim - d0);
+            for (int dd = 0; dd < nd; ++dd) {
+                const double diff = ys[wave][dd][lane] - ca[(int64_t)(d0 + dd) * Kpad];
+                own = fma(diff, diff, own);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    const double u = sqrt(own) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+    const double* hdr = hd + ((int64_t)r * K + a) * K;
+    // 2. how many centres the point cannot rule out (its own included)
+    int nkeep = 0;
+    for (int j0 = 0; j0 < K; j0 += 16) {
+        double h[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) h[t] = j0 + t < K ? hdr[j0 + t] : INFINITY;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) nkeep += !(u < h[t]);
+    }
+    const bool wide = live && nkeep > PR_WIDE;
+    const bool narrow = live && !wide;
+    {
+        const unsigned long long mask = __ballot(wide);
+        if (mask) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&fcnt[r], (int)__popcll(mask));
+            base = __shfl(base, 0);
+            if (wide) fl[(int64_t)r * n + base + __popcll(mask & lanes_below)] = i;
+        }
+    }
+    // the narrow points' candidates besides their own centre (wave-uniform
+    // ascending list), and per point the least half-separation of the rest
+    int m = 0;
+    double hmin = INFINITY;
+    for (int j0 = 0; j0 < K; j0 += 16) {
+        double h[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) h[t] = j0 + t < K ? hdr[j0 + t] : INFINITY;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int j = j0 + t;
+            const bool keep = narrow && j < K && j != a && !(u < h[t]);
+            const unsigned long long mask = __ballot(keep);
+            if (mask) {
+                if (lane == 0) cand[wave][m] = (uint16_t)j;
+                ++m;
+            } else if (narrow && j < K && j != a) {
+                hmin = fmin(hmin, h[t]);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // 3. scan of the candidates
+    double best = own, second = INFINITY;
+    int bj = a;
+    for (int g0 = 0; g0 < m; g0 += JB) {
+        int cj[JB];
+#pragma unroll
+        for (int u2 = 0; u2 < JB; ++u2) cj[u2] = uniform(cand[wave][min(g0 + u2, m - 1)]);
+        double acc[JB];
+#pragma unroll
+        for (int u2 = 0; u2 < JB; ++u2) acc[u2] = 0.0;
+        double v[PR_DC];
+        pr_load(v, Y, pid[wave], dim, 0, lane);
+        for (int d0 = 0; d0 < dim; d0 += PR_DC) {
+            pr_store(ys[wave], v, lane);
+            if (d0 + PR_DC < dim) pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+            __builtin_amdgcn_wave_barrier();
+            const int nd = min(PR_DC, dim - d0);
+            for (int dd = 0; dd < nd; ++dd) {
+                const double y = ys[wave][dd][lane];
+                const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad;
+#pragma unroll
+                for (int u2 = 0; u2 < JB; ++u2) {
+                    const double diff = y - crow[cj[u2]];
+                    acc[u2] = fma(diff, diff, acc[u2]);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int u2 = 0; u2 < JB; ++u2) {
+            if (g0 + u2 < m) {
+                const double v2 = acc[u2];
+                const int j = cj[u2];
+                if (v2 < best || (v2 == best && j < bj)) {
+                    second = best;
+                    best = v2;
+                    bj = j;
+                } else if (v2 < second) {
+                    second = v2;
+                }
+            }
+        }
+    }
+    const bool moved = narrow && bj != a;
+    const unsigned long long mv = __ballot(moved);
+    if (mv && lane == 0) atomicAdd(&changed[r], (int)__popcll(mv));
+    if (!narrow) return;
+    if (moved) {
+        dirty[(int64_t)r * K + a] = 1;          // both member lists changed
+        dirty[(int64_t)r * K + bj] = 1;
+    }
+    lab[e] = bj;
+    ub[e] = sqrt(best) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+    double l = isinf(second) ? INFINITY : sqrt(second) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+    if (hmin < INFINITY) l = fmin(l, (2.0 * hmin - u) * (1.0 - BOUND_MARGIN) - BOUND_TINY);
+    lb[e] = l;
 }
 
 // centre displacements: delta[r][j] = ||c_new - c_old|| (inflated), and per
@@ -705,11 +931,11 @@ int assign_kpad(int K) {
 struct KmWs {
     double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
     uint64_t *wq, *scan_tmp, *keys, *keys_alt, *radix_tmp;
-    uint32_t *vals, *vals_alt, *pts;
+    uint32_t *vals, *vals_alt, *pts, *fl;
     int32_t* lab;
-    int *changed, *active, *cnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
+    int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
     int64_t* seg;
-    double *bsum, *ccur;
+    double *bsum, *ccur, *hd;
     int64_t max_blocks;
     int Rpad;
     unsigned long long *m2, *q;
@@ -737,11 +963,13 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.vals = c.take<uint32_t>(nr);
     w.vals_alt = c.take<uint32_t>(nr);
     w.pts = c.take<uint32_t>(nr);
+    w.fl = w.vals_alt;                        // full-scan lists: free once the list sorts are done
     w.radix_tmp = c.take<uint64_t>(radix_tmp_elems(nr));
     w.lab = c.take<int32_t>(nr);
     w.changed = c.take<int>(R);
     w.active = c.take<int>(R);
     w.cnt = c.take<int>(R);
+    w.fcnt = c.take<int>(R);
     w.status = c.take<int>(1);
     w.dirty = c.take<int>((size_t)R * K);
     w.seg = c.take<int64_t>(2 * (size_t)R * K);
@@ -754,6 +982,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.bsum = c.take<double>((size_t)w.max_blocks * dim);
     w.Rpad = (R + RB - 1) / RB * RB;
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
+    w.hd = c.take<double>((size_t)R * K * K);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
     return c.size();
@@ -771,11 +1000,13 @@ sc_status km_validate(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* o) 
     return SC_OK;
 }
 
+// full scans of the lists (list, lcnt); max_cnt bounds every restart's count
 template <int JB>
-void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
-    dim3 grid((unsigned)ceil_div(n, 64), (unsigned)R);
+void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first,
+                   const uint32_t* list, const int* lcnt, int64_t max_cnt) {
+    dim3 grid((unsigned)ceil_div(max_cnt, 64), (unsigned)R);
     hipLaunchKernelGGL((k_assign_list<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
-                       assign_kpad(K), w.Y, w.Ct, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
+                       assign_kpad(K), w.Y, w.Ct, list, lcnt, w.active, w.lab, w.ub, w.lb,
                        w.changed, w.dirty, first);
 }
 
@@ -795,17 +1026,26 @@ void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs
     else seed_d2_go<16>(ctx, n, dim, R, Rpad, j, w, shift);
 }
 
-void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first) {
+template <int JB>
+void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int max_cnt) {
+    dim3 grid((unsigned)ceil_div(max_cnt, TH), (unsigned)R);
+    hipLaunchKernelGGL((k_assign_pruned<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                       assign_kpad(K), w.Y, w.Ct, w.hd, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
+                       w.changed, w.dirty, w.fl, w.fcnt);
+}
+
+void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first,
+            const uint32_t* list, const int* lcnt, int64_t max_cnt) {
     switch (assign_width(K)) {
-        case 2: launch_assign<2>(ctx, n, dim, K, R, w, first); break;
-        case 8: launch_assign<8>(ctx, n, dim, K, R, w, first); break;
-        case 16: launch_assign<16>(ctx, n, dim, K, R, w, first); break;
-        case 24: launch_assign<24>(ctx, n, dim, K, R, w, first); break;
-        case 32: launch_assign<32>(ctx, n, dim, K, R, w, first); break;
-        case 40: launch_assign<40>(ctx, n, dim, K, R, w, first); break;
-        case 48: launch_assign<48>(ctx, n, dim, K, R, w, first); break;
-        case 56: launch_assign<56>(ctx, n, dim, K, R, w, first); break;
-        default: launch_assign<64>(ctx, n, dim, K, R, w, first); break;
+        case 2: launch_assign<2>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 8: launch_assign<8>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 16: launch_assign<16>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 24: launch_assign<24>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 32: launch_assign<32>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 40: launch_assign<40>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 48: launch_assign<48>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        case 56: launch_assign<56>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
+        default: launch_assign<64>(ctx, n, dim, K, R, w, first, list, lcnt, max_cnt); break;
     }
 }
 
@@ -901,7 +1141,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (init_centroids) {
         hipLaunchKernelGGL(k_fill_lists, gnr, dim3(TH), 0, st, n, R, w.pts, w.cnt);
         SC_CHECK_LAUNCH(ctx);
-        assign(ctx, n, dim, K, R, w, 1);
+        assign(ctx, n, dim, K, R, w, 1, w.pts, w.cnt, n);
     } else {
         hipLaunchKernelGGL(k_first_bounds, gnr, dim3(TH), 0, st, nr, w.D2, w.ub, w.lb);
     }
@@ -911,7 +1151,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     const int bits = ceil_log2_u64((uint64_t)K);
     int n_active = R;
     int iterations = 0;
-    std::vector<int> ch(R);
+    std::vector<int> ch(R), cnt_h(R);
     for (int it = 1; it <= opts->max_iter && n_active > 0; ++it) {
         iterations = it;
         // centroid update from the stable member lists
@@ -946,15 +1186,39 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                            w.dinfo);
         hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C,
                            w.Ct);
+        hipLaunchKernelGGL(k_half_sep, dim3((unsigned)ceil_div((int64_t)K * K, TH), (unsigned)R),
+                           dim3(TH), 0, st, K, Kpad, dim, w.Ct, w.active, w.hd);
         SC_CHECK_LAUNCH(ctx);
         // points whose assignment may change, then their scans
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.cnt, R);
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.changed, R);
+        hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.fcnt, R);
         hipLaunchKernelGGL(k_bounds, dim3((unsigned)ceil_div(n, TH * PPT), (unsigned)R), dim3(TH), 0,
                            st, n, K, w.lab, w.ub, w.lb, w.delta, w.dinfo, w.active, w.pts, w.cnt);
         SC_CHECK_LAUNCH(ctx);
-        assign(ctx, n, dim, K, R, w, 0);
-        SC_CHECK_LAUNCH(ctx);
+        SC_CHECK_HIP(ctx, hipMemcpyAsync(cnt_h.data(), w.cnt, R * sizeof(int), hipMemcpyDeviceToHost, st));
+        SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
+        int max_cnt = 0;
+        for (int r = 0; r < R; ++r) {
+            if (!act_h[r]) continue;
+            const int cr = cnt_h[r];
+            max_cnt = std::max(max_cnt, cr);
+            if (cr < PR_SORT_MIN) continue;
+            // order the list by current label (stable: ascending point within a label)
+            const int64_t o = (int64_t)r * n;
+            hipLaunchKernelGGL(k_list_keys, dim3((unsigned)ceil_div(cr, TH)), dim3(TH), 0, st, n, cr,
+                               w.lab + o, w.pts + o, w.keys + o);
+            SC_CHECK_LAUNCH(ctx);
+            SC_TRY(radix_sort_pairs(ctx, w.keys + o, w.pts + o, w.keys_alt + o, w.vals_alt + o, cr,
+                                    bits, w.radix_tmp));
+        }
+        if (max_cnt > 0) {
+            // pruned scans; the points they cannot settle get full scans
+            launch_pruned<8>(ctx, n, dim, K, R, w, max_cnt);
+            SC_CHECK_LAUNCH(ctx);
+            assign(ctx, n, dim, K, R, w, 0, w.fl, w.fcnt, max_cnt);
+            SC_CHECK_LAUNCH(ctx);
+        }
         SC_CHECK_HIP(ctx, hipMemcpyAsync(ch.data(), w.changed, R * sizeof(int), hipMemcpyDeviceToHost, st));
         SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
         bool any_stop = false;
