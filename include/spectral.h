@@ -245,7 +245,14 @@ typedef struct {
     int max_iter;          /* Lloyd updates per restart, >= 0 */
     int normalize_rows;    /* 1: y_i = x_i / ||x_i|| (zero rows stay zero) */
     int x_fp32;            /* 1: X is float32 (widened to float64 on load), 0: float64 */
+    int scan;              /* Lloyd scans of the points whose bounds fail:
+                              SC_KM_SCAN_AUTO: pruned (Elkan) scans while the lists are long,
+                              full scans once they are short;
+                              SC_KM_SCAN_PRUNED: pruned scans whenever a list is long enough
+                              to be ordered by label; SC_KM_SCAN_FULL: full scans only.
+                              All three give identical results. */
 } sc_kmeans_opts;
+enum { SC_KM_SCAN_AUTO = 0, SC_KM_SCAN_PRUNED = 1, SC_KM_SCAN_FULL = 2 };
 
 sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* opts,
                               size_t* bytes);

@@ -41,7 +41,10 @@ class sc_lobpcg_info(C.Structure):
 
 class sc_kmeans_opts(C.Structure):
     _fields_ = [("n_clusters", _int), ("restarts", _int), ("max_iter", _int),
-                ("normalize_rows", _int), ("x_fp32", _int)]
+                ("normalize_rows", _int), ("x_fp32", _int), ("scan", _int)]
+
+
+SC_KM_SCAN_AUTO, SC_KM_SCAN_PRUNED, SC_KM_SCAN_FULL = 0, 1, 2
 
 
 SC_KIND_SPMM, SC_KIND_GRAM, SC_KIND_RR, SC_KIND_UPDATE, SC_KIND_CHOLQR, SC_KIND_RESIDUAL, \

@@ -217,7 +217,7 @@ class KmeansResult:
 def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.Tensor | None,
                   restarts: int | None = None, max_iter: int = 100, normalize: bool = True,
                   init_centroids: torch.Tensor | None = None,
-                  ws: torch.Tensor | None = None) -> KmeansResult:
+                  ws: torch.Tensor | None = None, scan: str = "auto") -> KmeansResult:
     n, dim = X.shape
     if init_centroids is not None:
         restarts = 1
@@ -225,8 +225,10 @@ def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.T
         restarts = draws.shape[0]
     if X.dtype not in (torch.float64, torch.float32):
         raise TypeError("X must be float64 or float32")
+    scan_mode = {"auto": _lib.SC_KM_SCAN_AUTO, "pruned": _lib.SC_KM_SCAN_PRUNED,
+                 "full": _lib.SC_KM_SCAN_FULL}[scan]
     opts = _lib.sc_kmeans_opts(n_clusters, restarts, max_iter, int(bool(normalize)),
-                               int(X.dtype == torch.float32))
+                               int(X.dtype == torch.float32), scan_mode)
     nb = C.c_size_t()
     ctx.check(lib().sc_kmeans_workspace(ctx.handle, n, dim, C.byref(opts), C.byref(nb)),
               "sc_kmeans_workspace")

@@ -353,25 +353,47 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
     }
 }
 
-// Half the separation of every centre pair, hd[r][a][j] <= ||c_a - c_j|| / 2
-// (deflated by the bound margin; 0 on the diagonal), from the transposed
-// centroid table.  Elkan's lemma: a point with ||y - c_a|| <= ub < hd[a][j]
-// is strictly nearer to c_a than to c_j.
+constexpr int PR_DC = 8;
+constexpr int PR_KMAX = 1024;
+constexpr int PR_KMAX_HS = PR_KMAX;
+constexpr int PR_WIDE = 16;
+constexpr int PR_SORT_MIN = 2048;       // lists at least this long are ordered by label
+// the pruned path runs when (points listed over all restarts) x K reaches this
+constexpr int64_t PR_WORK_MIN = 32000000;
+
+// Half the separation of every centre pair, h(a, j) <= ||c_a - c_j|| / 2
+// (deflated by the bound margin; 0 for j = a), from the transposed centroid
+// table.  Elkan's lemma: a point with ||y - c_a|| <= u < h(a, j) is strictly
+// nearer to c_a than to c_j.  Each centre's row is stored sorted ascending
+// (ties by index): hsv[r][a][t] the t-th least value, hsi[r][a][t] its centre.
+// One workgroup per (centre a, restart r).
 __global__ void __launch_bounds__(TH)
 k_half_sep(int K, int Kpad, int dim, const double* __restrict__ Ct, const int* __restrict__ active,
-           double* __restrict__ hd) {
-    const int r = blockIdx.y;
+           double* __restrict__ hsv, uint16_t* __restrict__ hsi) {
+    __shared__ double hv[PR_KMAX_HS];
+    const int r = blockIdx.y, a = blockIdx.x;
     if (!active[r]) return;
-    const int64_t e = (int64_t)blockIdx.x * TH + threadIdx.x;
-    if (e >= (int64_t)K * K) return;
-    const int a = (int)(e / K), j = (int)(e % K);
     const double* ct = Ct + (int64_t)r * dim * Kpad;
-    double s = 0.0;
-    for (int d = 0; d < dim; ++d) {
-        const double t = ct[(int64_t)d * Kpad + a] - ct[(int64_t)d * Kpad + j];
-        s = fma(t, t, s);
+    for (int j = threadIdx.x; j < K; j += TH) {
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            const double t = ct[(int64_t)d * Kpad + a] - ct[(int64_t)d * Kpad + j];
+            s = fma(t, t, s);
+        }
+        hv[j] = a == j ? 0.0 : 0.5 * sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
     }
-    hd[(int64_t)r * K * K + e] = a == j ? 0.0 : 0.5 * sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+    __syncthreads();
+    const int64_t row = ((int64_t)r * K + a) * K;
+    for (int j = threadIdx.x; j < K; j += TH) {
+        const double v = hv[j];
+        int rank = 0;
+        for (int l = 0; l < K; ++l) {
+            const double w = hv[l];
+            rank += w < v || (w == v && l < j);
+        }
+        hsv[row + rank] = v;
+        hsi[row + rank] = (uint16_t)j;
+    }
 }
 
 // sort keys of a scan list: the point's current label, with the point as value
@@ -385,24 +407,20 @@ __global__ void k_list_keys(int64_t n, int c, const int32_t* __restrict__ lab,
 // consecutive list entries; a long list is ordered by current label, so a
 // wave's points share one or a few labels.
 //   1. The exact distance to the assigned centre a gives a tight bound u.
-//   2. A centre j with u < hd[a][j] cannot be nearer than c_a.  A point that
-//      cannot rule out more than PR_WIDE centres is "narrow"; a wider one is
-//      handed to the full scan (appended to the list fl), and so is every
-//      point of a short, unordered list.
-//   3. The wave scans the union of its narrow points' remaining candidates, in
+//   2. A centre j with u < h(a, j) cannot be nearer than c_a.  A point that
+//      cannot rule out more than PR_WIDE centres is "wide" and is handed to
+//      the full scan (appended to the list fl), and so is every point of a
+//      short, unordered list.  The rest are "narrow": their candidates are
+//      the head of their centre's sorted row, merged into a wave bitmap.
+//   3. The wave scans the union of the narrow points' candidates, in
 //      ascending order, JB at a time.
 // Rows are staged in LDS PR_DC dimensions at a time (the next chunk is loaded
 // into registers while the current one is used); centre coordinates come from
 // the transposed table.  Every distance is the full fma chain in dimension
 // order, and a ruled-out centre is strictly farther than c_a, so the argmin
 // (lowest index on ties) equals a full scan's.  The new lower bound covers the
-// ruled-out centres by the triangle inequality,
-// ||y - c_j|| >= 2 hd[a][j] - ||y - c_a||.
-constexpr int PR_DC = 8;
-constexpr int PR_KMAX = 1024;
-constexpr int PR_WIDE = 16;
-constexpr int PR_SORT_MIN = 2048;       // lists at least this long are ordered by label
-
+// centres nobody scanned by the triangle inequality,
+// ||y - c_j|| >= 2 h(a, j) - ||y - c_a||.
 __device__ inline void pr_load(double (&v)[PR_DC], const double* __restrict__ Y,
                                const uint32_t* pidw, int dim, int d0, int lane) {
 #pragma unroll
@@ -424,15 +442,17 @@ __device__ inline void pr_store(double (*ys)[65], const double (&v)[PR_DC], int 
 template <int JB>
 __global__ void __launch_bounds__(TH)
 k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
-                const double* __restrict__ Ct, const double* __restrict__ hd,
-                const uint32_t* __restrict__ pts, const int* __restrict__ cnt,
-                const int* __restrict__ active, int32_t* __restrict__ lab, double* __restrict__ ub,
-                double* __restrict__ lb, int* __restrict__ changed, int* __restrict__ dirty,
-                uint32_t* __restrict__ fl, int* __restrict__ fcnt) {
+                const double* __restrict__ Ct, const double* __restrict__ hsv,
+                const uint16_t* __restrict__ hsi, const uint32_t* __restrict__ pts,
+                const int* __restrict__ cnt, const int* __restrict__ active,
+                int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
+                int* __restrict__ changed, int* __restrict__ dirty, uint32_t* __restrict__ fl,
+                int* __restrict__ fcnt) {
     constexpr int NW = TH / 64;
     __shared__ double ys[NW][PR_DC][65];
     __shared__ uint32_t pid[NW][64];
     __shared__ uint16_t cand[NW][PR_KMAX];
+    __shared__ uint32_t bits[NW][PR_KMAX / 32];
     const int r = blockIdx.y;
     if (!active[r]) return;
     const int c = cnt[r];
@@ -443,10 +463,9 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
     const bool live = lane < np;
     const uint32_t i = pts[(int64_t)r * n + q0 + min(lane, np - 1)];
     const int64_t e = (int64_t)r * n + i;
-    const bool ordered = c >= PR_SORT_MIN;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
-    if (!ordered) {
-        // short list: every point goes to the full scan
+    if (c < PR_SORT_MIN) {
+        // short, unordered list: every point goes to the full scan
         const unsigned long long mask = __ballot(live);
         int base = 0;
         if (lane == 0) base = atomicAdd(&fcnt[r], (int)__popcll(mask));
@@ -454,7 +473,9 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
         if (live) fl[(int64_t)r * n + base + __popcll(mask & lanes_below)] = i;
         return;
     }
+    const int nwords = (K + 31) / 32;
     pid[wave][lane] = i;
+    if (lane < nwords) bits[wave][lane] = 0u;
     const int a = lab[e];
     const double* Ctr = Ct + (int64_t)r * dim * Kpad;
     __builtin_amdgcn_wave_barrier();
@@ -462,32 +483,37 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
     double own = 0.0;
     {
         const double* ca = Ctr + a;
-        double v[PR_DC];
+        double v[PR_DC], cv[PR_DC];
         pr_load(v, Y, pid[wave], dim, 0, lane);
+#pragma unroll
+        for (int dd = 0; dd < PR_DC; ++dd) cv[dd] = dd < dim ? ca[(int64_t)dd * Kpad] : 0.0;
         for (int d0 = 0; d0 < dim; d0 += PR_DC) {
             pr_store(ys[wave], v, lane);
-            if (d0 + PR_DC < dim) pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+            double cc[PR_DC];
+#pragma unroll
+            for (int dd = 0; dd < PR_DC; ++dd) cc[dd] = cv[dd];
+            if (d0 + PR_DC < dim) {
+                pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+#pragma unroll
+                for (int dd = 0; dd < PR_DC; ++dd)
+                    cv[dd] = d0 + PR_DC + dd < dim ? ca[(int64_t)(d0 + PR_DC + dd) * Kpad] : 0.0;
+            }
             __builtin_amdgcn_wave_barrier();
             const int nd = min(PR_DC, dim - d0);
-            for (int dd = 0; dd < nd; ++dd) {
-                const double diff = ys[wave][dd][lane] - ca[(int64_t)(d0 + dd) * Kpad];
-                own = fma(diff, diff, own);
+#pragma unroll
+            for (int dd = 0; dd < PR_DC; ++dd) {
+                if (dd < nd) {
+                    const double diff = ys[wave][dd][lane] - cc[dd];
+                    own = fma(diff, diff, own);
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
     }
     const double u = sqrt(own) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
-    const double* hdr = hd + ((int64_t)r * K + a) * K;
-    // 2. how many centres the point cannot rule out (its own included)
-    int nkeep = 0;
-    for (int j0 = 0; j0 < K; j0 += 16) {
-        double h[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) h[t] = j0 + t < K ? hdr[j0 + t] : INFINITY;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) nkeep += !(u < h[t]);
-    }
-    const bool wide = live && nkeep > PR_WIDE;
+    const int64_t row = ((int64_t)r * K + a) * K;
+    // 2. wide: the PR_WIDE-th smallest half-separation (0-based) is not above u
+    const bool wide = live && K > PR_WIDE && !(u < hsv[row + PR_WIDE]);
     const bool narrow = live && !wide;
     {
         const unsigned long long mask = __ballot(wide);
@@ -498,25 +524,44 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
             if (wide) fl[(int64_t)r * n + base + __popcll(mask & lanes_below)] = i;
         }
     }
-    // the narrow points' candidates besides their own centre (wave-uniform
-    // ascending list), and per point the least half-separation of the rest
+    // a narrow point's candidates: the head of its sorted row (own centre aside)
+    int nkeep = 0;
+    if (narrow) {
+        while (nkeep < K && !(u < hsv[row + nkeep])) {
+            const int j = hsi[row + nkeep];
+            if (j != a) atomicOr(&bits[wave][j >> 5], 1u << (j & 31));
+            ++nkeep;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // the union as an ascending list: lane l expands word l
     int m = 0;
+    {
+        const uint32_t wbits = lane < nwords ? bits[wave][lane] : 0u;
+        const int pc = __popc(wbits);
+        int incl = pc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        m = __shfl(incl, 63);
+        int off = incl - pc;
+        uint32_t b = wbits;
+        while (b) {
+            const int bit = __ffs(b) - 1;
+            cand[wave][off++] = (uint16_t)(lane * 32 + bit);
+            b &= b - 1u;
+        }
+    }
+    // least half-separation over the centres nobody scans
     double hmin = INFINITY;
-    for (int j0 = 0; j0 < K; j0 += 16) {
-        double h[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) h[t] = j0 + t < K ? hdr[j0 + t] : INFINITY;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int j = j0 + t;
-            const bool keep = narrow && j < K && j != a && !(u < h[t]);
-            const unsigned long long mask = __ballot(keep);
-            if (mask) {
-                if (lane == 0) cand[wave][m] = (uint16_t)j;
-                ++m;
-            } else if (narrow && j < K && j != a) {
-                hmin = fmin(hmin, h[t]);
-            }
+    if (narrow) {
+        for (int t = nkeep; t < K; ++t) {
+            const int j = hsi[row + t];
+            if (j == a || ((bits[wave][j >> 5] >> (j & 31)) & 1u)) continue;
+            hmin = hsv[row + t];
+            break;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -537,13 +582,16 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
             if (d0 + PR_DC < dim) pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
             __builtin_amdgcn_wave_barrier();
             const int nd = min(PR_DC, dim - d0);
-            for (int dd = 0; dd < nd; ++dd) {
-                const double y = ys[wave][dd][lane];
-                const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad;
 #pragma unroll
-                for (int u2 = 0; u2 < JB; ++u2) {
-                    const double diff = y - crow[cj[u2]];
-                    acc[u2] = fma(diff, diff, acc[u2]);
+            for (int dd = 0; dd < PR_DC; ++dd) {
+                if (dd < nd) {
+                    const double y = ys[wave][dd][lane];
+                    const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad;
+#pragma unroll
+                    for (int u2 = 0; u2 < JB; ++u2) {
+                        const double diff = y - crow[cj[u2]];
+                        acc[u2] = fma(diff, diff, acc[u2]);
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
@@ -935,7 +983,8 @@ struct KmWs {
     int32_t* lab;
     int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
     int64_t* seg;
-    double *bsum, *ccur, *hd;
+    double *bsum, *ccur, *hsv;
+    uint16_t* hsi;
     int64_t max_blocks;
     int Rpad;
     unsigned long long *m2, *q;
@@ -982,7 +1031,8 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.bsum = c.take<double>((size_t)w.max_blocks * dim);
     w.Rpad = (R + RB - 1) / RB * RB;
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
-    w.hd = c.take<double>((size_t)R * K * K);
+    w.hsv = c.take<double>((size_t)R * K * K);
+    w.hsi = c.take<uint16_t>((size_t)R * K * K);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
     return c.size();
@@ -995,6 +1045,8 @@ sc_status km_validate(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_opts* o) 
         return sc_fail(ctx, SC_E_INVAL, "kmeans: need 1 <= K <= min(n, 1024)");
     if (o->restarts < 1 || o->max_iter < 0)
         return sc_fail(ctx, SC_E_INVAL, "kmeans: need restarts >= 1 and max_iter >= 0");
+    if (o->scan != SC_KM_SCAN_AUTO && o->scan != SC_KM_SCAN_PRUNED && o->scan != SC_KM_SCAN_FULL)
+        return sc_fail(ctx, SC_E_INVAL, "kmeans: unknown scan mode %d", o->scan);
     if ((int64_t)o->restarts * n >= (int64_t(1) << 31))
         return sc_fail(ctx, SC_E_UNSUPPORTED, "kmeans: restarts * n >= 2^31");
     return SC_OK;
@@ -1030,7 +1082,7 @@ template <int JB>
 void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int max_cnt) {
     dim3 grid((unsigned)ceil_div(max_cnt, TH), (unsigned)R);
     hipLaunchKernelGGL((k_assign_pruned<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
-                       assign_kpad(K), w.Y, w.Ct, w.hd, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
+                       assign_kpad(K), w.Y, w.Ct, w.hsv, w.hsi, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
                        w.changed, w.dirty, w.fl, w.fcnt);
 }
 
@@ -1186,8 +1238,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                            w.dinfo);
         hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C,
                            w.Ct);
-        hipLaunchKernelGGL(k_half_sep, dim3((unsigned)ceil_div((int64_t)K * K, TH), (unsigned)R),
-                           dim3(TH), 0, st, K, Kpad, dim, w.Ct, w.active, w.hd);
+        hipLaunchKernelGGL(k_half_sep, dim3((unsigned)K, (unsigned)R), dim3(TH), 0, st, K, Kpad,
+                           dim, w.Ct, w.active, w.hsv, w.hsi);
         SC_CHECK_LAUNCH(ctx);
         // points whose assignment may change, then their scans
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.cnt, R);
@@ -1199,24 +1251,35 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         SC_CHECK_HIP(ctx, hipMemcpyAsync(cnt_h.data(), w.cnt, R * sizeof(int), hipMemcpyDeviceToHost, st));
         SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
         int max_cnt = 0;
-        for (int r = 0; r < R; ++r) {
-            if (!act_h[r]) continue;
-            const int cr = cnt_h[r];
-            max_cnt = std::max(max_cnt, cr);
-            if (cr < PR_SORT_MIN) continue;
-            // order the list by current label (stable: ascending point within a label)
-            const int64_t o = (int64_t)r * n;
-            hipLaunchKernelGGL(k_list_keys, dim3((unsigned)ceil_div(cr, TH)), dim3(TH), 0, st, n, cr,
-                               w.lab + o, w.pts + o, w.keys + o);
-            SC_CHECK_LAUNCH(ctx);
-            SC_TRY(radix_sort_pairs(ctx, w.keys + o, w.pts + o, w.keys_alt + o, w.vals_alt + o, cr,
-                                    bits, w.radix_tmp));
-        }
-        if (max_cnt > 0) {
-            // pruned scans; the points they cannot settle get full scans
+        int64_t total = 0;
+        for (int r = 0; r < R; ++r)
+            if (act_h[r]) {
+                max_cnt = std::max(max_cnt, cnt_h[r]);
+                total += cnt_h[r];
+            }
+        const bool prune = opts->scan == SC_KM_SCAN_PRUNED ||
+                           (opts->scan == SC_KM_SCAN_AUTO && total * K >= PR_WORK_MIN);
+        if (prune) {
+            // long lists: ordered by current label (stable: ascending point
+            // within a label), pruned scans, then full scans of the points
+            // those cannot settle
+            for (int r = 0; r < R; ++r) {
+                const int cr = cnt_h[r];
+                if (!act_h[r] || cr < PR_SORT_MIN) continue;
+                const int64_t o = (int64_t)r * n;
+                hipLaunchKernelGGL(k_list_keys, dim3((unsigned)ceil_div(cr, TH)), dim3(TH), 0, st, n,
+                                   cr, w.lab + o, w.pts + o, w.keys + o);
+                SC_CHECK_LAUNCH(ctx);
+                SC_TRY(radix_sort_pairs(ctx, w.keys + o, w.pts + o, w.keys_alt + o, w.vals_alt + o,
+                                        cr, bits, w.radix_tmp));
+            }
             launch_pruned<8>(ctx, n, dim, K, R, w, max_cnt);
             SC_CHECK_LAUNCH(ctx);
             assign(ctx, n, dim, K, R, w, 0, w.fl, w.fcnt, max_cnt);
+            SC_CHECK_LAUNCH(ctx);
+        } else if (max_cnt > 0) {
+            // short lists: the fixed latency of the pruned path outweighs its saving
+            assign(ctx, n, dim, K, R, w, 0, w.pts, w.cnt, max_cnt);
             SC_CHECK_LAUNCH(ctx);
         }
         SC_CHECK_HIP(ctx, hipMemcpyAsync(ch.data(), w.changed, R * sizeof(int), hipMemcpyDeviceToHost, st));

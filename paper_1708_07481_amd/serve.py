@@ -386,7 +386,7 @@ class LibraryBackend:
         opts = self.api.lobpcg_opts(req.k, self.maxit, self.tol, prec, req.k)
         lw = self.api.lobpcg_workspace(ctx, req.n, nnz_cap, opts)
         kw = C.c_size_t()
-        ko = sc_kmeans_opts(req.k, self.restarts, self.kmeans_iters, 1, int(elem == 4))
+        ko = sc_kmeans_opts(req.k, self.restarts, self.kmeans_iters, 1, int(elem == 4), 0)
         ctx.check(lib().sc_kmeans_workspace(ctx.handle, req.n, req.k, C.byref(ko), C.byref(kw)),
                   "sc_kmeans_workspace")
         return footprint_bytes(req.n, nnz_cap, req.k, elem, self.restarts, lw, kw.value)

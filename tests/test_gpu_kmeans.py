@@ -28,14 +28,48 @@ def _same(ko, kg):
 @pytest.mark.parametrize("n,dim,K,R,seed", [(10, 2, 3, 2, 0), (257, 5, 4, 3, 1),
                                             (1000, 8, 8, 10, 2), (3001, 19, 19, 4, 3),
                                             (20000, 44, 44, 3, 4)])
-def test_kmeans_bit_exact_random(orc, ctx, n, dim, K, R, seed):
+@pytest.mark.parametrize("scan", ["auto", "pruned"])
+def test_kmeans_bit_exact_random(orc, ctx, n, dim, K, R, seed, scan):
     from paper_1708_07481_amd import api
     rng = np.random.default_rng(seed)
     centers = rng.standard_normal((K, dim))
     X = centers[rng.integers(0, K, n)] + 0.3 * rng.standard_normal((n, dim))
     draws = kmeans_draws(R, K, seed)
     ko = orc.kmeans(X, K, draws, max_iter=100)
-    kg = api.kmeans_assign(ctx, to_dev(X), K, to_dev(draws.view(np.int64)), max_iter=100)
+    kg = api.kmeans_assign(ctx, to_dev(X), K, to_dev(draws.view(np.int64)), max_iter=100,
+                           scan=scan)
+    _same(ko, kg)
+
+
+@pytest.mark.parametrize("n,dim,K,R,noise,seed", [(30000, 16, 24, 2, 1.0, 5),
+                                                  (12000, 40, 40, 2, 0.6, 6)])
+@pytest.mark.parametrize("scan", ["pruned", "full"])
+def test_kmeans_bit_exact_overlapping(orc, ctx, n, dim, K, R, noise, seed, scan):
+    """Overlapping clusters: many points cannot rule out more than a few
+    centres, so the pruned scans hand a large share to the full scan, and
+    waves mix narrow and wide points."""
+    from paper_1708_07481_amd import api
+    rng = np.random.default_rng(seed)
+    centers = rng.standard_normal((K, dim))
+    X = centers[rng.integers(0, K, n)] + noise * rng.standard_normal((n, dim))
+    draws = kmeans_draws(R, K, seed)
+    ko = orc.kmeans(X, K, draws, max_iter=100)
+    kg = api.kmeans_assign(ctx, to_dev(X), K, to_dev(draws.view(np.int64)), max_iter=100,
+                           scan=scan)
+    _same(ko, kg)
+
+
+@pytest.mark.parametrize("scan", ["pruned", "full"])
+def test_kmeans_bit_exact_lattice_ties(orc, ctx, scan):
+    """Integer points, no normalisation: many distances tie exactly, and a tie
+    goes to the lowest centre index on both sides."""
+    from paper_1708_07481_amd import api
+    rng = np.random.default_rng(7)
+    X = rng.integers(0, 3, (12000, 6)).astype(np.float64)
+    draws = kmeans_draws(2, 10, 7)
+    ko = orc.kmeans(X, 10, draws, max_iter=100, normalize=False)
+    kg = api.kmeans_assign(ctx, to_dev(X), 10, to_dev(draws.view(np.int64)), max_iter=100,
+                           normalize=False, scan=scan)
     _same(ko, kg)
 
 

@@ -65,7 +65,7 @@ def test_kmeans_workspace_independent(graph):
     from paper_1708_07481_amd._lib import lib, sc_kmeans_opts
     X = to_dev(np.random.default_rng(2).standard_normal((g0.n, 12)))
     draws = to_dev(kmeans_draws(5, 12, 2).view(np.int64))
-    o = sc_kmeans_opts(12, 5, 100, 1, 0)
+    o = sc_kmeans_opts(12, 5, 100, 1, 0, 0)
     nb = C.c_size_t()
     ctx.check(lib().sc_kmeans_workspace(ctx.handle, g0.n, 12, C.byref(o), C.byref(nb)), "ws")
     r = [api.kmeans_assign(ctx, X, 12, draws, ws=_ws(nb.value, byte)) for byte in (0, 0xFF)]
