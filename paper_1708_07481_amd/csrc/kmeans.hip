@@ -100,37 +100,78 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
     if (bad && live) atomicOr(status, DEV_NUMERIC);
 }
 
-// centre j of every restart r from a chosen row (grid: R blocks)
-__global__ void k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict__ Y,
-                            const uint64_t* __restrict__ draws, const uint64_t* __restrict__ pref,
-                            double* __restrict__ C, double* __restrict__ ccur) {
+// Seeding weights w_i = floor(D2_i 2^shift) are summed per tile of SEED_TILE
+// consecutive points by the distance kernel (tsum[r][tile]).  The pick of
+// centre j finds c_j = y[min i : prefix_i > t], t = mulhi64(u, T), T = sum w,
+// in two levels: the tile whose inclusive prefix first exceeds t, then the
+// point inside it (weights recomputed from D2); all sums are exact integers.
+// Grid: R blocks of PICK_NT threads.
+constexpr int SEED_TILE = 64;
+constexpr int PICK_NT = 1024;
+__global__ void __launch_bounds__(PICK_NT)
+k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict__ Y,
+            const uint64_t* __restrict__ draws, const uint64_t* __restrict__ tsum,
+            const double* __restrict__ D2, int shift, double* __restrict__ C,
+            double* __restrict__ ccur) {
+    __shared__ uint64_t part[PICK_NT];
     __shared__ int64_t pick;
-    const int r = blockIdx.x;
-    if (threadIdx.x == 0) {
-        const uint64_t u = draws[(int64_t)r * K + j];
-        if (j == 0) {
-            pick = (int64_t)mulhi64(u, (uint64_t)n);
-        } else {
-            const uint64_t* pr = pref + (int64_t)r * n;
-            const uint64_t T = pr[n - 1];
-            if (T == 0) {
-                pick = (int64_t)mulhi64(u, (uint64_t)n);
-            } else {
-                const uint64_t t = mulhi64(u, T);
-                int64_t lo = 0, hi = n - 1;          // first i with prefix_i > t
-                while (lo < hi) {
-                    const int64_t mid = lo + (hi - lo) / 2;
-                    if (pr[mid] > t) hi = mid;
-                    else lo = mid + 1;
+    __shared__ int64_t tile_s;
+    __shared__ uint64_t base_s;
+    const int r = blockIdx.x, tid = threadIdx.x;
+    const uint64_t u = draws[(int64_t)r * K + j];
+    if (tid == 0) pick = (int64_t)mulhi64(u, (uint64_t)n);
+    if (j > 0) {
+        const int64_t ntiles = (n + SEED_TILE - 1) / SEED_TILE;
+        const uint64_t* ts = tsum + (int64_t)r * ntiles;
+        const int64_t per = (ntiles + PICK_NT - 1) / PICK_NT;
+        const int64_t t0 = min((int64_t)tid * per, ntiles), t1 = min(t0 + per, ntiles);
+        uint64_t mine = 0;
+        for (int64_t t = t0; t < t1; ++t) mine += ts[t];
+        part[tid] = mine;
+        __syncthreads();
+        // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
+        for (int o = 1; o < PICK_NT; o <<= 1) {
+            const uint64_t add = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        const uint64_t T = part[PICK_NT - 1];
+        if (T > 0) {
+            const uint64_t t = mulhi64(u, T);
+            const uint64_t lo = part[tid] - mine;            // prefix before this thread's tiles
+            if (lo <= t && t < part[tid]) {
+                uint64_t acc = lo;
+                for (int64_t q = t0; q < t1; ++q) {
+                    if (t < acc + ts[q]) {
+                        tile_s = q;
+                        base_s = acc;
+                        break;
+                    }
+                    acc += ts[q];
                 }
-                pick = lo;
+            }
+            __syncthreads();
+            if (tid < 64) {
+                const int64_t i = tile_s * SEED_TILE + tid;
+                uint64_t wv = i < n ? (uint64_t)floor(ldexp(D2[(int64_t)r * n + i], shift)) : 0;
+                uint64_t incl = wv;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint64_t x = __shfl_up(incl, o);
+                    if (tid >= o) incl += x;
+                }
+                const bool hit = i < n && base_s + incl > t;
+                const unsigned long long m = __ballot(hit);
+                if (tid == 0) pick = tile_s * SEED_TILE + (__ffsll((long long)m) - 1);
             }
         }
     }
     __syncthreads();
+    const int64_t pk = pick;
     double* c = C + ((int64_t)r * K + j) * dim;
-    for (int d = threadIdx.x; d < dim; d += blockDim.x) {
-        const double v = Y[pick * dim + d];
+    for (int d = tid; d < dim; d += PICK_NT) {
+        const double v = Y[pk * dim + d];
         c[d] = v;
         ccur[(int64_t)d * Rpad + r] = v;      // this round's centres, dimension-major
     }
@@ -145,10 +186,13 @@ constexpr int RB = 16;
 template <int WB>
 __global__ void __launch_bounds__(TH)
 k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
-          const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ wq,
+          const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ tsum,
           int shift, int32_t* __restrict__ lab, double* __restrict__ sec) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i0 < n;
+    const int64_t i = live ? i0 : n - 1;
+    const int64_t ntiles = (n + SEED_TILE - 1) / SEED_TILE;
+    const int64_t tile = i0 / SEED_TILE;    // a wave is one tile
     for (int r0 = 0; r0 < R; r0 += WB) {
         double acc[WB];
 #pragma unroll
@@ -188,23 +232,29 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
             if (r0 + q < R) {
                 const int64_t e = (int64_t)(r0 + q) * n + i;
                 const double a = acc[q];
-                double v;
-                if (j == 0) {
-                    v = a;
-                    sec[e] = INFINITY;
-                    lab[e] = 0;
-                } else {
-                    v = D2[e];
-                    if (a < v) {
-                        sec[e] = v;
+                double v = 0.0;
+                if (live) {
+                    if (j == 0) {
                         v = a;
-                        lab[e] = j;
-                    } else if (a < sec[e]) {
-                        sec[e] = a;
+                        sec[e] = INFINITY;
+                        lab[e] = 0;
+                    } else {
+                        v = D2[e];
+                        if (a < v) {
+                            sec[e] = v;
+                            v = a;
+                            lab[e] = j;
+                        } else if (a < sec[e]) {
+                            sec[e] = a;
+                        }
                     }
+                    D2[e] = v;
                 }
-                D2[e] = v;
-                wq[e] = (uint64_t)floor(ldexp(v, shift));
+                // the tile's weight sum
+                uint64_t ws = live ? (uint64_t)floor(ldexp(v, shift)) : 0;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) ws += __shfl_xor(ws, o);
+                if ((threadIdx.x & 63) == 0 && tile < ntiles) tsum[(int64_t)(r0 + q) * ntiles + tile] = ws;
             }
         }
     }
@@ -978,7 +1028,7 @@ int assign_kpad(int K) {
 
 struct KmWs {
     double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
-    uint64_t *wq, *scan_tmp, *keys, *keys_alt, *radix_tmp;
+    uint64_t *tsum, *keys, *keys_alt, *radix_tmp;
     uint32_t *vals, *vals_alt, *pts, *fl;
     int32_t* lab;
     int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
@@ -1005,8 +1055,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.dinfo = c.take<double>(3 * (size_t)R);
     w.part = c.take<double>(ceil_div(n, TH * 16) + 1);
     w.inertia = c.take<double>(1);
-    w.wq = c.take<uint64_t>(nr);
-    w.scan_tmp = c.take<uint64_t>(scan_u64_batched_tmp_elems(n, R));
+    w.tsum = c.take<uint64_t>((size_t)R * ceil_div(n, SEED_TILE));
     w.keys = c.take<uint64_t>(nr);
     w.keys_alt = c.take<uint64_t>(nr);
     w.vals = c.take<uint32_t>(nr);
@@ -1065,7 +1114,7 @@ void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
 template <int WB>
 void seed_d2_go(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
     hipLaunchKernelGGL((k_seed_d2<WB>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, dim, R,
-                       Rpad, j, w.Yt, w.ccur, w.D2, w.wq, shift, w.lab, w.lb);
+                       Rpad, j, w.Yt, w.ccur, w.D2, w.tsum, shift, w.lab, w.lb);
 }
 
 void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
@@ -1169,19 +1218,17 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (init_centroids) {
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.C, init_centroids, cent_bytes, hipMemcpyDeviceToDevice, st));
     } else {
-        uint64_t* pref = w.keys;            // prefix sums of the weights (scan output)
         // this round's centres of restarts >= R stay 0.0
         hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div((int64_t)w.Rpad * dim, TH)), dim3(TH), 0, st,
                            reinterpret_cast<int64_t*>(w.ccur), (int64_t)w.Rpad * dim);
         for (int j = 0; j < K; ++j) {
-            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(TH), 0, st, n, dim, K, j, w.Rpad, w.Y,
-                               draws, pref, w.C, w.ccur);
+            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(PICK_NT), 0, st, n, dim, K, j, w.Rpad, w.Y,
+                               draws, w.tsum, w.D2, shift, w.C, w.ccur);
             SC_CHECK_LAUNCH(ctx);
             // distances to centre j (also after the last one: they complete the
             // first assignment)
             seed_d2(ctx, n, dim, R, w.Rpad, j, w, shift);
             SC_CHECK_LAUNCH(ctx);
-            if (j + 1 < K) SC_TRY(scan_u64_batched(ctx, w.wq, pref, n, R, w.scan_tmp));
         }
     }
     const dim3 gcent((unsigned)ceil_div((int64_t)R * K * dim, TH));
