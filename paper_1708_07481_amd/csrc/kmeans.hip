@@ -783,29 +783,151 @@ k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, double* __restrict__
     }
 }
 
-// sort keys of the active restarts: the label, with the vertex index as value
-// (restart r occupies positions [r n, (r + 1) n) of both arrays)
-__global__ void k_label_keys(int64_t n, int R, const int* __restrict__ active,
-                             const int32_t* __restrict__ lab, uint64_t* __restrict__ keys,
-                             uint32_t* __restrict__ vals) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * R || !active[e / n]) return;
-    keys[e] = (uint64_t)lab[e];
-    vals[e] = (uint32_t)(e % n);
+// Member lists: a stable counting sort of each active restart's points by
+// label (ascending vertex order within a label).  Tiles of LS_TILE points:
+// per-tile label histograms (label-major, tile-minor), one exclusive scan per
+// restart, then every tile is ordered by label in LDS with one stable one-bit
+// split per label bit and scattered to its offsets.  The scan also gives the
+// segment of every label directly.
+constexpr int LS_ITEMS = 8;
+constexpr int LS_TILE = TH * LS_ITEMS;
+
+__device__ inline uint32_t ls_block_excl_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < TH / 64; ++w) {
+            const uint32_t t = wsum[w];
+            wsum[w] = acc;
+            acc += t;
+        }
+        wsum[TH / 64] = acc;
+    }
+    __syncthreads();
+    const uint32_t r = x - v + wsum[wave];
+    *total = wsum[TH / 64];
+    __syncthreads();
+    return r;
 }
 
-// segment [start, end) of every (restart, label) in the per-restart sorted
-// lists (empty: 0, 0); positions are global (r n + p)
-__global__ void k_segments(int64_t n, int K, int R, const int* __restrict__ active,
-                           const uint64_t* __restrict__ keys, int64_t* __restrict__ seg) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n * R) return;
-    const int64_t r = p / n, q = p - r * n;
+// grid (tiles, R)
+__global__ void __launch_bounds__(TH)
+k_lab_hist(int64_t n, int K, const int* __restrict__ active, const int32_t* __restrict__ lab,
+           uint64_t* __restrict__ hist, int ntiles) {
+    __shared__ uint32_t h[PR_KMAX];
+    const int r = blockIdx.y;
     if (!active[r]) return;
-    const uint64_t k = keys[p];
-    const int64_t g = r * K + (int64_t)k;
-    if (q == 0 || keys[p - 1] != k) seg[2 * g] = p;
-    if (q + 1 == n || keys[p + 1] != k) seg[2 * g + 1] = p + 1;
+    for (int b = threadIdx.x; b < K; b += TH) h[b] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * LS_TILE;
+    const int32_t* lr = lab + (int64_t)r * n;
+#pragma unroll
+    for (int t = 0; t < LS_ITEMS; ++t) {
+        const int64_t idx = base + (int64_t)t * TH + threadIdx.x;
+        if (idx < n) atomicAdd(&h[lr[idx]], 1u);
+    }
+    __syncthreads();
+    uint64_t* hr = hist + (int64_t)r * K * ntiles;
+    for (int b = threadIdx.x; b < K; b += TH) hr[(int64_t)b * ntiles + blockIdx.x] = h[b];
+}
+
+// label segments from the scanned histogram: seg[2 (r K + b)] / seg[2 (r K + b) + 1]
+// = first / one past the last position of label b in restart r's list
+__global__ void k_lab_segments(int64_t n, int K, int R, const int* __restrict__ active,
+                               const uint64_t* __restrict__ off, int ntiles,
+                               int64_t* __restrict__ seg) {
+    const int64_t rj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rj >= (int64_t)R * K) return;
+    const int r = (int)(rj / K), b = (int)(rj % K);
+    if (!active[r]) return;
+    const uint64_t* o = off + (int64_t)r * K * ntiles;
+    const int64_t start = (int64_t)o[(int64_t)b * ntiles];
+    const int64_t end = b + 1 < K ? (int64_t)o[(int64_t)(b + 1) * ntiles] : n;
+    seg[2 * rj] = (int64_t)r * n + start;
+    seg[2 * rj + 1] = (int64_t)r * n + end;
+}
+
+// grid (tiles, R); vals[r n + position] = vertex
+__global__ void __launch_bounds__(TH)
+k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
+              const int32_t* __restrict__ lab, const uint64_t* __restrict__ off, int ntiles,
+              uint32_t* __restrict__ vals) {
+    __shared__ uint16_t kb[2][LS_TILE];
+    __shared__ uint32_t vb[2][LS_TILE];
+    __shared__ uint32_t wsum[TH / 64 + 1];
+    __shared__ uint32_t lstart[PR_KMAX];
+    const int r = blockIdx.y;
+    if (!active[r]) return;
+    const int64_t base = (int64_t)blockIdx.x * LS_TILE;
+    const int cnt = (int)min<int64_t>(LS_TILE, n - base);
+    const int32_t* lr = lab + (int64_t)r * n;
+    // padding carries the largest key and stays behind every real point
+    const uint16_t pad = (uint16_t)((1u << nbits) - 1u);
+#pragma unroll
+    for (int t = 0; t < LS_ITEMS; ++t) {
+        const int p = t * TH + threadIdx.x;
+        kb[0][p] = p < cnt ? (uint16_t)lr[base + p] : pad;
+        vb[0][p] = (uint32_t)(base + p);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int bit = 0; bit < nbits; ++bit) {
+        uint16_t k[LS_ITEMS];
+        uint32_t v[LS_ITEMS];
+        uint32_t zeros = 0;
+#pragma unroll
+        for (int t = 0; t < LS_ITEMS; ++t) {
+            k[t] = kb[cur][threadIdx.x * LS_ITEMS + t];
+            v[t] = vb[cur][threadIdx.x * LS_ITEMS + t];
+            zeros += ((k[t] >> bit) & 1) ? 0u : 1u;
+        }
+        uint32_t Z;
+        const uint32_t zt = ls_block_excl_scan(zeros, &Z, wsum);
+        uint32_t zb = 0;
+#pragma unroll
+        for (int t = 0; t < LS_ITEMS; ++t) {
+            const uint32_t P = threadIdx.x * LS_ITEMS + t;
+            uint32_t np;
+            if (((k[t] >> bit) & 1) == 0) {
+                np = zt + zb;
+                ++zb;
+            } else {
+                np = Z + (P - (zt + zb));
+            }
+            kb[cur ^ 1][np] = k[t];
+            vb[cur ^ 1][np] = v[t];
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    // first sorted position of every label present in the tile
+#pragma unroll
+    for (int t = 0; t < LS_ITEMS; ++t) {
+        const int p = threadIdx.x * LS_ITEMS + t;
+        if (p < cnt) {
+            const uint16_t key = kb[cur][p];
+            if (p == 0 || kb[cur][p - 1] != key) lstart[key] = p;
+        }
+    }
+    __syncthreads();
+    const uint64_t* o = off + (int64_t)r * K * ntiles;
+    uint32_t* vr = vals + (int64_t)r * n;
+#pragma unroll
+    for (int t = 0; t < LS_ITEMS; ++t) {
+        const int p = t * TH + threadIdx.x;
+        if (p < cnt) {
+            const uint16_t key = kb[cur][p];
+            vr[o[(int64_t)key * ntiles + blockIdx.x] + (p - (int)lstart[key])] = vb[cur][p];
+        }
+    }
 }
 
 // Centroid update.  The members of cluster (r, j), in ascending vertex order
@@ -921,11 +1043,13 @@ k_centroid_total(int dim, int K, int R, const int64_t* __restrict__ seg,
     C[e] = c / (double)cnt;
 }
 
-// exact squared distance of every point to its assigned centre
+// exact squared distance of every point to its assigned centre, reading the
+// transposed centroid table Ct[r][d][Kpad] (a dimension's centres share a few
+// cache lines, so the per-lane gathers by label stay in L1)
 template <int WB>
 __global__ void __launch_bounds__(TH)
-k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
-           const double* __restrict__ C, const int32_t* __restrict__ lab,
+k_final_d2(int64_t n, int dim, int K, int Kpad, int R, const double* __restrict__ Yt,
+           const double* __restrict__ Ct, const int32_t* __restrict__ lab,
            double* __restrict__ D2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -937,14 +1061,14 @@ k_final_d2(int64_t n, int dim, int K, int R, const double* __restrict__ Yt,
 #pragma unroll
         for (int q = 0; q < WB; ++q) {
             const int r = min(r0 + q, R - 1);
-            c[q] = C + ((int64_t)r * K + lab[(int64_t)r * n + i]) * dim;
+            c[q] = Ct + (int64_t)r * dim * Kpad + lab[(int64_t)r * n + i];
             acc[q] = 0.0;
         }
         for (int d = 0; d < dim; ++d) {
             const double y = Yt[(int64_t)d * n + i];
 #pragma unroll
             for (int q = 0; q < WB; ++q) {
-                const double diff = y - c[q][d];
+                const double diff = y - c[q][(int64_t)d * Kpad];
                 acc[q] = fma(diff, diff, acc[q]);
             }
         }
@@ -1028,7 +1152,7 @@ int assign_kpad(int K) {
 
 struct KmWs {
     double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
-    uint64_t *tsum, *keys, *keys_alt, *radix_tmp;
+    uint64_t *tsum, *keys, *keys_alt, *radix_tmp, *lhist, *lscan_tmp;
     uint32_t *vals, *vals_alt, *pts, *fl;
     int32_t* lab;
     int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
@@ -1056,6 +1180,8 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.part = c.take<double>(ceil_div(n, TH * 16) + 1);
     w.inertia = c.take<double>(1);
     w.tsum = c.take<uint64_t>((size_t)R * ceil_div(n, SEED_TILE));
+    w.lhist = c.take<uint64_t>((size_t)R * K * ceil_div(n, LS_TILE));
+    w.lscan_tmp = c.take<uint64_t>(scan_u64_batched_tmp_elems(K * ceil_div(n, LS_TILE), R));
     w.keys = c.take<uint64_t>(nr);
     w.keys_alt = c.take<uint64_t>(nr);
     w.vals = c.take<uint32_t>(nr);
@@ -1255,17 +1381,19 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         iterations = it;
         // centroid update from the stable member lists
         SC_CHECK_HIP(ctx, hipMemcpyAsync(w.Cold, w.C, cent_bytes, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_label_keys, gnr, dim3(TH), 0, st, n, R, w.active, w.lab, w.keys, w.vals);
-        SC_CHECK_LAUNCH(ctx);
-        // stable sort by label of each active restart's own range
-        for (int r = 0; r < R; ++r)
-            if (act_h[r])
-                SC_TRY(radix_sort_pairs(ctx, w.keys + (int64_t)r * n, w.vals + (int64_t)r * n,
-                                        w.keys_alt + (int64_t)r * n, w.vals_alt + (int64_t)r * n, n,
-                                        bits, w.radix_tmp));
-        hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div(2 * (int64_t)R * K, TH)), dim3(TH), 0, st, w.seg,
-                           2 * (int64_t)R * K);
-        hipLaunchKernelGGL(k_segments, gnr, dim3(TH), 0, st, n, K, R, w.active, w.keys, w.seg);
+        {
+            // member lists sorted by label, and every label's segment
+            const int lt = (int)ceil_div(n, LS_TILE);
+            const dim3 glt((unsigned)lt, (unsigned)R);
+            hipLaunchKernelGGL(k_lab_hist, glt, dim3(TH), 0, st, n, K, w.active, w.lab, w.lhist, lt);
+            SC_CHECK_LAUNCH(ctx);
+            SC_TRY(scan_u64_batched_exclusive(ctx, w.lhist, w.lhist, (int64_t)K * lt, R, w.lscan_tmp));
+            hipLaunchKernelGGL(k_lab_segments, dim3((unsigned)ceil_div((int64_t)R * K, TH)), dim3(TH), 0,
+                               st, n, K, R, w.active, w.lhist, lt, w.seg);
+            hipLaunchKernelGGL(k_lab_scatter, glt, dim3(TH), 0, st, n, K, bits, w.active, w.lab,
+                               w.lhist, lt, w.vals);
+            SC_CHECK_LAUNCH(ctx);
+        }
         {
             const int m = R * K;
             hipLaunchKernelGGL(k_block_counts, dim3(ceil_div(m, TH)), dim3(TH), 0, st, K, R, w.seg,
@@ -1344,14 +1472,14 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     }
     // exact distances to the final centres, integer inertia, best restart
     if (R <= 4)
-        hipLaunchKernelGGL((k_final_d2<4>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
-                           w.Yt, w.C, w.lab, w.D2);
+        hipLaunchKernelGGL((k_final_d2<4>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
+                           R, w.Yt, w.Ct, w.lab, w.D2);
     else if (R <= 10)
-        hipLaunchKernelGGL((k_final_d2<10>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
-                           w.Yt, w.C, w.lab, w.D2);
+        hipLaunchKernelGGL((k_final_d2<10>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
+                           R, w.Yt, w.Ct, w.lab, w.D2);
     else
-        hipLaunchKernelGGL((k_final_d2<16>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, R,
-                           w.Yt, w.C, w.lab, w.D2);
+        hipLaunchKernelGGL((k_final_d2<16>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
+                           R, w.Yt, w.Ct, w.lab, w.D2);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st, n,
                        w.D2, shift, w.q);

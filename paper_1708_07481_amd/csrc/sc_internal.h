@@ -103,9 +103,12 @@ static inline int ceil_log2_u64(uint64_t v) {
 size_t scan_u64_tmp_elems(int64_t n);
 sc_status scan_u64(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n, int inclusive,
                    uint64_t* tmp);
-// Batched inclusive scan: `batch` independent rows of length n (row stride n).
+// Batched inclusive (exclusive) scan: `batch` independent rows of length n
+// (row stride n), in place allowed.
 sc_status scan_u64_batched(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n, int batch,
                            uint64_t* tmp);
+sc_status scan_u64_batched_exclusive(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n,
+                                     int batch, uint64_t* tmp);
 size_t scan_u64_batched_tmp_elems(int64_t n, int batch);
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of key.

@@ -152,3 +152,8 @@ sc_status scan_u64_batched(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64
                            uint64_t* tmp) {
     return scan_impl(ctx, in, out, n, batch, 1, tmp);
 }
+
+sc_status scan_u64_batched_exclusive(sc_ctx* ctx, const uint64_t* in, uint64_t* out, int64_t n,
+                                     int batch, uint64_t* tmp) {
+    return scan_impl(ctx, in, out, n, batch, 0, tmp);
+}
