@@ -731,6 +731,134 @@ k_tridiag_coop(const int* __restrict__ info, double* __restrict__ M, double* __r
     }
 }
 
+// The same reduction with every workgroup's rows resident in LDS and one grid
+// barrier per column.  Row R belongs to workgroup R mod G (slot R / G), so
+// the trailing block stays spread over all workgroups.  Every workgroup keeps
+// the whole current column j (= row j, by symmetry) and computes the
+// reflector from it.  At step j each workgroup
+//   1. forms P_R = tau_j (A_R,trailing . v) for its rows and publishes P_R and
+//      its rows' entries of column j + 1 (before this step's update);
+//   2. after the barrier reads all of P and of column j + 1, forms
+//      w = P - (tau_j / 2)(P . v) v, updates column j + 1 itself (it is the
+//      next step's column) and applies A -= v w' + w v' to its own rows.
+// The arithmetic of every element is that of the two-barrier kernel above.
+// The exchange buffer X holds two sets (steps alternate) of P and column
+// values, 4 * MAXM doubles; a set is rewritten only after the barrier that
+// follows its last reader.
+__global__ void __launch_bounds__(TD_NT)
+k_tridiag_lds(const int* __restrict__ info, int m_max, double* __restrict__ M,
+              double* __restrict__ dtau, double* __restrict__ X, unsigned* __restrict__ bar,
+              int* status) {
+    extern __shared__ double lds[];
+    const int m = info[0];
+    if (m == 0) return;
+    const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slots = (m_max + G - 1) / G;
+    double* A = lds;                              // slots x m_max (own rows)
+    double* col = A + (int64_t)slots * m_max;     // current column, by row index
+    double* vs = col + m_max;                     // reflector, by trailing index
+    double* ws = vs + m_max;
+    __shared__ double red[TD_WAVES];
+    unsigned gen = 0;
+    // own rows and column 0, symmetrised
+    for (int s = 0; s * G + g < m; ++s) {
+        const int R = s * G + g;
+        for (int c = tid; c < m; c += TD_NT)
+            A[(int64_t)s * m_max + c] = 0.5 * (M[(int64_t)R * m + c] + M[(int64_t)c * m + R]);
+    }
+    for (int R = tid; R < m; R += TD_NT) col[R] = 0.5 * (M[(int64_t)R * m] + M[R]);
+    __syncthreads();
+    double* d = dtau;
+    double* e = d + MAXM;
+    double* tau = e + MAXM;
+    for (int j = 0; j + 2 < m; ++j) {
+        const int len = m - j - 1;
+        const double* x = col + j + 1;
+        double part = 0.0;
+        for (int r = 1 + tid; r < len; r += TD_NT) part = fma(x[r], x[r], part);
+        const double sigma = block_sum_td(part, red);
+        const double x0 = x[0];
+        double tj, v0, ej;
+        if (sigma == 0.0) {
+            tj = 0.0;
+            ej = x0;
+            v0 = 1.0;
+        } else {
+            const double mu = sqrt(x0 * x0 + sigma);
+            v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+            tj = 2.0 * v0 * v0 / (sigma + v0 * v0);
+            ej = mu;
+        }
+        if (g == 0 && tid == 0) {
+            d[j] = col[j];
+            e[j] = ej;
+            tau[j] = tj;
+        }
+        for (int r = tid; r < len; r += TD_NT) vs[r] = r == 0 ? 1.0 : x[r] / v0;
+        __syncthreads();
+        double* Pb = X + (int64_t)(j & 1) * 2 * MAXM;
+        double* Cb = Pb + MAXM;
+        // 1. own rows of the trailing block: P and the column j + 1 entries
+        const int s0 = (j + 1 - g + G - 1) / G;   // first slot with R >= j + 1
+        for (int s = s0 + wave; s * G + g < m; s += TD_WAVES) {
+            const int R = s * G + g;
+            const double* row = A + (int64_t)s * m_max + (j + 1);
+            double sacc = 0.0;
+            if (tj != 0.0) {
+                for (int c = lane; c < len; c += 64) sacc = fma(row[c], vs[c], sacc);
+                sacc = wave_sum(sacc);
+            }
+            if (lane == 0) {
+                Pb[R] = tj * sacc;
+                Cb[R] = row[0];
+            }
+        }
+        grid_sync(bar, gen, status);
+        // 2. w, the next column, and the update of the own rows
+        part = 0.0;
+        for (int r = tid; r < len; r += TD_NT) {
+            const double pr = Pb[j + 1 + r];
+            ws[r] = pr;
+            part = fma(pr, vs[r], part);
+        }
+        const double Kc = 0.5 * tj * block_sum_td(part, red);
+        for (int r = tid; r < len; r += TD_NT) ws[r] = ws[r] - Kc * vs[r];
+        __syncthreads();
+        for (int r = tid; r < len; r += TD_NT) {
+            const double cv = Cb[j + 1 + r];
+            col[j + 1 + r] = tj != 0.0 ? cv - (vs[r] * ws[0] + ws[r] * vs[0]) : cv;
+        }
+        if (tj != 0.0) {
+            for (int s = s0 + wave; s * G + g < m; s += TD_WAVES) {
+                const int r = s * G + g - (j + 1);
+                double* row = A + (int64_t)s * m_max + (j + 1);
+                const double vr = vs[r], wr = ws[r];
+                for (int c = lane; c < len; c += 64) row[c] -= vr * ws[c] + wr * vs[c];
+            }
+            // the reflector is kept in row j (not read again by the reduction)
+            if (g == 0)
+                for (int r = 1 + tid; r < len; r += TD_NT) M[(int64_t)j * m + j + 1 + r] = vs[r];
+        }
+        __syncthreads();
+    }
+    if (g == 0 && tid == 0) {
+        if (m >= 2) {
+            d[m - 2] = col[m - 2];
+            e[m - 2] = col[m - 1];
+            tau[m - 2] = 0.0;
+        }
+        tau[m - 1] = 0.0;
+    }
+    // the last diagonal entry from its owner's row
+    if (g == (m - 1) % G && tid == 0) d[m - 1] = A[(int64_t)((m - 1) / G) * m_max + (m - 1)];
+}
+
+size_t tridiag_lds_bytes(int m_max, int G) {
+    const int slots = (m_max + G - 1) / G;
+    return ((size_t)slots * m_max + 3 * (size_t)m_max) * sizeof(double);
+}
+
 __global__ void k_zero_u32(unsigned* p, int n) {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
 }
@@ -754,14 +882,30 @@ k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
     back_transform_col(m, M, dtau + 2 * MAXM, Q + i, k);
 }
 
-// reduction to tridiagonal form: the cooperative kernel when the matrix is
+// reduction to tridiagonal form: a cooperative kernel when the matrix is
 // large enough to feed many workgroups (m_max >= 128), else one workgroup.
-// `P` holds >= m_max doubles, `bar` two unsigned ints.
+// `P` holds >= 4 MAXM doubles, `bar` two unsigned ints.
 static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, double* M,
                                        double* tri, double* P, unsigned* bar, int* status) {
     hipStream_t st = ctx->stream;
     if (m_max >= 128) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
+        // rows resident in LDS when they fit, else the two-barrier kernel
+        const size_t lds = tridiag_lds_bytes(m_max, TD_GRID);
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) !=
+            hipSuccess)
+            lds_max = 0;
+        if (lds + 1024 <= (size_t)lds_max &&
+            hipFuncSetAttribute((const void*)k_tridiag_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) == hipSuccess) {
+            void* args[] = {(void*)&info, (void*)&m_max, (void*)&M, (void*)&tri, (void*)&P,
+                            (void*)&bar, (void*)&status};
+            const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tridiag_lds, dim3(TD_GRID),
+                                                            dim3(TD_NT), args, (unsigned)lds, st);
+            if (e == hipSuccess) return SC_OK;
+        }
+        (void)hipGetLastError();
         void* args[] = {(void*)&info, (void*)&M, (void*)&tri, (void*)&P, (void*)&bar, (void*)&status};
         const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tridiag_coop, dim3(TD_GRID),
                                                         dim3(TD_NT), args, 0, st);

@@ -26,7 +26,7 @@ def _theta_ok(tg, to):
 
 
 @pytest.mark.parametrize("m,k", [(1, 1), (2, 2), (5, 3), (24, 8), (60, 20), (132, 44),
-                                 (300, 98), (480, 160)])
+                                 (300, 98), (480, 160), (700, 50), (1000, 20)])
 def test_symeig_vs_numpy(ctx, m, k):
     from paper_1708_07481_amd import api
     rng = np.random.default_rng(m)
