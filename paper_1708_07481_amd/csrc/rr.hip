@@ -323,12 +323,17 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
 // clusters g, g + gridDim, ...  A cluster is first copied to the scratch Wt
 // with each vector contiguous (V itself is row-major, one row per entry), so
 // every dot product and update reads consecutive addresses; it is copied back
-// at the end.  Wt holds >= k * m doubles (vector q at Wt + q m).
+// at the end.  The vector being orthogonalised is held in LDS; each wave
+// forms four dot products per sweep over the rows, and the update keeps four
+// independent partial sums, so the loads of the earlier members overlap.
+// Wt holds >= k * m doubles (vector q at Wt + q m).
+constexpr int MGS_U = 4;
 __global__ void __launch_bounds__(NT)
 k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
           const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ Wt) {
     __shared__ double red[NWAVE + 1];
     __shared__ double dots[MAXM];
+    __shared__ double vl[MAXM];
     const int m = info[0];
     if (m == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -346,28 +351,49 @@ k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
             __syncthreads();
             for (int q = c0; q < c1; ++q) {
                 double* vq = Wt + (int64_t)q * m;
+                for (int r = tid; r < m; r += NT) vl[r] = vq[r];
+                __syncthreads();
                 for (int pass = 0; pass < 2 && q > c0; ++pass) {
-                    // dots with the earlier members, one wave per member
-                    for (int pp = c0 + wave; pp < q; pp += NWAVE) {
-                        const double* vp = Wt + (int64_t)pp * m;
-                        double part = 0.0;
-                        for (int r = lane; r < m; r += 64) part = fma(vp[r], vq[r], part);
+                    // dots with the earlier members, MGS_U members per wave sweep
+                    for (int p0 = c0 + wave * MGS_U; p0 < q; p0 += NWAVE * MGS_U) {
+                        double part[MGS_U];
+                        const double* vp[MGS_U];
 #pragma unroll
-                        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-                        if (lane == 0) dots[pp - c0] = part;
+                        for (int u = 0; u < MGS_U; ++u) {
+                            part[u] = 0.0;
+                            vp[u] = Wt + (int64_t)min(p0 + u, q - 1) * m;
+                        }
+                        for (int r = lane; r < m; r += 64) {
+                            const double y = vl[r];
+#pragma unroll
+                            for (int u = 0; u < MGS_U; ++u) part[u] = fma(vp[u][r], y, part[u]);
+                        }
+#pragma unroll
+                        for (int u = 0; u < MGS_U; ++u) {
+                            double t = part[u];
+#pragma unroll
+                            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+                            if (lane == 0 && p0 + u < q) dots[p0 + u - c0] = t;
+                        }
                     }
                     __syncthreads();
                     for (int r = tid; r < m; r += NT) {
-                        double x = vq[r];
-                        for (int pp = c0; pp < q; ++pp) x = fma(-dots[pp - c0], Wt[(int64_t)pp * m + r], x);
-                        vq[r] = x;
+                        double acc[MGS_U] = {};
+                        int pp = c0;
+                        for (; pp + MGS_U <= q; pp += MGS_U) {
+#pragma unroll
+                            for (int u = 0; u < MGS_U; ++u)
+                                acc[u] = fma(dots[pp + u - c0], Wt[(int64_t)(pp + u) * m + r], acc[u]);
+                        }
+                        for (; pp < q; ++pp) acc[0] = fma(dots[pp - c0], Wt[(int64_t)pp * m + r], acc[0]);
+                        vl[r] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
                     }
                     __syncthreads();
                 }
                 double part = 0.0;
-                for (int r = tid; r < m; r += NT) part = fma(vq[r], vq[r], part);
+                for (int r = tid; r < m; r += NT) part = fma(vl[r], vl[r], part);
                 const double inv = 1.0 / sqrt(block_sum(part, red));
-                for (int r = tid; r < m; r += NT) vq[r] *= inv;
+                for (int r = tid; r < m; r += NT) vq[r] = vl[r] * inv;
                 __syncthreads();
             }
             for (int e = tid; e < cs * m; e += NT) {
