@@ -8,7 +8,7 @@
 //   - k-means++ draws use integer weights floor(D2 * 2^s) and an exact
 //     integer prefix sum;
 //   - a centroid is the sum of its members in ascending vertex order (a
-//     stable radix sort by label gives the member lists), divided by the count;
+//     stable counting sort by label gives the member lists), divided by the count;
 //   - the restart with the least integer inertia wins (ties: lowest restart).
 // Lloyd iterations skip points whose assignment provably cannot change
 // (Hamerly's bounds: an upper bound on the distance to the assigned centre
@@ -407,7 +407,7 @@ constexpr int PR_DC = 8;
 constexpr int PR_KMAX = 1024;
 constexpr int PR_KMAX_HS = PR_KMAX;
 constexpr int PR_WIDE = 16;
-constexpr int PR_SORT_MIN = 2048;       // lists at least this long are ordered by label
+constexpr int PR_LIST_MIN = 2048;       // shorter lists go to the full scan whole
 // the pruned path runs when (points listed over all restarts) x K reaches this
 constexpr int64_t PR_WORK_MIN = 32000000;
 
@@ -446,21 +446,14 @@ k_half_sep(int K, int Kpad, int dim, const double* __restrict__ Ct, const int* _
     }
 }
 
-// sort keys of a scan list: the point's current label, with the point as value
-__global__ void k_list_keys(int64_t n, int c, const int32_t* __restrict__ lab,
-                            const uint32_t* __restrict__ pts, uint64_t* __restrict__ keys) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < c) keys[q] = (uint64_t)lab[pts[q]];
-}
-
 // Lloyd scan of the listed points with Elkan pruning.  Each wave owns 64
-// consecutive list entries; a long list is ordered by current label, so a
+// consecutive list entries; the list is ordered by current label, so a
 // wave's points share one or a few labels.
 //   1. The exact distance to the assigned centre a gives a tight bound u.
 //   2. A centre j with u < h(a, j) cannot be nearer than c_a.  A point that
 //      cannot rule out more than PR_WIDE centres is "wide" and is handed to
 //      the full scan (appended to the list fl), and so is every point of a
-//      short, unordered list.  The rest are "narrow": their candidates are
+//      list shorter than PR_LIST_MIN.  The rest are "narrow": their candidates are
 //      the head of their centre's sorted row, merged into a wave bitmap.
 //   3. The wave scans the union of the narrow points' candidates, in
 //      ascending order, JB at a time.
@@ -514,8 +507,8 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
     const uint32_t i = pts[(int64_t)r * n + q0 + min(lane, np - 1)];
     const int64_t e = (int64_t)r * n + i;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
-    if (c < PR_SORT_MIN) {
-        // short, unordered list: every point goes to the full scan
+    if (c < PR_LIST_MIN) {
+        // short list: every point goes to the full scan
         const unsigned long long mask = __ballot(live);
         int base = 0;
         if (lane == 0) base = atomicAdd(&fcnt[r], (int)__popcll(mask));
@@ -818,9 +811,12 @@ __device__ inline uint32_t ls_block_excl_scan(uint32_t v, uint32_t* total, uint3
     return r;
 }
 
-// grid (tiles, R)
+// The same sort serves the scan lists: with `list` given, restart r sorts its
+// first counts[r] entries list[r n + q] by lab[r n + list[r n + q]]; without,
+// it sorts its points 0 .. n - 1.  grid (tiles, R)
 __global__ void __launch_bounds__(TH)
 k_lab_hist(int64_t n, int K, const int* __restrict__ active, const int32_t* __restrict__ lab,
+           const uint32_t* __restrict__ list, const int* __restrict__ counts,
            uint64_t* __restrict__ hist, int ntiles) {
     __shared__ uint32_t h[PR_KMAX];
     const int r = blockIdx.y;
@@ -828,11 +824,13 @@ k_lab_hist(int64_t n, int K, const int* __restrict__ active, const int32_t* __re
     for (int b = threadIdx.x; b < K; b += TH) h[b] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * LS_TILE;
+    const int64_t c = list ? counts[r] : n;
     const int32_t* lr = lab + (int64_t)r * n;
+    const uint32_t* li = list ? list + (int64_t)r * n : nullptr;
 #pragma unroll
     for (int t = 0; t < LS_ITEMS; ++t) {
         const int64_t idx = base + (int64_t)t * TH + threadIdx.x;
-        if (idx < n) atomicAdd(&h[lr[idx]], 1u);
+        if (idx < c) atomicAdd(&h[lr[li ? li[idx] : idx]], 1u);
     }
     __syncthreads();
     uint64_t* hr = hist + (int64_t)r * K * ntiles;
@@ -858,7 +856,8 @@ __global__ void k_lab_segments(int64_t n, int K, int R, const int* __restrict__ 
 // grid (tiles, R); vals[r n + position] = vertex
 __global__ void __launch_bounds__(TH)
 k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
-              const int32_t* __restrict__ lab, const uint64_t* __restrict__ off, int ntiles,
+              const int32_t* __restrict__ lab, const uint32_t* __restrict__ list,
+              const int* __restrict__ counts, const uint64_t* __restrict__ off, int ntiles,
               uint32_t* __restrict__ vals) {
     __shared__ uint16_t kb[2][LS_TILE];
     __shared__ uint32_t vb[2][LS_TILE];
@@ -867,15 +866,19 @@ k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
     const int r = blockIdx.y;
     if (!active[r]) return;
     const int64_t base = (int64_t)blockIdx.x * LS_TILE;
-    const int cnt = (int)min<int64_t>(LS_TILE, n - base);
+    const int64_t c = list ? counts[r] : n;
+    if (base >= c) return;
+    const int cnt = (int)min<int64_t>(LS_TILE, c - base);
     const int32_t* lr = lab + (int64_t)r * n;
+    const uint32_t* li = list ? list + (int64_t)r * n : nullptr;
     // padding carries the largest key and stays behind every real point
     const uint16_t pad = (uint16_t)((1u << nbits) - 1u);
 #pragma unroll
     for (int t = 0; t < LS_ITEMS; ++t) {
         const int p = t * TH + threadIdx.x;
-        kb[0][p] = p < cnt ? (uint16_t)lr[base + p] : pad;
-        vb[0][p] = (uint32_t)(base + p);
+        const uint32_t v = p < cnt ? (li ? li[base + p] : (uint32_t)(base + p)) : 0u;
+        kb[0][p] = p < cnt ? (uint16_t)lr[v] : pad;
+        vb[0][p] = v;
     }
     __syncthreads();
     int cur = 0;
@@ -1152,8 +1155,8 @@ int assign_kpad(int K) {
 
 struct KmWs {
     double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
-    uint64_t *tsum, *keys, *keys_alt, *radix_tmp, *lhist, *lscan_tmp;
-    uint32_t *vals, *vals_alt, *pts, *fl;
+    uint64_t *tsum, *lhist, *lscan_tmp;
+    uint32_t *vals, *pts, *fl;
     int32_t* lab;
     int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
     int64_t* seg;
@@ -1182,13 +1185,9 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.tsum = c.take<uint64_t>((size_t)R * ceil_div(n, SEED_TILE));
     w.lhist = c.take<uint64_t>((size_t)R * K * ceil_div(n, LS_TILE));
     w.lscan_tmp = c.take<uint64_t>(scan_u64_batched_tmp_elems(K * ceil_div(n, LS_TILE), R));
-    w.keys = c.take<uint64_t>(nr);
-    w.keys_alt = c.take<uint64_t>(nr);
     w.vals = c.take<uint32_t>(nr);
-    w.vals_alt = c.take<uint32_t>(nr);
     w.pts = c.take<uint32_t>(nr);
-    w.fl = w.vals_alt;                        // full-scan lists: free once the list sorts are done
-    w.radix_tmp = c.take<uint64_t>(radix_tmp_elems(nr));
+    w.fl = c.take<uint32_t>(nr);              // full-scan lists
     w.lab = c.take<int32_t>(nr);
     w.changed = c.take<int>(R);
     w.active = c.take<int>(R);
@@ -1254,10 +1253,11 @@ void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs
 }
 
 template <int JB>
-void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int max_cnt) {
+void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
+                   const uint32_t* list, int max_cnt) {
     dim3 grid((unsigned)ceil_div(max_cnt, TH), (unsigned)R);
     hipLaunchKernelGGL((k_assign_pruned<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
-                       assign_kpad(K), w.Y, w.Ct, w.hsv, w.hsi, w.pts, w.cnt, w.active, w.lab, w.ub, w.lb,
+                       assign_kpad(K), w.Y, w.Ct, w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb,
                        w.changed, w.dirty, w.fl, w.fcnt);
 }
 
@@ -1385,13 +1385,14 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             // member lists sorted by label, and every label's segment
             const int lt = (int)ceil_div(n, LS_TILE);
             const dim3 glt((unsigned)lt, (unsigned)R);
-            hipLaunchKernelGGL(k_lab_hist, glt, dim3(TH), 0, st, n, K, w.active, w.lab, w.lhist, lt);
+            hipLaunchKernelGGL(k_lab_hist, glt, dim3(TH), 0, st, n, K, w.active, w.lab, nullptr, nullptr,
+                               w.lhist, lt);
             SC_CHECK_LAUNCH(ctx);
             SC_TRY(scan_u64_batched_exclusive(ctx, w.lhist, w.lhist, (int64_t)K * lt, R, w.lscan_tmp));
             hipLaunchKernelGGL(k_lab_segments, dim3((unsigned)ceil_div((int64_t)R * K, TH)), dim3(TH), 0,
                                st, n, K, R, w.active, w.lhist, lt, w.seg);
             hipLaunchKernelGGL(k_lab_scatter, glt, dim3(TH), 0, st, n, K, bits, w.active, w.lab,
-                               w.lhist, lt, w.vals);
+                               nullptr, nullptr, w.lhist, lt, w.vals);
             SC_CHECK_LAUNCH(ctx);
         }
         {
@@ -1436,19 +1437,21 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                            (opts->scan == SC_KM_SCAN_AUTO && total * K >= PR_WORK_MIN);
         if (prune) {
             // long lists: ordered by current label (stable: ascending point
-            // within a label), pruned scans, then full scans of the points
-            // those cannot settle
-            for (int r = 0; r < R; ++r) {
-                const int cr = cnt_h[r];
-                if (!act_h[r] || cr < PR_SORT_MIN) continue;
-                const int64_t o = (int64_t)r * n;
-                hipLaunchKernelGGL(k_list_keys, dim3((unsigned)ceil_div(cr, TH)), dim3(TH), 0, st, n,
-                                   cr, w.lab + o, w.pts + o, w.keys + o);
+            // within a label) into vals, pruned scans, then full scans of the
+            // points those cannot settle
+            {
+                const int lt = (int)ceil_div(max_cnt, LS_TILE);
+                const dim3 glt((unsigned)lt, (unsigned)R);
+                hipLaunchKernelGGL(k_lab_hist, glt, dim3(TH), 0, st, n, K, w.active, w.lab, w.pts,
+                                   w.cnt, w.lhist, lt);
                 SC_CHECK_LAUNCH(ctx);
-                SC_TRY(radix_sort_pairs(ctx, w.keys + o, w.pts + o, w.keys_alt + o, w.vals_alt + o,
-                                        cr, bits, w.radix_tmp));
+                SC_TRY(scan_u64_batched_exclusive(ctx, w.lhist, w.lhist, (int64_t)K * lt, R,
+                                                  w.lscan_tmp));
+                hipLaunchKernelGGL(k_lab_scatter, glt, dim3(TH), 0, st, n, K, bits, w.active, w.lab,
+                                   w.pts, w.cnt, w.lhist, lt, w.vals);
+                SC_CHECK_LAUNCH(ctx);
             }
-            launch_pruned<8>(ctx, n, dim, K, R, w, max_cnt);
+            launch_pruned<8>(ctx, n, dim, K, R, w, w.vals, max_cnt);
             SC_CHECK_LAUNCH(ctx);
             assign(ctx, n, dim, K, R, w, 0, w.fl, w.fcnt, max_cnt);
             SC_CHECK_LAUNCH(ctx);
