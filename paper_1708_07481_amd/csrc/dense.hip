@@ -435,6 +435,154 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
     }
 }
 
+// The same factor with the equilibrated Gram matrix resident in LDS (packed
+// upper triangle), for up to CQL_MAXM columns, same modes, pivot test and
+// outputs as k_cholqr_factor:
+//   - the active columns are flagged in parallel and listed by one thread
+//     from LDS;
+//   - Cholesky column by column: every thread forms the pivot, the pivot row
+//     is scaled, the trailing triangle takes the rank-one update (one wave
+//     per row); two barriers per column;
+//   - R^-1 one wave per column j by a column sweep of R x = e_j: for
+//     a = j .. 0, x_a = b_a / R(a, a) (b_a broadcast from its lane), then
+//     b_l -= R(l, a) x_a on the lanes' rows l < a; no cross-lane reductions.
+constexpr int CQL_MAXM = 176;
+constexpr int CQL_SLOTS = (CQL_MAXM + 63) / 64;
+__device__ inline int cql_off(int a, int m) { return a * m - (a * (a - 1)) / 2; }
+
+__device__ inline double cql_readlane(double v, int lane) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__global__ void __launch_bounds__(CQ_TH)
+k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask, double tol,
+                    double* __restrict__ T64, float* __restrict__ T32, int mode, int* status,
+                    int* counter) {
+    __shared__ double P[CQL_MAXM * (CQL_MAXM + 1) / 2];
+    __shared__ double d[CQL_MAXM], diag0[CQL_MAXM], gd[CQL_MAXM];
+    __shared__ int idx[CQL_MAXM], ok[CQL_MAXM];
+    __shared__ int m_s, fail_s, fail_at;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int NW = CQ_TH / 64;
+    int m = 0;
+    for (int pass = 0; pass <= c; ++pass) {
+        for (int j = tid; j < c; j += CQ_TH) {
+            const double g = G[(int64_t)j * c + j];
+            ok[j] = mask[j] ? ((isfinite(g) && g > 0.0) ? 1 : 2) : 0;
+            gd[j] = g;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int mm = 0, missing = 0;
+            for (int j = 0; j < c; ++j) {
+                if (ok[j] == 1) {
+                    idx[mm] = j;
+                    d[mm] = sqrt(gd[j]);
+                    ++mm;
+                } else if (ok[j] == 2) {
+                    missing = 1;
+                    mask[j] = 0;
+                }
+            }
+            m_s = mm;
+            fail_s = (mode == CQ_REQUIRE_ALL && missing) ? 1 : 0;
+            fail_at = -1;
+        }
+        __syncthreads();
+        m = m_s;
+        if (fail_s) break;
+        for (int a = wave; a < m; a += NW) {
+            const int o = cql_off(a, m) - a;
+            for (int b = a + lane; b < m; b += 64) {
+                const double v = G[(int64_t)idx[a] * c + idx[b]] / (d[a] * d[b]);
+                P[o + b] = v;
+                if (b == a) diag0[a] = v;
+            }
+        }
+        __syncthreads();
+        int fa = -1;
+        for (int j = 0; j < m; ++j) {
+            const int oj = cql_off(j, m) - j;
+            const double sj = P[oj + j];
+            if (!isfinite(sj) || !(sj > tol * diag0[j]) || !(sj > 0.0)) {
+                fa = j;                              // the same decision in every thread
+                break;
+            }
+            const double rjj = sqrt(sj);
+            for (int b = j + 1 + tid; b < m; b += CQ_TH) P[oj + b] /= rjj;
+            __syncthreads();
+            if (tid == 0) P[oj + j] = rjj;
+            for (int a = j + 1 + wave; a < m; a += NW) {
+                const int o = cql_off(a, m) - a;
+                const double xa = P[oj + a];
+                for (int b = a + lane; b < m; b += 64) P[o + b] -= xa * P[oj + b];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            fail_at = fa;
+            fail_s = fa >= 0;
+        }
+        __syncthreads();
+        if (!fail_s || mode != CQ_DROP_DEPENDENT) break;
+        // the failing column is (numerically) in the span of the earlier ones
+        if (tid == 0) {
+            mask[idx[fail_at]] = 0;
+            if (counter) atomicAdd(counter, 1);
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < c * c; e += CQ_TH) {
+        T64[e] = 0.0;
+        T32[e] = 0.0f;
+    }
+    if (fail_s) {
+        if (tid == 0) {
+            if (mode == CQ_DROP_ALL) {
+                for (int j = 0; j < c; ++j) mask[j] = 0;
+                atomicOr(status, DEV_P_DROPPED);
+                if (counter) atomicAdd(counter, 1);
+            } else {
+                atomicOr(status, DEV_BREAKDOWN);
+            }
+        }
+        return;
+    }
+    __syncthreads();
+    // R^-1 by column sweeps; lane l holds rows l, l + 64, ...
+    for (int j = wave; j < m; j += NW) {
+        double x[CQL_SLOTS];
+#pragma unroll
+        for (int t = 0; t < CQL_SLOTS; ++t) x[t] = (lane + 64 * t == j) ? 1.0 : 0.0;
+        for (int a = j; a >= 0; --a) {
+            const int ta = a >> 6, la = a & 63;
+            double xa_src = x[0];
+#pragma unroll
+            for (int t = 1; t < CQL_SLOTS; ++t)
+                if (t == ta) xa_src = x[t];
+            const double xa = cql_readlane(xa_src, la) / P[cql_off(a, m)];
+#pragma unroll
+            for (int t = 0; t < CQL_SLOTS; ++t) {
+                const int l = lane + 64 * t;
+                if (l == a) x[t] = xa;
+                else if (l < a) x[t] -= P[cql_off(l, m) - l + a] * xa;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < CQL_SLOTS; ++t) {
+            const int l = lane + 64 * t;
+            if (l <= j) {
+                const double v = x[t] / d[l];
+                T64[(int64_t)idx[l] * c + idx[j]] = v;
+                T32[(int64_t)idx[l] * c + idx[j]] = (float)v;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row-block products with a small matrix, in place.  For every row of V:
 //   acc1[j] = sum_{l in [a0,a1)} V[row][l] M[l][j]
@@ -723,8 +871,12 @@ sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, d
                                double* T64, float* T32, double* scratch, int mode,
                                int* status, int* counter) {
     if (c > CQ_MAX) return sc_fail(ctx, SC_E_UNSUPPORTED, "cholqr: %d columns > %d", c, CQ_MAX);
-    hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(CQ_TH), 0, ctx->stream, c, G, mask, tol, T64,
-                       T32, scratch, mode, status, counter);
+    if (c <= CQL_MAXM)
+        hipLaunchKernelGGL(k_cholqr_factor_lds, dim3(1), dim3(CQ_TH), 0, ctx->stream, c, G, mask, tol,
+                           T64, T32, mode, status, counter);
+    else
+        hipLaunchKernelGGL(k_cholqr_factor, dim3(1), dim3(CQ_TH), 0, ctx->stream, c, G, mask, tol,
+                           T64, T32, scratch, mode, status, counter);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }

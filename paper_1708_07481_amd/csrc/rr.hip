@@ -231,13 +231,21 @@ k_tri_bisect(int k, const int* __restrict__ info, const double* __restrict__ tri
     if (lane == 0) w[i] = 0.5 * (lo + hi);
 }
 
-// one thread per eigenvector; LU arrays laid out [q][eigenvector] so that
-// the lanes of a wave touch consecutive addresses
-__global__ void __launch_bounds__(64)
+// one thread per eigenvector, IV_T eigenvectors per workgroup.  The LU
+// factors live in global memory laid out [q][eigenvector] (a workgroup's
+// threads touch consecutive addresses); the iterate z lives in LDS during the
+// sweeps and is written to V once at the end, so the sweeps issue no global
+// stores and their loads of the (read-only) factors never wait for stores.
+// Factorisation and sweeps are serial recurrences whose loads do not depend
+// on the recurrence: they are issued IV_B steps ahead.
+constexpr int IV_B = 8;
+constexpr int IV_T = 16;
+__global__ void __launch_bounds__(IV_T)
 k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
             const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ lu) {
+    __shared__ double zs[MAXM * IV_T];
     const int m = info[0];
-    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int i = blockIdx.x * IV_T + threadIdx.x;
     if (m == 0 || i >= k) return;
     const double* d = tri;
     const double* e = tri + MAXM;
@@ -257,22 +265,53 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
     double* Lm = U2 + (int64_t)MAXM * k;
     double* SW = Lm + (int64_t)MAXM * k;
 #define AT(arr, q) arr[(int64_t)(q) * k + i]
-    double r0 = d[0] - lam, r1 = m > 1 ? e[0] : 0.0;
-    for (int q = 0; q + 1 < m; ++q) {
-        const double sub = e[q];
-        const double a1 = d[q + 1] - lam;
-        const double b1 = q + 2 < m ? e[q + 1] : 0.0;
-        if (fabs(r0) >= fabs(sub)) {
-            if (r0 == 0.0) r0 = tiny;
-            const double l = sub / r0;
-            AT(U0, q) = r0; AT(U1, q) = r1; AT(U2, q) = 0.0; AT(Lm, q) = l; AT(SW, q) = 0.0;
-            r0 = a1 - l * r1;
-            r1 = b1;
-        } else {
-            const double l = r0 / sub;
-            AT(U0, q) = sub; AT(U1, q) = a1; AT(U2, q) = b1; AT(Lm, q) = l; AT(SW, q) = 1.0;
-            r0 = r1 - l * a1;
-            r1 = -l * b1;
+#define ZS(q) zs[(q) * IV_T + threadIdx.x]
+    // LU with partial pivoting of T - lam I (rows q, q + 1 per step); the
+    // factors of a block are stored after the next block's loads
+    const int nq = m - 1;                        // steps
+    double r0 = d[0] - lam, r1 = (m > 1 ? e[0] : 0.0) + 0.0;
+    {
+        double sub[IV_B], a1[IV_B], b1[IV_B];
+        double f0[IV_B], f1[IV_B], f2[IV_B], fl[IV_B], fs[IV_B];
+        auto load = [&](int q0) {
+#pragma unroll
+            for (int t = 0; t < IV_B; ++t) {
+                const int q = min(q0 + t, nq - 1);
+                sub[t] = e[q];
+                a1[t] = d[q + 1] - lam;
+                b1[t] = q + 2 < m ? e[q + 1] : 0.0;
+            }
+        };
+        if (nq > 0) load(0);
+        for (int q0 = 0; q0 < nq; q0 += IV_B) {
+            const int nb = min(IV_B, nq - q0);
+#pragma unroll
+            for (int t = 0; t < IV_B; ++t) {
+                if (t < nb) {
+                    // keep row q (no interchange) or swap in row q + 1
+                    const bool keep = fabs(r0) >= fabs(sub[t]);
+                    const double p0 = (keep && r0 == 0.0) ? tiny : r0;
+                    const double l = keep ? sub[t] / p0 : p0 / sub[t];
+                    f0[t] = keep ? p0 : sub[t];
+                    f1[t] = keep ? r1 : a1[t];
+                    f2[t] = keep ? 0.0 : b1[t];
+                    fl[t] = l;
+                    fs[t] = keep ? 0.0 : 1.0;
+                    const double n0 = keep ? a1[t] - l * r1 : r1 - l * a1[t];
+                    const double n1 = keep ? b1[t] : -l * b1[t];
+                    r0 = n0;
+                    r1 = n1;
+                }
+            }
+            if (q0 + IV_B < nq) load(q0 + IV_B);
+#pragma unroll
+            for (int t = 0; t < IV_B; ++t) {
+                if (t < nb) {
+                    const int q = q0 + t;
+                    AT(U0, q) = f0[t]; AT(U1, q) = f1[t]; AT(U2, q) = f2[t]; AT(Lm, q) = fl[t];
+                    AT(SW, q) = fs[t];
+                }
+            }
         }
     }
     if (r0 == 0.0) r0 = tiny;
@@ -281,39 +320,90 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
     // zero) by the back substitution, so they must not hold stale NaN / Inf
     AT(U1, m - 1) = 0.0;
     AT(U2, m - 1) = 0.0;
-    double* z = V + i;      // column i, row stride ldv
     for (int r = 0; r < m; ++r)
-        z[(int64_t)r * ldv] =
-            (double)(mix64(((uint64_t)i << 32) ^ (uint64_t)r) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        ZS(r) = (double)(mix64(((uint64_t)i << 32) ^ (uint64_t)r) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    double inv = 1.0;
     for (int itn = 0; itn < 3; ++itn) {
-        double rc = z[0];
-        for (int q = 0; q + 1 < m; ++q) {
-            const double nxt = z[(int64_t)(q + 1) * ldv];
-            const double l = AT(Lm, q);
-            if (AT(SW, q) != 0.0) {
-                z[(int64_t)q * ldv] = nxt;
-                rc = rc - l * nxt;
-            } else {
-                z[(int64_t)q * ldv] = rc;
-                rc = nxt - l * rc;
+        // forward sweep (row interchanges and L)
+        double rc = ZS(0) * inv;
+        {
+            double l[IV_B], sw[IV_B];
+            auto load = [&](int q0) {
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    const int q = min(q0 + t, nq - 1);
+                    l[t] = AT(Lm, q);
+                    sw[t] = AT(SW, q);
+                }
+            };
+            if (nq > 0) load(0);
+            for (int q0 = 0; q0 < nq; q0 += IV_B) {
+                const int nb = min(IV_B, nq - q0);
+                double nxt[IV_B], lc[IV_B], swc[IV_B];
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    nxt[t] = t < nb ? ZS(q0 + t + 1) * inv : 0.0;
+                    lc[t] = l[t];
+                    swc[t] = sw[t];
+                }
+                if (q0 + IV_B < nq) load(q0 + IV_B);
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    if (t < nb) {
+                        const bool swp = swc[t] != 0.0;
+                        ZS(q0 + t) = swp ? nxt[t] : rc;
+                        rc = swp ? rc - lc[t] * nxt[t] : nxt[t] - lc[t] * rc;
+                    }
+                }
             }
         }
-        z[(int64_t)(m - 1) * ldv] = rc;
+        ZS(m - 1) = rc;
         // back substitution; the last two solution values stay in registers
         double z1 = 0.0, z2 = 0.0, nn = 0.0;
-        for (int q = m - 1; q >= 0; --q) {
-            double sacc = z[(int64_t)q * ldv];
-            sacc -= AT(U1, q) * z1;
-            sacc -= AT(U2, q) * z2;
-            const double zq = sacc / AT(U0, q);
-            z[(int64_t)q * ldv] = zq;
-            nn = fma(zq, zq, nn);
-            z2 = z1;
-            z1 = zq;
+        {
+            double u0[IV_B], u1[IV_B], u2[IV_B];
+            auto load = [&](int q1) {
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    const int q = max(q1 - t, 0);
+                    u0[t] = AT(U0, q);
+                    u1[t] = AT(U1, q);
+                    u2[t] = AT(U2, q);
+                }
+            };
+            load(m - 1);
+            for (int q1 = m - 1; q1 >= 0; q1 -= IV_B) {
+                const int nb = min(IV_B, q1 + 1);
+                double zc[IV_B], a0[IV_B], a1v[IV_B], a2[IV_B];
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    zc[t] = t < nb ? ZS(q1 - t) : 0.0;
+                    a0[t] = u0[t];
+                    a1v[t] = u1[t];
+                    a2[t] = u2[t];
+                }
+                if (q1 - IV_B >= 0) load(q1 - IV_B);
+#pragma unroll
+                for (int t = 0; t < IV_B; ++t) {
+                    if (t < nb) {
+                        double sacc = zc[t];
+                        sacc -= a1v[t] * z1;
+                        sacc -= a2[t] * z2;
+                        const double zq = sacc / a0[t];
+                        ZS(q1 - t) = zq;
+                        nn = fma(zq, zq, nn);
+                        z2 = z1;
+                        z1 = zq;
+                    }
+                }
+            }
         }
-        const double inv = 1.0 / sqrt(nn);
-        for (int r = 0; r < m; ++r) z[(int64_t)r * ldv] *= inv;
+        // the normalisation is applied where z is next read
+        inv = 1.0 / sqrt(nn);
     }
+    double* z = V + i;      // column i, row stride ldv
+    for (int r = 0; r < m; ++r) z[(int64_t)r * ldv] = ZS(r) * inv;
+#undef ZS
 #undef AT
 }
 
@@ -902,10 +992,19 @@ __global__ void k_copy_f64(int64_t n, const double* __restrict__ a, double* __re
 __global__ void __launch_bounds__(256)
 k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
           const double* __restrict__ dtau, double* __restrict__ Q) {
+    // the wave's column stays in LDS while the reflectors are applied (their
+    // loads are then never queued behind stores to the column)
+    __shared__ double col[4][MAXM];
     const int m = info[0];
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wave;
     if (m == 0 || i >= k) return;
-    back_transform_col(m, M, dtau + 2 * MAXM, Q + i, k);
+    double* cv = col[wave];
+    for (int r = lane; r < m; r += 64) cv[r] = Q[(int64_t)r * k + i];
+    __builtin_amdgcn_wave_barrier();
+    back_transform_col(m, M, dtau + 2 * MAXM, cv, 1);
+    __builtin_amdgcn_wave_barrier();
+    for (int r = lane; r < m; r += 64) Q[(int64_t)r * k + i] = cv[r];
 }
 
 // reduction to tridiagonal form: a cooperative kernel when the matrix is
@@ -949,8 +1048,8 @@ static void eig_pipeline(hipStream_t st, int k, const int* info, const double* M
                          double* w, double* V, double* lu) {
     hipLaunchKernelGGL(k_tri_params, dim3(1), dim3(NT), 0, st, info, tri);
     hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, tri, w);
-    hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, 64)), dim3(64), 0, st, k, info, tri, w,
-                       V, k, lu);
+    hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, IV_T)), dim3(IV_T), 0, st, k, info,
+                       tri, w, V, k, lu);
     // the inverse-iteration LU arrays (5 MAXM k doubles) are free again: cluster scratch
     hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k, lu);
     hipLaunchKernelGGL(k_rr_back, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, M, tri, V);
