@@ -527,7 +527,7 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
            int* __restrict__ act, double tol, double* __restrict__ U, double* __restrict__ Am,
            int* __restrict__ info, int* status, int* counter, const int* __restrict__ pred,
            int* __restrict__ probe, int* __restrict__ probe_counter, int* __restrict__ wcounter) {
-    __shared__ int idx[MAXM];
+    __shared__ int idx[MAXM], actl[MAXM];
     __shared__ int m_s, fail_s, fail_at, has_p;
     __shared__ CholLds L;
     if (pred && *pred == 0) return;
@@ -535,10 +535,13 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
     int m = 0;
     // each failed attempt removes P, or (with wcounter) one dependent W column
     for (int attempt = 0; attempt < K3 + 2; ++attempt) {
+        // active columns: flags read in parallel, listed from LDS by one thread
+        for (int j = tid; j < K3; j += NT) actl[j] = act[j];
+        __syncthreads();
         if (tid == 0) {
             int mm = 0;
             for (int j = 0; j < K3; ++j)
-                if (act[j]) idx[mm++] = j;
+                if (actl[j]) idx[mm++] = j;
             m_s = mm;
             fail_s = 0;
             fail_at = -1;
@@ -659,29 +662,74 @@ k_gemm64(const int* __restrict__ info, int n_fixed, int transA, const double* __
     }
 }
 
-// --- step 2: U^-1 (upper triangular), one wave per column j: back
-// substitution from row j-1 up to row 0, each row's dot product split over
-// the lanes; the column being built lives in LDS.
+// --- step 2: U^-1 (upper triangular), one wave per row i: the row x' of U^-1
+// solves x' U = e_i', a forward sweep over c = i .. m-1 with x_c = b_c / U(c, c)
+// and b_l -= x_c U(c, l) for l > c.  Lane l holds entries l, l + 64, ...; each
+// step reads one contiguous row of U and broadcasts b_c from its lane, with no
+// cross-lane reductions.  U was written by another workgroup (often another
+// XCD), so rows are loaded INV_G steps ahead.
+constexpr int INV_G = 4;
+
+__device__ inline double rr_readlane(double v, int lane) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// INV_SLOTS * 64 >= m: the launch picks the smallest of 8 and 16
+template <int INV_SLOTS>
 __global__ void __launch_bounds__(256)
 k_rr_inv(const int* __restrict__ info, const double* __restrict__ U, double* __restrict__ Ui) {
-    __shared__ double col[4][MAXM];
     const int m = info[0];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + wave;
-    if (j >= m) return;
-    double* cj = col[wave];
-    if (lane == 0) cj[j] = 1.0 / U[(int64_t)j * m + j];
-    __builtin_amdgcn_wave_barrier();
-    for (int a = j - 1; a >= 0; --a) {
-        double part = 0.0;
-        for (int l = a + 1 + lane; l <= j; l += 64) part = fma(U[(int64_t)a * m + l], cj[l], part);
+    const int i = blockIdx.x * 4 + wave;
+    if (i >= m) return;
+    double x[INV_SLOTS], u[INV_G][INV_SLOTS], un[INV_G][INV_SLOTS];
+    auto load = [&](double (&dst)[INV_G][INV_SLOTS], int c0) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        const double x = -part / U[(int64_t)a * m + a];
-        if (lane == 0) cj[a] = x;
-        __builtin_amdgcn_wave_barrier();
+        for (int g = 0; g < INV_G; ++g)
+#pragma unroll
+            for (int t = 0; t < INV_SLOTS; ++t) {
+                const int l = lane + 64 * t, c = c0 + g;
+                dst[g][t] = (c < m && l < m) ? U[(int64_t)c * m + l] : 0.0;
+            }
+    };
+#pragma unroll
+    for (int t = 0; t < INV_SLOTS; ++t) x[t] = lane + 64 * t == i ? 1.0 : 0.0;
+    load(u, i);
+    for (int c0 = i; c0 < m; c0 += INV_G) {
+        if (c0 + INV_G < m) load(un, c0 + INV_G);
+#pragma unroll
+        for (int g = 0; g < INV_G; ++g) {
+            const int c = c0 + g;
+            if (c >= m) break;
+            const int tc = c >> 6, lc = c & 63;
+            double bsrc = x[0], dsrc = u[g][0];
+#pragma unroll
+            for (int t = 1; t < INV_SLOTS; ++t)
+                if (t == tc) {
+                    bsrc = x[t];
+                    dsrc = u[g][t];
+                }
+            const double xc = rr_readlane(bsrc, lc) / rr_readlane(dsrc, lc);
+#pragma unroll
+            for (int t = 0; t < INV_SLOTS; ++t) {
+                const int l = lane + 64 * t;
+                if (l == c) x[t] = xc;
+                else if (l > c) x[t] -= xc * u[g][t];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < INV_G; ++g)
+#pragma unroll
+            for (int t = 0; t < INV_SLOTS; ++t) u[g][t] = un[g][t];
     }
-    for (int a = lane; a < m; a += 64) Ui[(int64_t)a * m + j] = a <= j ? cj[a] : 0.0;
+#pragma unroll
+    for (int t = 0; t < INV_SLOTS; ++t) {
+        const int l = lane + 64 * t;
+        if (l < m) Ui[(int64_t)i * m + l] = l >= i ? x[t] : 0.0;
+    }
 }
 
 // --- step 3a (one workgroup): symmetrise M and reduce it to tridiagonal form
@@ -715,6 +763,7 @@ k_rr_tridiag(const int* __restrict__ info, double* __restrict__ M, double* __res
 constexpr int TD_NT = 256;
 constexpr int TD_WAVES = TD_NT / 64;
 constexpr int TD_GRID = 32;
+constexpr int TDL_GRID = 32;    // workgroups of the LDS-resident reduction
 // bound on the spin of one barrier wait (each spin sleeps ~128 clocks); a
 // wait that reaches it raises DEV_SYNC_TIMEOUT and the kernel runs to its end
 constexpr unsigned long long TD_SPIN_LIMIT = 1ull << 26;
@@ -1016,7 +1065,7 @@ static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, 
     if (m_max >= 128) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, bar, 2);
         // rows resident in LDS when they fit, else the two-barrier kernel
-        const size_t lds = tridiag_lds_bytes(m_max, TD_GRID);
+        const size_t lds = tridiag_lds_bytes(m_max, TDL_GRID);
         int lds_max = 0;
         if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) !=
             hipSuccess)
@@ -1026,7 +1075,7 @@ static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, 
                                 (int)lds) == hipSuccess) {
             void* args[] = {(void*)&info, (void*)&m_max, (void*)&M, (void*)&tri, (void*)&P,
                             (void*)&bar, (void*)&status};
-            const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tridiag_lds, dim3(TD_GRID),
+            const hipError_t e = hipLaunchCooperativeKernel((const void*)k_tridiag_lds, dim3(TDL_GRID),
                                                             dim3(TD_NT), args, (unsigned)lds, st);
             if (e == hipSuccess) return SC_OK;
         }
@@ -1128,7 +1177,12 @@ sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float
     if (K3 > MAXM) return sc_fail(ctx, SC_E_UNSUPPORTED, "rayleigh_ritz: basis %d > %d", K3, MAXM);
     RrScratch w(scratch, K3, k);
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_rr_inv, dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st, w.info, w.U, w.Ui);
+    if (K3 <= 512)
+        hipLaunchKernelGGL((k_rr_inv<8>), dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st, w.info,
+                           w.U, w.Ui);
+    else
+        hipLaunchKernelGGL((k_rr_inv<MAXM / 64>), dim3((unsigned)ceil_div(K3, 4)), dim3(256), 0, st,
+                           w.info, w.U, w.Ui);
     const dim3 gsq((unsigned)ceil_div(K3, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 0, w.Am, w.Ui, w.Tm);  // Tm = A U^-1
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 1, w.Ui, w.Tm, w.U);   // M = U^-T Tm
