@@ -764,6 +764,7 @@ constexpr int TD_NT = 256;
 constexpr int TD_WAVES = TD_NT / 64;
 constexpr int TD_GRID = 32;
 constexpr int TDL_GRID = 32;    // workgroups of the LDS-resident reduction
+constexpr int TDL_RG = 4;       // rows per wave whose dot products run together
 // bound on the spin of one barrier wait (each spin sleeps ~128 clocks); a
 // wait that reaches it raises DEV_SYNC_TIMEOUT and the kernel runs to its end
 constexpr unsigned long long TD_SPIN_LIMIT = 1ull << 26;
@@ -964,19 +965,39 @@ k_tridiag_lds(const int* __restrict__ info, int m_max, double* __restrict__ M,
         __syncthreads();
         double* Pb = X + (int64_t)(j & 1) * 2 * MAXM;
         double* Cb = Pb + MAXM;
-        // 1. own rows of the trailing block: P and the column j + 1 entries
+        // 1. own rows of the trailing block: P and the column j + 1 entries;
+        //    a wave takes TDL_RG of its rows at once so their reductions overlap
         const int s0 = (j + 1 - g + G - 1) / G;   // first slot with R >= j + 1
-        for (int s = s0 + wave; s * G + g < m; s += TD_WAVES) {
-            const int R = s * G + g;
-            const double* row = A + (int64_t)s * m_max + (j + 1);
-            double sacc = 0.0;
+        for (int s = s0 + wave; s * G + g < m; s += TDL_RG * TD_WAVES) {
+            double sacc[TDL_RG];
+            const double* row[TDL_RG];
+            bool ok[TDL_RG];
+#pragma unroll
+            for (int q = 0; q < TDL_RG; ++q) {
+                const int sq = s + q * TD_WAVES;
+                ok[q] = sq * G + g < m;
+                row[q] = A + (int64_t)(ok[q] ? sq : s) * m_max + (j + 1);
+                sacc[q] = 0.0;
+            }
             if (tj != 0.0) {
-                for (int c = lane; c < len; c += 64) sacc = fma(row[c], vs[c], sacc);
-                sacc = wave_sum(sacc);
+                for (int c = lane; c < len; c += 64) {
+                    const double v = vs[c];
+#pragma unroll
+                    for (int q = 0; q < TDL_RG; ++q) sacc[q] = fma(row[q][c], v, sacc[q]);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                    for (int q = 0; q < TDL_RG; ++q) sacc[q] += __shfl_xor(sacc[q], o, 64);
             }
             if (lane == 0) {
-                Pb[R] = tj * sacc;
-                Cb[R] = row[0];
+#pragma unroll
+                for (int q = 0; q < TDL_RG; ++q) {
+                    if (!ok[q]) continue;
+                    const int R = (s + q * TD_WAVES) * G + g;
+                    Pb[R] = tj * sacc[q];
+                    Cb[R] = row[q][0];
+                }
             }
         }
         grid_sync(bar, gen, status);
