@@ -26,8 +26,7 @@ constexpr int NWAVE = NT / 64;
 constexpr int MAXM = 1024;
 
 __device__ inline double block_sum(double v, double* red) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    v = sc_wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
     __syncthreads();
@@ -460,9 +459,7 @@ k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
                         }
 #pragma unroll
                         for (int u = 0; u < MGS_U; ++u) {
-                            double t = part[u];
-#pragma unroll
-                            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+                            const double t = sc_wave_sum(part[u]);
                             if (lane == 0 && p0 + u < q) dots[p0 + u - c0] = t;
                         }
                     }
@@ -493,28 +490,6 @@ k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
             __syncthreads();
         }
         c0 = c1;
-    }
-}
-
-// Householder reflectors (stored in A as described for tridiagonalize)
-// applied to the columns of V: V <- H_0 H_1 ... H_{m-3} V, one wave per
-// column, the reflector dot products reduced across the wave.
-__device__ void back_transform_col(int m, const double* A, const double* tau, double* v_col,
-                                   int ldv) {
-    const int lane = threadIdx.x & 63;
-    for (int j = m - 3; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj == 0.0) continue;
-        const double* vj = A + (int64_t)j * m + j + 1;   // v_0 = 1 implicit
-        const int len = m - j - 1;
-        double part = 0.0;
-        for (int r = lane; r < len; r += 64)
-            part = fma(r == 0 ? 1.0 : vj[r], v_col[(int64_t)(j + 1 + r) * ldv], part);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-        const double sc = tj * part;
-        for (int r = lane; r < len; r += 64)
-            v_col[(int64_t)(j + 1 + r) * ldv] -= sc * (r == 0 ? 1.0 : vj[r]);
     }
 }
 
@@ -769,11 +744,7 @@ constexpr int TDL_RG = 4;       // rows per wave whose dot products run together
 // wait that reaches it raises DEV_SYNC_TIMEOUT and the kernel runs to its end
 constexpr unsigned long long TD_SPIN_LIMIT = 1ull << 26;
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ inline double wave_sum(double v) { return sc_wave_sum(v); }
 
 __device__ inline double block_sum_td(double v, double* red) {
     v = wave_sum(v);
@@ -986,9 +957,7 @@ k_tridiag_lds(const int* __restrict__ info, int m_max, double* __restrict__ M,
                     for (int q = 0; q < TDL_RG; ++q) sacc[q] = fma(row[q][c], v, sacc[q]);
                 }
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-                    for (int q = 0; q < TDL_RG; ++q) sacc[q] += __shfl_xor(sacc[q], o, 64);
+                for (int q = 0; q < TDL_RG; ++q) sacc[q] = sc_wave_sum(sacc[q]);
             }
             if (lane == 0) {
 #pragma unroll
@@ -1059,22 +1028,67 @@ __global__ void k_copy_f64(int64_t n, const double* __restrict__ a, double* __re
 }
 
 // --- step 3c: Householder back-transform of the k eigenvectors, one wave each
-__global__ void __launch_bounds__(256)
+// BK_W columns per workgroup, one per wave, held in registers (lane l owns
+// entries l, l + 64, ...).  The reflectors are staged in LDS BK_NB at a time
+// by the whole workgroup, so each is read from global memory once per
+// workgroup, in bulk, instead of once per column and step.
+constexpr int BK_NB = 8;
+constexpr int BK_W = 16;
+template <int SL>
+__global__ void __launch_bounds__(BK_W * 64)
 k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
           const double* __restrict__ dtau, double* __restrict__ Q) {
-    // the wave's column stays in LDS while the reflectors are applied (their
-    // loads are then never queued behind stores to the column)
-    __shared__ double col[4][MAXM];
+    __shared__ double refl[BK_NB][MAXM];
+    __shared__ double tl[BK_NB];
     const int m = info[0];
+    if (m == 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + wave;
-    if (m == 0 || i >= k) return;
-    double* cv = col[wave];
-    for (int r = lane; r < m; r += 64) cv[r] = Q[(int64_t)r * k + i];
-    __builtin_amdgcn_wave_barrier();
-    back_transform_col(m, M, dtau + 2 * MAXM, cv, 1);
-    __builtin_amdgcn_wave_barrier();
-    for (int r = lane; r < m; r += 64) Q[(int64_t)r * k + i] = cv[r];
+    const int i = blockIdx.x * BK_W + wave;
+    const bool live = i < k;
+    const double* tau = dtau + 2 * MAXM;
+    double x[SL];
+#pragma unroll
+    for (int t = 0; t < SL; ++t) {
+        const int e = lane + 64 * t;
+        x[t] = (live && e < m) ? Q[(int64_t)e * k + i] : 0.0;
+    }
+    for (int jb = m - 3; jb >= 0; jb -= BK_NB) {
+        __syncthreads();
+        for (int q = 0; q < BK_NB; ++q) {
+            const int j = jb - q;
+            if (j < 0) break;
+            const int len = m - j - 1;
+            for (int r = threadIdx.x; r < len; r += BK_W * 64)
+                refl[q][r] = r == 0 ? 1.0 : M[(int64_t)j * m + j + 1 + r];
+            if (threadIdx.x == 0) tl[q] = tau[j];
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int q = 0; q < BK_NB; ++q) {
+            const int j = jb - q;
+            if (j < 0) break;
+            const double tj = tl[q];
+            if (tj == 0.0) continue;
+            double part = 0.0;
+#pragma unroll
+            for (int t = 0; t < SL; ++t) {
+                const int e = lane + 64 * t;
+                if (e > j && e < m) part = fma(refl[q][e - j - 1], x[t], part);
+            }
+            const double sc = tj * sc_wave_sum(part);
+#pragma unroll
+            for (int t = 0; t < SL; ++t) {
+                const int e = lane + 64 * t;
+                if (e > j && e < m) x[t] -= sc * refl[q][e - j - 1];
+            }
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int t = 0; t < SL; ++t) {
+        const int e = lane + 64 * t;
+        if (e < m) Q[(int64_t)e * k + i] = x[t];
+    }
 }
 
 // reduction to tridiagonal form: a cooperative kernel when the matrix is
@@ -1114,15 +1128,20 @@ static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, 
 
 // tridiagonalised M (in `M`, reflectors inside) + tri block -> k smallest
 // eigenpairs (w, and V = m x k eigenvectors of M)
-static void eig_pipeline(hipStream_t st, int k, const int* info, const double* M, double* tri,
-                         double* w, double* V, double* lu) {
+static void eig_pipeline(hipStream_t st, int m_max, int k, const int* info, const double* M,
+                         double* tri, double* w, double* V, double* lu) {
     hipLaunchKernelGGL(k_tri_params, dim3(1), dim3(NT), 0, st, info, tri);
     hipLaunchKernelGGL(k_tri_bisect, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, tri, w);
     hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, IV_T)), dim3(IV_T), 0, st, k, info,
                        tri, w, V, k, lu);
     // the inverse-iteration LU arrays (5 MAXM k doubles) are free again: cluster scratch
     hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k, lu);
-    hipLaunchKernelGGL(k_rr_back, dim3((unsigned)ceil_div(k, 4)), dim3(256), 0, st, k, info, M, tri, V);
+    if (m_max <= 512)
+        hipLaunchKernelGGL((k_rr_back<8>), dim3((unsigned)ceil_div(k, BK_W)), dim3(BK_W * 64), 0, st, k,
+                           info, M, tri, V);
+    else
+        hipLaunchKernelGGL((k_rr_back<MAXM / 64>), dim3((unsigned)ceil_div(k, BK_W)), dim3(BK_W * 64),
+                           0, st, k, info, M, tri, V);
 }
 
 // --- step 5: scatter C_act (m x k) to the rows of the active columns (the
@@ -1208,7 +1227,7 @@ sc_status launch_rr_solve(sc_ctx* ctx, int K3, int kp, int k, double* C64, float
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 0, w.Am, w.Ui, w.Tm);  // Tm = A U^-1
     hipLaunchKernelGGL(k_gemm64, gsq, dim3(256), 0, st, w.info, 0, 1, w.Ui, w.Tm, w.U);   // M = U^-T Tm
     SC_TRY(tridiagonalize_launch(ctx, K3, w.info, w.U, w.dtau, w.Tm, w.bar, status));   // Tm is free here
-    eig_pipeline(st, k, w.info, w.U, w.dtau, theta, w.Q, w.ews);
+    eig_pipeline(st, K3, k, w.info, w.U, w.dtau, theta, w.Q, w.ews);
     const dim3 gk((unsigned)ceil_div(k, 64), (unsigned)ceil_div(K3, 64));
     hipLaunchKernelGGL(k_gemm64, gk, dim3(256), 0, st, w.info, k, 0, w.Ui, w.Q, w.Cq);    // C = U^-1 Q
     hipLaunchKernelGGL(k_rr_zero, dim3((unsigned)ceil_div((int64_t)K3 * kp, 256)), dim3(256), 0, st,
@@ -1243,7 +1262,7 @@ sc_status launch_symeig(sc_ctx* ctx, int m, int k, const double* A, double* w, d
                        (int64_t)m * m, A, M);
     hipLaunchKernelGGL(k_set_info, dim3(1), dim3(64), 0, st, info, m);
     SC_TRY(tridiagonalize_launch(ctx, m, info, M, tri, lu, bar, flags));
-    eig_pipeline(st, k, info, M, tri, w, V, lu);
+    eig_pipeline(st, m, k, info, M, tri, w, V, lu);
     SC_CHECK_LAUNCH(ctx);
     int h = 0;
     SC_CHECK_HIP(ctx, hipMemcpyAsync(&h, flags, sizeof h, hipMemcpyDeviceToHost, st));

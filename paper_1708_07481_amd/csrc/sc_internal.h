@@ -96,6 +96,35 @@ static inline int ceil_log2_u64(uint64_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// Wave-wide FP64 sum through DPP moves (quad permutes, row mirrors, row
+// broadcasts), which stay in the vector ALU instead of going through the LDS
+// crossbar like a shuffle does.  The total ends in lane 63 and is returned to
+// every lane.  All 64 lanes must be active.  The order of the additions is
+// fixed (lanes pairwise within quads, then half-rows, rows, and the four rows
+// in sequence), so the result is deterministic.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ inline double sc_dpp_move(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ inline double sc_wave_sum(double v) {
+    v += sc_dpp_move<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    v += sc_dpp_move<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    v += sc_dpp_move<0x141, 0xF>(v);   // row_half_mirror
+    v += sc_dpp_move<0x140, 0xF>(v);   // row_mirror
+    v += sc_dpp_move<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += sc_dpp_move<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((int)u, 63);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(u >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// ---------------------------------------------------------------------------
 // Device-wide primitives (scan.hip, radix.hip)
 // ---------------------------------------------------------------------------
 // Exclusive (inclusive = 0) or inclusive scan of n uint64 values, in place
