@@ -669,27 +669,42 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
     lb[e] = l;
 }
 
-// centre displacements: delta[r][j] = ||c_new - c_old|| (inflated), and per
-// restart the largest (with its index) and second largest displacement
+// centre displacements: delta[r][j] = ||c_new - c_old|| (inflated); a centre
+// whose member list did not change kept its coordinates, so its displacement
+// is 0.  One wave per centre, lanes along the dimensions (the order of the sum
+// does not matter: the value only moves bounds, with the bound margin).
 __global__ void __launch_bounds__(TH)
-k_delta(int K, int dim, const double* __restrict__ C, const double* __restrict__ Cold,
-        const int* __restrict__ active, double* __restrict__ delta, double* __restrict__ dinfo) {
-    const int r = blockIdx.x;
+k_delta(int K, int R, int dim, const double* __restrict__ C, const double* __restrict__ Cold,
+        const int* __restrict__ active, const int* __restrict__ dirty, double* __restrict__ delta) {
+    const int64_t rj = (int64_t)blockIdx.x * (TH / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (rj >= (int64_t)R * K || !active[rj / K]) return;
+    if (!dirty[rj]) {
+        if (lane == 0) delta[rj] = 0.0;
+        return;
+    }
+    const double* cn = C + rj * dim;
+    const double* co = Cold + rj * dim;
+    double s = 0.0;
+    for (int d = lane; d < dim; d += 64) {
+        const double t = cn[d] - co[d];
+        s = fma(t, t, s);
+    }
+    s = sc_wave_sum(s);
+    if (lane == 0) delta[rj] = sqrt(s) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+}
+
+// per restart the largest displacement (with its centre) and the second
+// largest; one wave per restart
+__global__ void __launch_bounds__(64)
+k_delta_max(int K, const int* __restrict__ active, const double* __restrict__ delta,
+            double* __restrict__ dinfo) {
+    const int r = blockIdx.x, lane = threadIdx.x;
     if (!active[r]) return;
-    __shared__ double smax[TH], ssec[TH];
-    __shared__ int sarg[TH];
     double m1 = 0.0, m2 = 0.0;
     int a1 = -1;
-    for (int j = threadIdx.x; j < K; j += TH) {
-        const double* cn = C + ((int64_t)r * K + j) * dim;
-        const double* co = Cold + ((int64_t)r * K + j) * dim;
-        double s = 0.0;
-        for (int d = 0; d < dim; ++d) {
-            const double t = cn[d] - co[d];
-            s = fma(t, t, s);
-        }
-        const double dj = sqrt(s) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
-        delta[(int64_t)r * K + j] = dj;
+    for (int j = lane; j < K; j += 64) {
+        const double dj = delta[(int64_t)r * K + j];
         if (dj > m1) {
             m2 = m1;
             m1 = dj;
@@ -698,20 +713,23 @@ k_delta(int K, int dim, const double* __restrict__ C, const double* __restrict__
             m2 = dj;
         }
     }
-    smax[threadIdx.x] = m1;
-    ssec[threadIdx.x] = m2;
-    sarg[threadIdx.x] = a1;
+    // combine the lanes in order (lane 0 first), as a serial scan would
+    __shared__ double sm1[64], sm2[64];
+    __shared__ int sa[64];
+    sm1[lane] = m1;
+    sm2[lane] = m2;
+    sa[lane] = a1;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         double b1 = 0.0, b2 = 0.0;
         int arg = -1;
-        for (int t = 0; t < TH; ++t) {
-            if (smax[t] > b1) {
-                b2 = fmax(b1, ssec[t]);
-                b1 = smax[t];
-                arg = sarg[t];
+        for (int t = 0; t < 64; ++t) {
+            if (sm1[t] > b1) {
+                b2 = fmax(b1, sm2[t]);
+                b1 = sm1[t];
+                arg = sa[t];
             } else {
-                b2 = fmax(b2, smax[t]);
+                b2 = fmax(b2, sm1[t]);
             }
         }
         dinfo[3 * r + 0] = b1;
@@ -1082,13 +1100,17 @@ k_final_d2(int64_t n, int dim, int K, int Kpad, int R, const double* __restrict_
 }
 
 // integer inertia per restart: block sums (exact) then one atomic per block
+// of INERTIA_PPT * TH points
+constexpr int INERTIA_PPT = 16;
 __global__ void __launch_bounds__(TH)
 k_inertia(int64_t n, const double* __restrict__ D2, int shift, unsigned long long* __restrict__ q) {
     __shared__ unsigned long long sm[TH];
     const int r = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * TH + threadIdx.x;
     unsigned long long v = 0;
-    if (i < n) v = (unsigned long long)floor(ldexp(D2[(int64_t)r * n + i], shift));
+    for (int u = 0; u < INERTIA_PPT; ++u) {
+        const int64_t i = ((int64_t)blockIdx.x * INERTIA_PPT + u) * TH + threadIdx.x;
+        if (i < n) v += (unsigned long long)floor(ldexp(D2[(int64_t)r * n + i], shift));
+    }
     sm[threadIdx.x] = v;
     __syncthreads();
     for (int o = TH / 2; o > 0; o >>= 1) {
@@ -1408,14 +1430,13 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             hipLaunchKernelGGL(k_centroid_total, gcent, dim3(TH), 0, st, dim, K, R, w.seg, w.active,
                                w.dirty, w.nblk, w.boff, w.bsum, w.C);
         }
+        hipLaunchKernelGGL(k_delta, dim3((unsigned)ceil_div((int64_t)R * K, TH / 64)), dim3(TH), 0, st, K,
+                           R, dim, w.C, w.Cold, w.active, w.dirty, w.delta);
+        hipLaunchKernelGGL(k_delta_max, dim3(R), dim3(64), 0, st, K, w.active, w.delta, w.dinfo);
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
                            R * K);
-        hipLaunchKernelGGL(k_delta, dim3(R), dim3(TH), 0, st, K, dim, w.C, w.Cold, w.active, w.delta,
-                           w.dinfo);
         hipLaunchKernelGGL(k_transpose_centroids, gcentp, dim3(TH), 0, st, R, K, Kpad, dim, w.C,
                            w.Ct);
-        hipLaunchKernelGGL(k_half_sep, dim3((unsigned)K, (unsigned)R), dim3(TH), 0, st, K, Kpad,
-                           dim, w.Ct, w.active, w.hsv, w.hsi);
         SC_CHECK_LAUNCH(ctx);
         // points whose assignment may change, then their scans
         hipLaunchKernelGGL(k_zero_i32, dim3(ceil_div(R, TH)), dim3(TH), 0, st, w.cnt, R);
@@ -1436,6 +1457,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         const bool prune = opts->scan == SC_KM_SCAN_PRUNED ||
                            (opts->scan == SC_KM_SCAN_AUTO && total * K >= PR_WORK_MIN);
         if (prune) {
+            hipLaunchKernelGGL(k_half_sep, dim3((unsigned)K, (unsigned)R), dim3(TH), 0, st, K, Kpad,
+                               dim, w.Ct, w.active, w.hsv, w.hsi);
             // long lists: ordered by current label (stable: ascending point
             // within a label) into vals, pruned scans, then full scans of the
             // points those cannot settle
@@ -1484,7 +1507,8 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         hipLaunchKernelGGL((k_final_d2<16>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
                            R, w.Yt, w.Ct, w.lab, w.D2);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
-    hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH), (unsigned)R), dim3(TH), 0, st, n,
+    hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH * INERTIA_PPT), (unsigned)R), dim3(TH), 0,
+                       st, n,
                        w.D2, shift, w.q);
     SC_CHECK_LAUNCH(ctx);
     std::vector<unsigned long long> qh(R);
