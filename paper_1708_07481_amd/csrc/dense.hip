@@ -436,17 +436,19 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
 }
 
 // The same factor with the equilibrated Gram matrix resident in LDS (packed
-// upper triangle), for up to CQL_MAXM columns, same modes, pivot test and
-// outputs as k_cholqr_factor:
+// upper triangle, element (a, b) at P[ro[a] + b]), for up to CQL_MAXM columns,
+// same modes, pivot test and outputs as k_cholqr_factor:
 //   - the active columns are flagged in parallel and listed by one thread
 //     from LDS;
-//   - Cholesky column by column: every thread forms the pivot, the pivot row
-//     is scaled, the trailing triangle takes the rank-one update (one wave
-//     per row); two barriers per column;
+//   - blocked right-looking Cholesky with panels of CQL_NB rows: wave 0
+//     factors the diagonal block, one thread per column solves the panel
+//     rows (kept also in Xp), and the trailing triangle takes the rank-CQL_NB
+//     update in 4 x 4 register tiles; three barriers per panel;
 //   - R^-1 one wave per column j by a column sweep of R x = e_j: for
-//     a = j .. 0, x_a = b_a / R(a, a) (b_a broadcast from its lane), then
-//     b_l -= R(l, a) x_a on the lanes' rows l < a; no cross-lane reductions.
+//     a = j .. 0, x_a = b_a / R(a, a) (b_a broadcast from its lane, the
+//     reciprocal precomputed), then b_l -= R(l, a) x_a on the lanes' rows l < a.
 constexpr int CQL_MAXM = 176;
+constexpr int CQL_NB = 16;
 constexpr int CQL_SLOTS = (CQL_MAXM + 63) / 64;
 __device__ inline int cql_off(int a, int m) { return a * m - (a * (a - 1)) / 2; }
 
@@ -462,8 +464,9 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
                     double* __restrict__ T64, float* __restrict__ T32, int mode, int* status,
                     int* counter) {
     __shared__ double P[CQL_MAXM * (CQL_MAXM + 1) / 2];
+    __shared__ double Xp[CQL_NB][CQL_MAXM];
     __shared__ double d[CQL_MAXM], diag0[CQL_MAXM], gd[CQL_MAXM];
-    __shared__ int idx[CQL_MAXM], ok[CQL_MAXM];
+    __shared__ int idx[CQL_MAXM], ok[CQL_MAXM], ro[CQL_MAXM];
     __shared__ int m_s, fail_s, fail_at;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int NW = CQ_TH / 64;
@@ -494,6 +497,7 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
         __syncthreads();
         m = m_s;
         if (fail_s) break;
+        for (int a = tid; a < m; a += CQ_TH) ro[a] = cql_off(a, m) - a;
         for (int a = wave; a < m; a += NW) {
             const int o = cql_off(a, m) - a;
             for (int b = a + lane; b < m; b += 64) {
@@ -503,29 +507,84 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
             }
         }
         __syncthreads();
-        int fa = -1;
-        for (int j = 0; j < m; ++j) {
-            const int oj = cql_off(j, m) - j;
-            const double sj = P[oj + j];
-            if (!isfinite(sj) || !(sj > tol * diag0[j]) || !(sj > 0.0)) {
-                fa = j;                              // the same decision in every thread
-                break;
+        for (int p0 = 0; p0 < m; p0 += CQL_NB) {
+            const int nb = min(CQL_NB, m - p0);
+            const int q0 = p0 + nb;
+            const int len = m - q0;
+            // 1. diagonal block, by wave 0
+            if (wave == 0) {
+                for (int jj = 0; jj < nb; ++jj) {
+                    const int j = p0 + jj;
+                    const int oj = ro[j];
+                    const double sj = P[oj + j];
+                    if (!isfinite(sj) || !(sj > tol * diag0[j]) || !(sj > 0.0)) {
+                        if (lane == 0) fail_at = j;
+                        break;
+                    }
+                    const double rjj = sqrt(sj);
+                    if (j + 1 + lane < q0) P[oj + j + 1 + lane] /= rjj;
+                    __builtin_amdgcn_wave_barrier();
+                    if (lane == 0) P[oj + j] = rjj;
+                    const int L = q0 - j - 1;
+                    for (int e = lane; e < L * L; e += 64) {
+                        const int a = j + 1 + e / L, b = j + 1 + e % L;
+                        if (b >= a) P[ro[a] + b] -= P[oj + a] * P[oj + b];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
-            const double rjj = sqrt(sj);
-            for (int b = j + 1 + tid; b < m; b += CQ_TH) P[oj + b] /= rjj;
             __syncthreads();
-            if (tid == 0) P[oj + j] = rjj;
-            for (int a = j + 1 + wave; a < m; a += NW) {
-                const int o = cql_off(a, m) - a;
-                const double xa = P[oj + a];
-                for (int b = a + lane; b < m; b += 64) P[o + b] -= xa * P[oj + b];
+            if (fail_at >= 0) break;
+            // 2. panel rows right of the block: R_pp' X = A_p,rest, one thread per column
+            for (int cc = q0 + tid; cc < m; cc += CQ_TH) {
+                double x[CQL_NB];
+#pragma unroll
+                for (int i = 0; i < CQL_NB; ++i) {
+                    if (i < nb) {
+                        const int ri = ro[p0 + i];
+                        double sv = P[ri + cc];
+                        for (int l = 0; l < i; ++l) sv -= P[ro[p0 + l] + p0 + i] * x[l];
+                        x[i] = sv / P[ri + p0 + i];
+                        P[ri + cc] = x[i];
+                        Xp[i][cc] = x[i];
+                    }
+                }
+            }
+            __syncthreads();
+            // 3. trailing upper triangle in 4 x 4 tiles
+            const int T = (len + 3) / 4;
+            for (int t = tid; t < T * T; t += CQ_TH) {
+                const int ta = t / T, tb = t % T;
+                if (tb < ta) continue;
+                const int a0 = q0 + 4 * ta, b0 = q0 + 4 * tb;
+                double acc[4][4] = {};
+                for (int i = 0; i < nb; ++i) {
+                    double xa[4], xb[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        xa[r] = a0 + r < m ? Xp[i][a0 + r] : 0.0;
+                        xb[r] = b0 + r < m ? Xp[i][b0 + r] : 0.0;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[r][q] = fma(xa[r], xb[q], acc[r][q]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int aa = a0 + r;
+                    if (aa >= m) break;
+                    const int o = ro[aa];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int bb = b0 + q;
+                        if (bb < m && bb >= aa) P[o + bb] -= acc[r][q];
+                    }
+                }
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            fail_at = fa;
-            fail_s = fa >= 0;
-        }
+        if (tid == 0) fail_s = fail_at >= 0;
         __syncthreads();
         if (!fail_s || mode != CQ_DROP_DEPENDENT) break;
         // the failing column is (numerically) in the span of the earlier ones
@@ -551,8 +610,15 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
         }
         return;
     }
+    for (int a = tid; a < m; a += CQ_TH) gd[a] = 1.0 / P[ro[a] + a];     // reciprocals of R(a, a)
     __syncthreads();
     // R^-1 by column sweeps; lane l holds rows l, l + 64, ...
+    int rol[CQL_SLOTS];
+#pragma unroll
+    for (int t = 0; t < CQL_SLOTS; ++t) {
+        const int l = lane + 64 * t;
+        rol[t] = l < m ? ro[l] : 0;
+    }
     for (int j = wave; j < m; j += NW) {
         double x[CQL_SLOTS];
 #pragma unroll
@@ -563,12 +629,12 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
 #pragma unroll
             for (int t = 1; t < CQL_SLOTS; ++t)
                 if (t == ta) xa_src = x[t];
-            const double xa = cql_readlane(xa_src, la) / P[cql_off(a, m)];
+            const double xa = cql_readlane(xa_src, la) * gd[a];
 #pragma unroll
             for (int t = 0; t < CQL_SLOTS; ++t) {
                 const int l = lane + 64 * t;
                 if (l == a) x[t] = xa;
-                else if (l < a) x[t] -= P[cql_off(l, m) - l + a] * xa;
+                else if (l < a) x[t] -= P[rol[t] + a] * xa;
             }
         }
 #pragma unroll
