@@ -187,7 +187,7 @@ template <int WB>
 __global__ void __launch_bounds__(TH)
 k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
           const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ tsum,
-          int shift, int32_t* __restrict__ lab, double* __restrict__ sec) {
+          int shift, int32_t* __restrict__ lab, float* __restrict__ secf) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i0 < n;
     const int64_t i = live ? i0 : n - 1;
@@ -224,9 +224,10 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
                 acc[q] = fma(diff, diff, acc[q]);
             }
         }
-        // D2 = least distance so far (the seeding weights); lab / sec = its
-        // centre and the second least distance, which after the last centre
-        // are the first assignment (ties to the lowest centre)
+        // D2 = least distance so far (the seeding weights, stored only when it
+        // changes); lab = its centre; secf = a lower bound of the second least
+        // distance (rounded down to FP32).  After the last centre they give the
+        // first assignment (ties to the lowest centre) and its Hamerly bounds.
 #pragma unroll
         for (int q = 0; q < WB; ++q) {
             if (r0 + q < R) {
@@ -236,19 +237,20 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
                 if (live) {
                     if (j == 0) {
                         v = a;
-                        sec[e] = INFINITY;
+                        secf[e] = INFINITY;
                         lab[e] = 0;
+                        D2[e] = v;
                     } else {
                         v = D2[e];
                         if (a < v) {
-                            sec[e] = v;
+                            secf[e] = __double2float_rd(v);
                             v = a;
                             lab[e] = j;
-                        } else if (a < sec[e]) {
-                            sec[e] = a;
+                            D2[e] = v;
+                        } else if (a < (double)secf[e]) {
+                            secf[e] = __double2float_rd(a);
                         }
                     }
-                    D2[e] = v;
                 }
                 // the tile's weight sum
                 uint64_t ws = live ? (uint64_t)floor(ldexp(v, shift)) : 0;
@@ -261,13 +263,13 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
 }
 
 // first assignment from the seeding's distances: Hamerly bounds from the
-// least (D2) and second least (sec, stored in lb) distance
+// least distance (D2) and the lower bound of the second least (secf)
 __global__ void k_first_bounds(int64_t nr, const double* __restrict__ D2, double* __restrict__ ub,
-                               double* __restrict__ lb) {
+                               const float* __restrict__ secf, double* __restrict__ lb) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nr) return;
     ub[e] = sqrt(D2[e]) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
-    const double s = lb[e];
+    const double s = secf[e];
     lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
 }
 
@@ -1183,6 +1185,7 @@ struct KmWs {
     int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
     int64_t* seg;
     double *bsum, *ccur, *hsv;
+    float* secf;
     uint16_t* hsi;
     int64_t max_blocks;
     int Rpad;
@@ -1228,6 +1231,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.Rpad = (R + RB - 1) / RB * RB;
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
     w.hsv = c.take<double>((size_t)R * K * K);
+    w.secf = c.take<float>((size_t)nr);
     w.hsi = c.take<uint16_t>((size_t)R * K * K);
     w.m2 = c.take<unsigned long long>(1);
     w.q = c.take<unsigned long long>(R);
@@ -1261,7 +1265,7 @@ void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
 template <int WB>
 void seed_d2_go(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
     hipLaunchKernelGGL((k_seed_d2<WB>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, dim, R,
-                       Rpad, j, w.Yt, w.ccur, w.D2, w.tsum, shift, w.lab, w.lb);
+                       Rpad, j, w.Yt, w.ccur, w.D2, w.tsum, shift, w.lab, w.secf);
 }
 
 void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
@@ -1390,7 +1394,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         SC_CHECK_LAUNCH(ctx);
         assign(ctx, n, dim, K, R, w, 1, w.pts, w.cnt, n);
     } else {
-        hipLaunchKernelGGL(k_first_bounds, gnr, dim3(TH), 0, st, nr, w.D2, w.ub, w.lb);
+        hipLaunchKernelGGL(k_first_bounds, gnr, dim3(TH), 0, st, nr, w.D2, w.ub, w.secf, w.lb);
     }
     hipLaunchKernelGGL(k_fill_i32, dim3(ceil_div((int64_t)R * K, TH)), dim3(TH), 0, st, w.dirty,
                        R * K, 1);
