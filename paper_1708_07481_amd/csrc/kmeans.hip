@@ -32,7 +32,35 @@ constexpr double BOUND_TINY = 1e-150;    // absolute slack for zero distances
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Row norms and the normalised rows, Y (row-major) and Yt (dimension-major).
+// The normalised rows y_i = x_i / ||x_i|| are read in two layouts: row-major
+// (Lloyd scans, centroid sums, seeding picks) and dimension-major (the
+// point-per-lane seeding and final distances).  FP64 input: both are
+// materialised as FP64.  FP32 input: the row-major source is the caller's X
+// itself and the dimension-major copy is a transposed FP32 X (half the bytes of
+// every pass), with the divisor b_i of each row (its norm, or 1.0 for a zero
+// row or without normalisation) and r_i = RN(1/b_i); the kernels redo the
+// quotient in registers, with the same bits as the IEEE division:
+// q0 = x r is within 1.5 ulp of x/b, one fma residual correction brings it
+// within 1 ulp, and a second one rounds correctly (Markstein's theorem: with r
+// within half an ulp of 1/b and q within one ulp of x/b, the residual
+// x - b q is exact and RN(q + (x - b q) r) = RN(x/b)).  Five FP64 operations
+// instead of a division's eleven.  A -0.0 may come out as +0.0, which no
+// squared difference can tell apart.
+struct YDiv {
+    double b, r;
+};
+__device__ __forceinline__ double ycoord(double v, YDiv) { return v; }
+__device__ __forceinline__ double ycoord(float v, YDiv dv) {
+    const double x = v;
+    const double q0 = x * dv.r;
+    const double q1 = fma(fma(-q0, dv.b, x), dv.r, q0);
+    return fma(fma(-q1, dv.b, x), dv.r, q1);
+}
+template <class TT>
+__device__ __forceinline__ YDiv ydiv_of(const YDiv* dv, int64_t i) {
+    return sizeof(TT) == 4 ? dv[i] : YDiv{1.0, 1.0};
+}
+
 // A workgroup takes TH rows; the rows are staged through LDS in chunks of RN_DC
 // dimensions (coalesced loads and stores), while each thread accumulates its
 // own row's sum of squares in dimension order.  The chunks are read twice:
@@ -41,8 +69,9 @@ constexpr int RN_DC = 16;
 template <class TX>
 __global__ void __launch_bounds__(TH)
 k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normalize,
-          double* __restrict__ Y, double* __restrict__ Yt, unsigned long long* m2bits,
-          int* status) {
+          double* __restrict__ Y, TX* __restrict__ Yt, YDiv* __restrict__ dv,
+          unsigned long long* m2bits, int* status) {
+    constexpr bool RAW = sizeof(TX) == 4;    // the dimension-major copy holds x, not y
     __shared__ double xs[RN_DC][TH + 1];
     const int64_t row0 = (int64_t)blockIdx.x * TH;
     const int t = threadIdx.x;
@@ -51,6 +80,10 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
     bool bad = false;
     for (int pass = 0; pass < 2; ++pass) {
         const double nrm = sqrt(s);
+        if (RAW && pass == 1 && live) {
+            const double b = (normalize && nrm > 0.0) ? nrm : 1.0;
+            dv[row0 + t] = YDiv{b, 1.0 / b};
+        }
         double s2 = 0.0;
         for (int d0 = 0; d0 < dim; d0 += RN_DC) {
             const int nd = min(RN_DC, dim - d0);
@@ -67,6 +100,13 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
                     s = fma(xd, xd, s);
                 }
             } else {
+                if (RAW) {
+                    for (int q = t; q < TH * RN_DC; q += TH) { // dimension-major: rows fastest
+                        const int dd = q / TH, r = q % TH;
+                        if (dd < nd && row0 + r < n) Yt[(int64_t)(d0 + dd) * n + row0 + r] = (TX)xs[dd][r];
+                    }
+                    __syncthreads();
+                }
                 for (int dd = 0; dd < nd; ++dd) {
                     double y = xs[dd][t];
                     if (normalize) y = nrm > 0.0 ? y / nrm : 0.0;
@@ -74,14 +114,16 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
                     s2 = fma(y, y, s2);
                 }
                 __syncthreads();
-                for (int q = t; q < TH * RN_DC; q += TH) {     // dimension-major: rows fastest
-                    const int dd = q / TH, r = q % TH;
-                    if (dd < nd && row0 + r < n) Yt[(int64_t)(d0 + dd) * n + row0 + r] = xs[dd][r];
-                }
-                for (int q = t; q < TH * RN_DC; q += TH) {     // row-major: dimensions fastest
-                    const int r = q / RN_DC, dd = q % RN_DC;
-                    if (dd < nd && row0 + r < n) Y[(row0 + r) * dim + d0 + dd] = xs[dd][r];
-                }
+                if (!RAW)
+                    for (int q = t; q < TH * RN_DC; q += TH) { // dimension-major: rows fastest
+                        const int dd = q / TH, r = q % TH;
+                        if (dd < nd && row0 + r < n) Yt[(int64_t)(d0 + dd) * n + row0 + r] = (TX)xs[dd][r];
+                    }
+                if (!RAW)
+                    for (int q = t; q < TH * RN_DC; q += TH) { // row-major: dimensions fastest
+                        const int r = q / RN_DC, dd = q % RN_DC;
+                        if (dd < nd && row0 + r < n) Y[(row0 + r) * dim + d0 + dd] = xs[dd][r];
+                    }
             }
             __syncthreads();
         }
@@ -108,9 +150,10 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
 // Grid: R blocks of PICK_NT threads.
 constexpr int SEED_TILE = 64;
 constexpr int PICK_NT = 1024;
+template <class TT>
 __global__ void __launch_bounds__(PICK_NT)
-k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict__ Y,
-            const uint64_t* __restrict__ draws, const uint64_t* __restrict__ tsum,
+k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y, int64_t ldy,
+            const YDiv* __restrict__ dv, const uint64_t* __restrict__ draws, const uint64_t* __restrict__ tsum,
             const double* __restrict__ D2, int shift, double* __restrict__ C,
             double* __restrict__ ccur) {
     __shared__ uint64_t part[PICK_NT];
@@ -170,12 +213,14 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict
     __syncthreads();
     const int64_t pk = pick;
     double* c = C + ((int64_t)r * K + j) * dim;
+    const YDiv dp = ydiv_of<TT>(dv, pk);
     for (int d = tid; d < dim; d += PICK_NT) {
-        const double v = Y[pk * dim + d];
+        const double v = ycoord(Y[pk * ldy + d], dp);
         c[d] = v;
         ccur[(int64_t)d * Rpad + r] = v;      // this round's centres, dimension-major
     }
 }
+
 
 // For every point and every restart: D2 <- dist(y_i, c_j) (j == 0) or
 // min(D2, dist(y_i, c_j)); then the integer weights.  One pass over Y serves
@@ -183,14 +228,16 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const double* __restrict
 constexpr int RB = 16;
 // WB restarts per pass over the points (WB <= RB; the launch picks the
 // smallest width covering the restarts, so no accumulator is wasted)
-template <int WB>
+template <int WB, class TT>
 __global__ void __launch_bounds__(TH)
-k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__ Yt,
-          const double* __restrict__ ccur, double* __restrict__ D2, uint64_t* __restrict__ tsum,
-          int shift, int32_t* __restrict__ lab, float* __restrict__ secf) {
+k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const TT* __restrict__ Yt,
+          const YDiv* __restrict__ dv, const double* __restrict__ ccur, double* __restrict__ D2,
+          uint64_t* __restrict__ tsum, int shift, int32_t* __restrict__ lab,
+          float* __restrict__ secf) {
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i0 < n;
     const int64_t i = live ? i0 : n - 1;
+    const YDiv dvi = ydiv_of<TT>(dv, i);
     const int64_t ntiles = (n + SEED_TILE - 1) / SEED_TILE;
     const int64_t tile = i0 / SEED_TILE;    // a wave is one tile
     for (int r0 = 0; r0 < R; r0 += WB) {
@@ -202,21 +249,22 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const double* __restrict__
         constexpr int DU = 8;                 // coordinates loaded ahead of their use
         int d = 0;
         for (; d + DU <= dim; d += DU) {
-            double y[DU];
+            TT y[DU];
 #pragma unroll
             for (int u = 0; u < DU; ++u) y[u] = Yt[(int64_t)(d + u) * n + i];
 #pragma unroll
             for (int u = 0; u < DU; ++u) {
                 const double* cd = ccur + (int64_t)(d + u) * Rpad + r0;   // wave-uniform, contiguous
+                const double yu = ycoord(y[u], dvi);
 #pragma unroll
                 for (int q = 0; q < WB; ++q) {
-                    const double diff = y[u] - cd[q];
+                    const double diff = yu - cd[q];
                     acc[q] = fma(diff, diff, acc[q]);
                 }
             }
         }
         for (; d < dim; ++d) {
-            const double y = Yt[(int64_t)d * n + i];
+            const double y = ycoord(Yt[(int64_t)d * n + i], dvi);
             const double* cd = ccur + (int64_t)d * Rpad + r0;
 #pragma unroll
             for (int q = 0; q < WB; ++q) {
@@ -298,16 +346,17 @@ __global__ void k_fill_lists(int64_t n, int R, uint32_t* __restrict__ pts, int* 
 // of JB centres per pass, with the centre coordinates read as wave-uniform
 // (scalar) loads from the transposed centroid table.  Every distance is the
 // full fma chain over the dimensions in order.
-template <int JB>
+template <int JB, class TT>
 __global__ void __launch_bounds__(TH)
-k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
-              const double* __restrict__ Ct, const uint32_t* __restrict__ pts,
+k_assign_list(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, int64_t ldy,
+              const YDiv* __restrict__ dv, const double* __restrict__ Ct, const uint32_t* __restrict__ pts,
               const int* __restrict__ cnt, const int* __restrict__ active,
               int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
               int* __restrict__ changed, int* __restrict__ dirty, int first) {
     constexpr int DC = 32;
     __shared__ double ys[DC][65];   // padded row: fewer LDS bank conflicts on the transposing store
     __shared__ uint32_t pid[64];
+    __shared__ YDiv pdv[64];
     __shared__ double wbest[4][64], wsec[4][64];
     __shared__ int wj[4][64];
     const int r = blockIdx.y;
@@ -318,7 +367,11 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
     const int np = min(64, c - q0);
     const int lane = threadIdx.x & 63;
     const int wave = uniform(threadIdx.x >> 6);
-    if (threadIdx.x < 64) pid[threadIdx.x] = pts[(int64_t)r * n + q0 + min((int)threadIdx.x, np - 1)];
+    if (threadIdx.x < 64) {
+        const uint32_t i = pts[(int64_t)r * n + q0 + min((int)threadIdx.x, np - 1)];
+        pid[threadIdx.x] = i;
+        pdv[threadIdx.x] = ydiv_of<TT>(dv, i);
+    }
     double best = INFINITY, second = INFINITY;
     int bj = K;
     const int passes = Kpad / (4 * JB);
@@ -332,7 +385,7 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
             __syncthreads();
             for (int q = threadIdx.x; q < 64 * DC; q += TH) {
                 const int p = q / DC, dd = q % DC;
-                ys[dd][p] = d0 + dd < dim ? Y[(int64_t)pid[p] * dim + d0 + dd] : 0.0;
+                ys[dd][p] = d0 + dd < dim ? ycoord(Y[(int64_t)pid[p] * ldy + d0 + dd], pdv[p]) : 0.0;
             }
             __syncthreads();
             if (cb < K) {
@@ -405,7 +458,9 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
     }
 }
 
-constexpr int PR_DC = 8;
+constexpr int PR_DC = 8;                // dimensions per staged chunk: 64 B of a row
+template <class TT>
+constexpr int pr_dc() { return PR_DC * 8 / (int)sizeof(TT); }
 constexpr int PR_KMAX = 1024;
 constexpr int PR_KMAX_HS = PR_KMAX;
 constexpr int PR_WIDE = 16;
@@ -466,35 +521,38 @@ k_half_sep(int K, int Kpad, int dim, const double* __restrict__ Ct, const int* _
 // (lowest index on ties) equals a full scan's.  The new lower bound covers the
 // centres nobody scanned by the triangle inequality,
 // ||y - c_j|| >= 2 h(a, j) - ||y - c_a||.
-__device__ inline void pr_load(double (&v)[PR_DC], const double* __restrict__ Y,
+template <class TT, int DC>
+__device__ inline void pr_load(TT (&v)[DC], const TT* __restrict__ Y, int64_t ldy,
                                const uint32_t* pidw, int dim, int d0, int lane) {
 #pragma unroll
-    for (int t = 0; t < PR_DC; ++t) {
+    for (int t = 0; t < DC; ++t) {
         const int q = t * 64 + lane;
-        const int p = q / PR_DC, dd = q % PR_DC;
-        v[t] = d0 + dd < dim ? Y[(int64_t)pidw[p] * dim + d0 + dd] : 0.0;
+        const int p = q / DC, dd = q % DC;
+        v[t] = d0 + dd < dim ? Y[(int64_t)pidw[p] * ldy + d0 + dd] : (TT)0;
     }
 }
 
-__device__ inline void pr_store(double (*ys)[65], const double (&v)[PR_DC], int lane) {
+template <class TT, int DC>
+__device__ inline void pr_store(TT (*ys)[65], const TT (&v)[DC], int lane) {
 #pragma unroll
-    for (int t = 0; t < PR_DC; ++t) {
+    for (int t = 0; t < DC; ++t) {
         const int q = t * 64 + lane;
-        ys[q % PR_DC][q / PR_DC] = v[t];
+        ys[q % DC][q / DC] = v[t];
     }
 }
 
-template <int JB>
+template <int JB, class TT>
 __global__ void __launch_bounds__(TH)
-k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ Y,
-                const double* __restrict__ Ct, const double* __restrict__ hsv,
+k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, int64_t ldy,
+                const YDiv* __restrict__ dv, const double* __restrict__ Ct, const double* __restrict__ hsv,
                 const uint16_t* __restrict__ hsi, const uint32_t* __restrict__ pts,
                 const int* __restrict__ cnt, const int* __restrict__ active,
                 int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
                 int* __restrict__ changed, int* __restrict__ dirty, uint32_t* __restrict__ fl,
                 int* __restrict__ fcnt) {
     constexpr int NW = TH / 64;
-    __shared__ double ys[NW][PR_DC][65];
+    constexpr int DC = pr_dc<TT>();
+    __shared__ TT ys[NW][DC][65];      // raw values; each lane forms its own point's y
     __shared__ uint32_t pid[NW][64];
     __shared__ uint16_t cand[NW][PR_KMAX];
     __shared__ uint32_t bits[NW][PR_KMAX / 32];
@@ -522,33 +580,35 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
     pid[wave][lane] = i;
     if (lane < nwords) bits[wave][lane] = 0u;
     const int a = lab[e];
+    const YDiv mdv = ydiv_of<TT>(dv, i);
     const double* Ctr = Ct + (int64_t)r * dim * Kpad;
     __builtin_amdgcn_wave_barrier();
     // 1. exact distance to the assigned centre
     double own = 0.0;
     {
         const double* ca = Ctr + a;
-        double v[PR_DC], cv[PR_DC];
-        pr_load(v, Y, pid[wave], dim, 0, lane);
+        TT v[DC];
+        double cv[DC];
+        pr_load(v, Y, ldy, pid[wave], dim, 0, lane);
 #pragma unroll
-        for (int dd = 0; dd < PR_DC; ++dd) cv[dd] = dd < dim ? ca[(int64_t)dd * Kpad] : 0.0;
-        for (int d0 = 0; d0 < dim; d0 += PR_DC) {
+        for (int dd = 0; dd < DC; ++dd) cv[dd] = dd < dim ? ca[(int64_t)dd * Kpad] : 0.0;
+        for (int d0 = 0; d0 < dim; d0 += DC) {
             pr_store(ys[wave], v, lane);
-            double cc[PR_DC];
+            double cc[DC];
 #pragma unroll
-            for (int dd = 0; dd < PR_DC; ++dd) cc[dd] = cv[dd];
-            if (d0 + PR_DC < dim) {
-                pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+            for (int dd = 0; dd < DC; ++dd) cc[dd] = cv[dd];
+            if (d0 + DC < dim) {
+                pr_load(v, Y, ldy, pid[wave], dim, d0 + DC, lane);
 #pragma unroll
-                for (int dd = 0; dd < PR_DC; ++dd)
-                    cv[dd] = d0 + PR_DC + dd < dim ? ca[(int64_t)(d0 + PR_DC + dd) * Kpad] : 0.0;
+                for (int dd = 0; dd < DC; ++dd)
+                    cv[dd] = d0 + DC + dd < dim ? ca[(int64_t)(d0 + DC + dd) * Kpad] : 0.0;
             }
             __builtin_amdgcn_wave_barrier();
-            const int nd = min(PR_DC, dim - d0);
+            const int nd = min(DC, dim - d0);
 #pragma unroll
-            for (int dd = 0; dd < PR_DC; ++dd) {
+            for (int dd = 0; dd < DC; ++dd) {
                 if (dd < nd) {
-                    const double diff = ys[wave][dd][lane] - cc[dd];
+                    const double diff = ycoord(ys[wave][dd][lane], mdv) - cc[dd];
                     own = fma(diff, diff, own);
                 }
             }
@@ -620,17 +680,17 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const double* __restrict__ 
         double acc[JB];
 #pragma unroll
         for (int u2 = 0; u2 < JB; ++u2) acc[u2] = 0.0;
-        double v[PR_DC];
-        pr_load(v, Y, pid[wave], dim, 0, lane);
-        for (int d0 = 0; d0 < dim; d0 += PR_DC) {
+        TT v[DC];
+        pr_load(v, Y, ldy, pid[wave], dim, 0, lane);
+        for (int d0 = 0; d0 < dim; d0 += DC) {
             pr_store(ys[wave], v, lane);
-            if (d0 + PR_DC < dim) pr_load(v, Y, pid[wave], dim, d0 + PR_DC, lane);
+            if (d0 + DC < dim) pr_load(v, Y, ldy, pid[wave], dim, d0 + DC, lane);
             __builtin_amdgcn_wave_barrier();
-            const int nd = min(PR_DC, dim - d0);
+            const int nd = min(DC, dim - d0);
 #pragma unroll
-            for (int dd = 0; dd < PR_DC; ++dd) {
+            for (int dd = 0; dd < DC; ++dd) {
                 if (dd < nd) {
-                    const double y = ys[wave][dd][lane];
+                    const double y = ycoord(ys[wave][dd][lane], mdv);
                     const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad;
 #pragma unroll
                     for (int u2 = 0; u2 < JB; ++u2) {
@@ -1017,8 +1077,10 @@ __global__ void k_block_list(int m, const int* __restrict__ nblk, const int* __r
 
 // block sums: thread (slot, d), dimensions fastest (a member row is read
 // contiguously by consecutive threads)
+template <class TT>
 __global__ void __launch_bounds__(TH)
-k_centroid_blocks(int dim, int m, const double* __restrict__ Y, const uint32_t* __restrict__ members,
+k_centroid_blocks(int dim, int m, const TT* __restrict__ Y, int64_t ldy, const YDiv* __restrict__ dv,
+                  const uint32_t* __restrict__ members,
                   const int64_t* __restrict__ seg, const int* __restrict__ boff,
                   const int* __restrict__ brj, const int* __restrict__ bidx,
                   double* __restrict__ bsum) {
@@ -1036,15 +1098,15 @@ k_centroid_blocks(int dim, int m, const double* __restrict__ Y, const uint32_t* 
     constexpr int U = 16;
     for (; p + U <= cnt; p += U) {
         uint32_t id[U];
-        double v[U];
+        TT v[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) id[q] = mem[p + q];
 #pragma unroll
-        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * dim + d];
+        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * ldy + d];
 #pragma unroll
-        for (int q = 0; q < U; ++q) s += v[q];
+        for (int q = 0; q < U; ++q) s += ycoord(v[q], ydiv_of<TT>(dv, id[q]));
     }
-    for (; p < cnt; ++p) s += Y[(int64_t)mem[p] * dim + d];
+    for (; p < cnt; ++p) s += ycoord(Y[(int64_t)mem[p] * ldy + d], ydiv_of<TT>(dv, mem[p]));
     bsum[slot * dim + d] = s;
 }
 
@@ -1069,13 +1131,14 @@ k_centroid_total(int dim, int K, int R, const int64_t* __restrict__ seg,
 // exact squared distance of every point to its assigned centre, reading the
 // transposed centroid table Ct[r][d][Kpad] (a dimension's centres share a few
 // cache lines, so the per-lane gathers by label stay in L1)
-template <int WB>
+template <int WB, class TT>
 __global__ void __launch_bounds__(TH)
-k_final_d2(int64_t n, int dim, int K, int Kpad, int R, const double* __restrict__ Yt,
-           const double* __restrict__ Ct, const int32_t* __restrict__ lab,
-           double* __restrict__ D2) {
+k_final_d2(int64_t n, int dim, int K, int Kpad, int R, const TT* __restrict__ Yt,
+           const YDiv* __restrict__ dv, const double* __restrict__ Ct,
+           const int32_t* __restrict__ lab, double* __restrict__ D2) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const YDiv dvi = ydiv_of<TT>(dv, i);
     // one pass over the point's coordinates serves up to WB restarts; lanes of
     // restarts >= R repeat restart R - 1 and are not stored (no predicates)
     for (int r0 = 0; r0 < R; r0 += WB) {
@@ -1088,7 +1151,7 @@ k_final_d2(int64_t n, int dim, int K, int Kpad, int R, const double* __restrict_
             acc[q] = 0.0;
         }
         for (int d = 0; d < dim; ++d) {
-            const double y = Yt[(int64_t)d * n + i];
+            const double y = ycoord(Yt[(int64_t)d * n + i], dvi);
 #pragma unroll
             for (int q = 0; q < WB; ++q) {
                 const double diff = y - c[q][(int64_t)d * Kpad];
@@ -1178,7 +1241,7 @@ int assign_kpad(int K) {
 }
 
 struct KmWs {
-    double *Y, *Yt, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
+    double *Y, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
     uint64_t *tsum, *lhist, *lscan_tmp;
     uint32_t *vals, *pts, *fl;
     int32_t* lab;
@@ -1187,6 +1250,11 @@ struct KmWs {
     double *bsum, *ccur, *hsv;
     float* secf;
     uint16_t* hsi;
+    void* Yt;        // dimension-major copy: FP64 y, or FP32 x with the divisors dv
+    YDiv* dv;
+    bool yt32;       // FP32 input: Ysrc is the caller's X (row stride ldy), Yt and dv as above
+    const void* Ysrc;
+    int64_t ldy;
     int64_t max_blocks;
     int Rpad;
     unsigned long long *m2, *q;
@@ -1197,6 +1265,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     const size_t cent = (size_t)R * K * dim;
     w.Y = c.take<double>((size_t)n * dim);
     w.Yt = c.take<double>((size_t)n * dim);
+    w.dv = c.take<YDiv>((size_t)n);
     w.D2 = c.take<double>(nr);
     w.C = c.take<double>(cent);
     w.Cold = c.take<double>(cent);
@@ -1257,15 +1326,38 @@ template <int JB>
 void launch_assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first,
                    const uint32_t* list, const int* lcnt, int64_t max_cnt) {
     dim3 grid((unsigned)ceil_div(max_cnt, 64), (unsigned)R);
-    hipLaunchKernelGGL((k_assign_list<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
-                       assign_kpad(K), w.Y, w.Ct, list, lcnt, w.active, w.lab, w.ub, w.lb,
-                       w.changed, w.dirty, first);
+    if (w.yt32)
+        hipLaunchKernelGGL((k_assign_list<JB, float>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                           assign_kpad(K), static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.Ct,
+                           list, lcnt, w.active, w.lab, w.ub, w.lb, w.changed, w.dirty, first);
+    else
+        hipLaunchKernelGGL((k_assign_list<JB, double>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                           assign_kpad(K), static_cast<const double*>(w.Ysrc), w.ldy, w.dv, w.Ct,
+                           list, lcnt, w.active, w.lab, w.ub, w.lb, w.changed, w.dirty, first);
 }
 
 template <int WB>
 void seed_d2_go(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
-    hipLaunchKernelGGL((k_seed_d2<WB>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, dim, R,
-                       Rpad, j, w.Yt, w.ccur, w.D2, w.tsum, shift, w.lab, w.secf);
+    if (w.yt32)
+        hipLaunchKernelGGL((k_seed_d2<WB, float>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n,
+                           dim, R, Rpad, j, static_cast<const float*>(w.Yt), w.dv, w.ccur, w.D2,
+                           w.tsum, shift, w.lab, w.secf);
+    else
+        hipLaunchKernelGGL((k_seed_d2<WB, double>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream,
+                           n, dim, R, Rpad, j, static_cast<const double*>(w.Yt), w.dv, w.ccur, w.D2,
+                           w.tsum, shift, w.lab, w.secf);
+}
+
+template <int WB>
+void final_d2_go(sc_ctx* ctx, int64_t n, int dim, int K, int Kpad, int R, const KmWs& w) {
+    if (w.yt32)
+        hipLaunchKernelGGL((k_final_d2<WB, float>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream,
+                           n, dim, K, Kpad, R, static_cast<const float*>(w.Yt), w.dv, w.Ct, w.lab,
+                           w.D2);
+    else
+        hipLaunchKernelGGL((k_final_d2<WB, double>), dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream,
+                           n, dim, K, Kpad, R, static_cast<const double*>(w.Yt), w.dv, w.Ct, w.lab,
+                           w.D2);
 }
 
 void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
@@ -1282,9 +1374,16 @@ template <int JB>
 void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
                    const uint32_t* list, int max_cnt) {
     dim3 grid((unsigned)ceil_div(max_cnt, TH), (unsigned)R);
-    hipLaunchKernelGGL((k_assign_pruned<JB>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
-                       assign_kpad(K), w.Y, w.Ct, w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb,
-                       w.changed, w.dirty, w.fl, w.fcnt);
+    if (w.yt32)
+        hipLaunchKernelGGL((k_assign_pruned<JB, float>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                           assign_kpad(K), static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.Ct,
+                           w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
+                           w.dirty, w.fl, w.fcnt);
+    else
+        hipLaunchKernelGGL((k_assign_pruned<JB, double>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
+                           assign_kpad(K), static_cast<const double*>(w.Ysrc), w.ldy, w.dv, w.Ct,
+                           w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
+                           w.dirty, w.fl, w.fcnt);
 }
 
 void assign(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w, int first,
@@ -1341,14 +1440,17 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
 
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.m2, 0, sizeof(unsigned long long), st));
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.status, 0, sizeof(int), st));
+    w.yt32 = opts->x_fp32 != 0;
+    w.Ysrc = w.yt32 ? X : static_cast<const void*>(w.Y);
+    w.ldy = w.yt32 ? ldx : dim;
     if (opts->x_fp32)
         hipLaunchKernelGGL((k_rownorm<float>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
-                           static_cast<const float*>(X), ldx, opts->normalize_rows, w.Y, w.Yt, w.m2,
-                           w.status);
+                           static_cast<const float*>(X), ldx, opts->normalize_rows, nullptr,
+                           static_cast<float*>(w.Yt), w.dv, w.m2, w.status);
     else
         hipLaunchKernelGGL((k_rownorm<double>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
-                           static_cast<const double*>(X), ldx, opts->normalize_rows, w.Y, w.Yt,
-                           w.m2, w.status);
+                           static_cast<const double*>(X), ldx, opts->normalize_rows, w.Y,
+                           static_cast<double*>(w.Yt), nullptr, w.m2, w.status);
     SC_CHECK_LAUNCH(ctx);
     char* h = static_cast<char*>(ctx->stage);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(h, w.m2, 8, hipMemcpyDeviceToHost, st));
@@ -1374,8 +1476,14 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
         hipLaunchKernelGGL(k_zero_i64, dim3(ceil_div((int64_t)w.Rpad * dim, TH)), dim3(TH), 0, st,
                            reinterpret_cast<int64_t*>(w.ccur), (int64_t)w.Rpad * dim);
         for (int j = 0; j < K; ++j) {
-            hipLaunchKernelGGL(k_seed_pick, dim3(R), dim3(PICK_NT), 0, st, n, dim, K, j, w.Rpad, w.Y,
-                               draws, w.tsum, w.D2, shift, w.C, w.ccur);
+            if (w.yt32)
+                hipLaunchKernelGGL(k_seed_pick<float>, dim3(R), dim3(PICK_NT), 0, st, n, dim, K, j,
+                                   w.Rpad, static_cast<const float*>(w.Ysrc), w.ldy, w.dv,
+                                   draws, w.tsum, w.D2, shift, w.C, w.ccur);
+            else
+                hipLaunchKernelGGL(k_seed_pick<double>, dim3(R), dim3(PICK_NT), 0, st, n, dim, K, j,
+                                   w.Rpad, static_cast<const double*>(w.Ysrc), w.ldy, w.dv,
+                                   draws, w.tsum, w.D2, shift, w.C, w.ccur);
             SC_CHECK_LAUNCH(ctx);
             // distances to centre j (also after the last one: they complete the
             // first assignment)
@@ -1428,9 +1536,15 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(TH), 0, st, m, w.nblk, w.boff);
             hipLaunchKernelGGL(k_block_list, dim3(ceil_div(m, TH)), dim3(TH), 0, st, m, w.nblk,
                                w.boff, w.brj, w.bidx);
-            hipLaunchKernelGGL(k_centroid_blocks, dim3((unsigned)ceil_div(w.max_blocks * dim, TH)),
-                               dim3(TH), 0, st, dim, m, w.Y, w.vals, w.seg, w.boff, w.brj, w.bidx,
-                               w.bsum);
+            const dim3 gblk((unsigned)ceil_div(w.max_blocks * dim, TH));
+            if (w.yt32)
+                hipLaunchKernelGGL(k_centroid_blocks<float>, gblk, dim3(TH), 0, st, dim, m,
+                                   static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.vals, w.seg,
+                                   w.boff, w.brj, w.bidx, w.bsum);
+            else
+                hipLaunchKernelGGL(k_centroid_blocks<double>, gblk, dim3(TH), 0, st, dim, m,
+                                   static_cast<const double*>(w.Ysrc), w.ldy, w.dv, w.vals, w.seg,
+                                   w.boff, w.brj, w.bidx, w.bsum);
             hipLaunchKernelGGL(k_centroid_total, gcent, dim3(TH), 0, st, dim, K, R, w.seg, w.active,
                                w.dirty, w.nblk, w.boff, w.bsum, w.C);
         }
@@ -1501,15 +1615,9 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                                              hipMemcpyHostToDevice, st));
     }
     // exact distances to the final centres, integer inertia, best restart
-    if (R <= 4)
-        hipLaunchKernelGGL((k_final_d2<4>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
-                           R, w.Yt, w.Ct, w.lab, w.D2);
-    else if (R <= 10)
-        hipLaunchKernelGGL((k_final_d2<10>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
-                           R, w.Yt, w.Ct, w.lab, w.D2);
-    else
-        hipLaunchKernelGGL((k_final_d2<16>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim, K, Kpad,
-                           R, w.Yt, w.Ct, w.lab, w.D2);
+    if (R <= 4) final_d2_go<4>(ctx, n, dim, K, Kpad, R, w);
+    else if (R <= 10) final_d2_go<10>(ctx, n, dim, K, Kpad, R, w);
+    else final_d2_go<16>(ctx, n, dim, K, Kpad, R, w);
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.q, 0, R * sizeof(unsigned long long), st));
     hipLaunchKernelGGL(k_inertia, dim3((unsigned)ceil_div(n, TH * INERTIA_PPT), (unsigned)R), dim3(TH), 0,
                        st, n,

@@ -73,6 +73,36 @@ def test_kmeans_bit_exact_lattice_ties(orc, ctx, scan):
     _same(ko, kg)
 
 
+@pytest.mark.parametrize("n,dim,K,R,seed,norm,scan", [(20000, 44, 44, 3, 11, True, "pruned"),
+                                                      (20000, 44, 44, 3, 11, True, "full"),
+                                                      (3001, 19, 19, 4, 12, False, "auto"),
+                                                      (30000, 16, 24, 2, 13, True, "pruned"),
+                                                      (5000, 7, 6, 3, 14, True, "auto")])
+def test_kmeans_bit_exact_fp32_input(orc, ctx, n, dim, K, R, seed, norm, scan):
+    """FP32 rows (the FP32 solver's eigenvector block) read through a row
+    stride wider than dim.  The kernels form y = x / ||x|| from the FP32 values
+    in registers; labels, centroids and inertia must equal the oracle's on the
+    same values widened to FP64.  Zero rows, -0.0 entries and FP32 subnormals
+    included."""
+    from paper_1708_07481_amd import api
+    rng = np.random.default_rng(seed)
+    centers = rng.standard_normal((K, dim))
+    X = (centers[rng.integers(0, K, n)] + 0.5 * rng.standard_normal((n, dim))).astype(np.float32)
+    X[::97] = 0.0
+    X[1::89, ::2] = -0.0
+    X[2::113] = np.float32(1e-44) * np.sign(X[2::113])
+    X[3::131, 0] = np.float32(3e-39)
+    big = np.zeros((n, dim + 5), np.float32)
+    big[:, :dim] = X
+    Xd = to_dev(big)[:, :dim]
+    assert Xd.stride(0) == dim + 5
+    draws = kmeans_draws(R, K, seed)
+    ko = orc.kmeans(X.astype(np.float64), K, draws, max_iter=100, normalize=norm)
+    kg = api.kmeans_assign(ctx, Xd, K, to_dev(draws.view(np.int64)), max_iter=100,
+                           normalize=norm, scan=scan)
+    _same(ko, kg)
+
+
 def test_kmeans_edge_cases(orc, ctx):
     from paper_1708_07481_amd import api
     # zero rows, duplicate points, K == n, max_iter = 0, no normalisation
