@@ -54,7 +54,7 @@ _dbl = C.c_double
 
 class LobpcgOpts(C.Structure):
     _fields_ = [("k", _int), ("maxit", _int), ("tol", _dbl), ("lock_tol", _dbl),
-                ("chol_tol", _dbl)]
+                ("chol_tol", _dbl), ("op_norm", _dbl)]
 
 
 class LobpcgInfo(C.Structure):
@@ -67,8 +67,10 @@ def _declare(L):
     L.orc_graph_build.argtypes = [_i64, _i64, _p, _p, _p, _int, _p, _p, _p, _p, _p, _p]
     L.orc_laplacian.restype = _int
     L.orc_laplacian.argtypes = [_i64, _p, _p, _p, _p, _p, _p]
+    L.orc_laplacian_combinatorial.restype = _int
+    L.orc_laplacian_combinatorial.argtypes = [_i64, _p, _p, _p, _p]
     L.orc_spmm_rowmajor.restype = None
-    L.orc_spmm_rowmajor.argtypes = [_i64, _p, _p, _p, _int, _p, _i64, _p, _i64]
+    L.orc_spmm_rowmajor.argtypes = [_i64, _p, _p, _p, _p, _int, _p, _i64, _p, _i64]
     L.orc_gram.restype = None
     L.orc_gram.argtypes = [_i64, _int, _p, _int, _p, _p, _int]
     L.orc_cholesky.restype = _int
@@ -76,7 +78,7 @@ def _declare(L):
     L.orc_symeig.restype = _int
     L.orc_symeig.argtypes = [_int, _p, _p, _p]
     L.orc_lobpcg.restype = _int
-    L.orc_lobpcg.argtypes = [_i64, _p, _p, _p, C.POINTER(LobpcgOpts), _p, _p, _p, _p, _p,
+    L.orc_lobpcg.argtypes = [_i64, _p, _p, _p, _p, C.POINTER(LobpcgOpts), _p, _p, _p, _p, _p,
                              C.POINTER(LobpcgInfo)]
     L.orc_kmeans.restype = _int
     L.orc_kmeans.argtypes = [_i64, _int, _p, _i64, _int, _int, _int, _p, _p, _int, _p, _p,
@@ -143,19 +145,30 @@ def laplacian(g: CSR):
     return val[: g.nnz].copy(), dis
 
 
-def spmm(g: CSR, val, X):
-    """Y = L X for a row-major n x k block (same arithmetic as the definition)."""
+def laplacian_combinatorial(g: CSR):
+    """L = D - W (Section II-A): off-diagonal values -w and the diagonal (degrees)."""
+    val = np.zeros(max(g.nnz, 1), dtype=np.float64)
+    _check(lib().orc_laplacian_combinatorial(g.n, _ptr(g.row_ptr), _ptr(g.col), _ptr(g.w),
+                                             _ptr(val)), "laplacian_combinatorial")
+    return val[: g.nnz].copy(), g.degree.copy()
+
+
+def spmm(g: CSR, val, X, diag=None):
+    """Y = L X for a row-major n x k block (same arithmetic as the definition);
+    diag None: unit diagonal (normalised Laplacian)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     n, k = X.shape
     Y = np.empty_like(X)
     v = np.ascontiguousarray(val, dtype=np.float64)
-    lib().orc_spmm_rowmajor(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), k, _ptr(X), k, _ptr(Y), k)
+    d = None if diag is None else np.ascontiguousarray(diag, dtype=np.float64)
+    lib().orc_spmm_rowmajor(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), _ptr(d), k, _ptr(X), k,
+                            _ptr(Y), k)
     return Y
 
 
-def dense_laplacian(g: CSR, val) -> np.ndarray:
+def dense_laplacian(g: CSR, val, diag=None) -> np.ndarray:
     """Dense L (tests only, small n)."""
-    L = np.eye(g.n)
+    L = np.eye(g.n) if diag is None else np.diag(np.asarray(diag, dtype=np.float64))
     for i in range(g.n):
         for p in range(g.row_ptr[i], g.row_ptr[i + 1]):
             L[i, g.col[p]] += val[p]
@@ -206,19 +219,29 @@ class LobpcgResult:
     max_relres: float
 
 
-def lobpcg(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL) -> LobpcgResult:
-    """Smallest-k eigenpairs of L by block LOBPCG without preconditioning."""
+def op_norm_bound(diag) -> float:
+    """||L|| bound for the relative residual: 2 for the normalised Laplacian
+    (diag None), 2 max_i d_i for L = D - W (Gershgorin)."""
+    return 2.0 if diag is None else 2.0 * float(np.max(diag)) if len(diag) else 2.0
+
+
+def lobpcg(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL,
+           diag=None) -> LobpcgResult:
+    """Smallest-k eigenpairs of L by block LOBPCG without preconditioning
+    (diag None: the normalised Laplacian; else L = diag + offdiag(val))."""
     X0 = np.ascontiguousarray(X0, dtype=np.float64)
     n, k = X0.shape
     X = np.zeros_like(X0)
     theta = np.zeros(k)
     rh = np.zeros((maxit + 1, k))
     th = np.zeros((maxit + 1, k))
-    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol)
+    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol, op_norm_bound(diag))
     info = LobpcgInfo()
     v = np.ascontiguousarray(val, dtype=np.float64)
-    _check(lib().orc_lobpcg(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), C.byref(o), _ptr(X0),
-                            _ptr(X), _ptr(theta), _ptr(rh), _ptr(th), C.byref(info)), "lobpcg")
+    d = None if diag is None else np.ascontiguousarray(diag, dtype=np.float64)
+    _check(lib().orc_lobpcg(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), _ptr(d), C.byref(o),
+                            _ptr(X0), _ptr(X), _ptr(theta), _ptr(rh), _ptr(th), C.byref(info)),
+           "lobpcg")
     it = info.iterations
     return LobpcgResult(X, theta, rh[: it + 1].copy(), th[: it + 1].copy(), it,
                         bool(info.converged), info.p_drops, info.locked_cols, info.max_relres)
@@ -228,13 +251,13 @@ def lobpcg_status(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=C
     """Status code only (for the failure-path tests)."""
     X0 = np.ascontiguousarray(X0, dtype=np.float64)
     n, k = X0.shape
-    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol)
+    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol, 2.0)
     info = LobpcgInfo()
     X = np.zeros_like(X0)
     theta = np.zeros(k)
     v = np.ascontiguousarray(val, dtype=np.float64)
-    return lib().orc_lobpcg(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), C.byref(o), _ptr(X0),
-                            _ptr(X), _ptr(theta), None, None, C.byref(info))
+    return lib().orc_lobpcg(n, _ptr(g.row_ptr), _ptr(g.col), _ptr(v), None, C.byref(o),
+                            _ptr(X0), _ptr(X), _ptr(theta), None, None, C.byref(info))
 
 
 @dataclass

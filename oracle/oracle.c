@@ -22,6 +22,9 @@
  *   orc_graph_build   symmetrisation W + W' (Section II-A): logical sum for
  *                     unweighted graphs, algebraic sum for weighted ones
  *   orc_laplacian     normalised Laplacian I - D^-1/2 W D^-1/2 of W's pattern
+ *   orc_laplacian_combinatorial
+ *                     the graph Laplacian L = D - W as Section II-A introduces it
+ *                     (off-diagonal -w, diagonal the degrees)
  *   orc_spmm          Y = L X, the one matrix product per iteration (Section III)
  *   orc_gram, orc_cholesky, orc_symeig (cyclic Jacobi)  dense helpers
  *   orc_lobpcg        block LOBPCG without preconditioning (Section II-B,
@@ -141,17 +144,34 @@ int orc_laplacian(int64_t n, const int64_t* row_ptr, const int32_t* col, const d
     return ORC_OK;
 }
 
+/*
+ * The graph Laplacian L = D - W (Section II-A; the diagonal entries are the
+ * vertex degrees, as the pre-computed diagonal of the matrix-free product in
+ * Section III).  Off-diagonal value -w_p, exact.
+ */
+int orc_laplacian_combinatorial(int64_t n, const int64_t* row_ptr, const int32_t* col,
+                                const double* w_sym, double* val) {
+    if (n <= 0) return ORC_E_INVAL;
+    (void)col;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) val[p] = -(w_sym ? w_sym[p] : 1.0);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
-/* Y = L X with L = I + offdiag(val): y_ij = x_ij then, over row i in        */
-/* ascending column order, y_ij = fma(v_p, x_{col_p j}, y_ij).                */
+/* Y = L X with L = diag(a) + offdiag(val): y_ij = a_i x_ij (one rounded     */
+/* product; a_i = 1, i.e. y_ij = x_ij, when diag is NULL: the normalised     */
+/* Laplacian), then, over row i in ascending column order,                   */
+/* y_ij = fma(v_p, x_{col_p j}, y_ij).                                        */
 /* Row-major entry point (ld = row stride) used directly by the tests.       */
 /* ------------------------------------------------------------------------ */
 void orc_spmm_rowmajor(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
-                       int k, const double* X, int64_t ldx, double* Y, int64_t ldy) {
+                       const double* diag, int k, const double* X, int64_t ldx, double* Y,
+                       int64_t ldy) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         for (int j = 0; j < k; ++j) {
-            double acc = X[i * ldx + j];
+            double acc = diag ? diag[i] * X[i * ldx + j] : X[i * ldx + j];
             for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
                 acc = fma(val[p], X[(int64_t)col[p] * ldx + j], acc);
             Y[i * ldy + j] = acc;
@@ -161,13 +181,13 @@ void orc_spmm_rowmajor(int64_t n, const int64_t* row_ptr, const int32_t* col, co
 
 /* Column-major variant used inside the oracle's LOBPCG (same arithmetic). */
 static void spmm_cm(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
-                    int k, const double* X, double* Y) {
+                    const double* diag, int k, const double* X, double* Y) {
     for (int j = 0; j < k; ++j) {
         const double* x = X + (int64_t)j * n;
         double* y = Y + (int64_t)j * n;
 #pragma omp parallel for schedule(dynamic, 1024)
         for (int64_t i = 0; i < n; ++i) {
-            double acc = x[i];
+            double acc = diag ? diag[i] * x[i] : x[i];
             for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) acc = fma(val[p], x[col[p]], acc);
             y[i] = acc;
         }
@@ -449,6 +469,7 @@ typedef struct {
     double tol;        /* converged when max_j relres_j <= tol */
     double lock_tol;   /* columns with relres_j <= lock_tol leave the W block */
     double chol_tol;   /* relative pivot floor of every Cholesky */
+    double op_norm;    /* upper bound of ||L|| scaling the relative residual (0: 2) */
 } orc_lobpcg_opts;
 
 typedef struct {
@@ -460,17 +481,20 @@ typedef struct {
 } orc_lobpcg_info;
 
 /*
- * Smallest-k eigenpairs of the normalised Laplacian by block LOBPCG with
- * T = I.  X0 and X_out are row-major n x k (ld k).  relres_hist (optional)
+ * Smallest-k eigenpairs of L = diag(a) + offdiag(val) by block LOBPCG with
+ * T = I: the normalised Laplacian (diag NULL, a = 1) or L = D - W (diag the
+ * degrees).  X0 and X_out are row-major n x k (ld k).  relres_hist (optional)
  * receives (iterations+1) rows of k relative residuals
- *   relres_j = ||L x_j - theta_j x_j|| / (2 ||x_j||)   (||L|| <= 2);
+ *   relres_j = ||L x_j - theta_j x_j|| / (N ||x_j||),  N = op_norm >= ||L||
+ * (N = 2 for the normalised Laplacian; 2 max_i d_i bounds D - W, Gershgorin);
  * theta_hist (optional) receives the Ritz values after every RR step
  * (iterations+1 rows).  Both need room for (maxit+1)*k doubles.
  */
 int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const double* val,
-               const orc_lobpcg_opts* o, const double* X0, double* X_out, double* theta,
+               const double* diag, const orc_lobpcg_opts* o, const double* X0, double* X_out, double* theta,
                double* relres_hist, double* theta_hist, orc_lobpcg_info* info) {
     int k = o->k, K3 = 3 * o->k;
+    const double opn = o->op_norm > 0.0 ? o->op_norm : 2.0;
     if (n <= 0 || k < 1 || (int64_t)K3 > n || o->maxit < 0) return ORC_E_INVAL;
     for (int64_t i = 0; i < n * k; ++i) if (!isfinite(X0[i])) return ORC_E_NUMERIC;
     size_t blk = (size_t)n * (size_t)k;
@@ -498,7 +522,7 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
         if (!cholqr_masked(n, k, X, NULL, act3, o->chol_tol)) { status = ORC_E_BREAKDOWN; goto out; }
         for (int j = 0; j < k; ++j) if (!act3[j]) { status = ORC_E_BREAKDOWN; goto out; }
     }
-    spmm_cm(n, row_ptr, col, val, k, X, LX);
+    spmm_cm(n, row_ptr, col, val, diag, k, X, LX);
 
     /* Rayleigh-Ritz on span(X) alone; then the main loop */
     int has_p = 0;
@@ -523,7 +547,7 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
             for (int j = 0; j < k; ++j) inf.locked_cols += !act3[k + j];
             (void)any_w;
             if (!cholqr_masked(n, k, W, NULL, act3 + k, o->chol_tol)) { status = ORC_E_BREAKDOWN; goto out; }
-            spmm_cm(n, row_ptr, col, val, k, W, LW);
+            spmm_cm(n, row_ptr, col, val, diag, k, W, LW);
             if (has_p) {
                 for (int j = 0; j < k; ++j) act3[2 * k + j] = 1;
                 if (!cholqr_masked(n, k, P, LP, act3 + 2 * k, o->chol_tol)) {
@@ -586,7 +610,7 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
                 xx = fma(x[i], x[i], xx);
             }
             rho[j] = sqrt(rr);
-            relres[j] = rho[j] / (2.0 * sqrt(xx));
+            relres[j] = rho[j] / (opn * sqrt(xx));
         }
         double mx = 0.0;
         int all_locked = 1;
