@@ -35,10 +35,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def spmm_algorithmic_bytes(n, nnz, k, s):
+def spmm_algorithmic_bytes(n, nnz, k, s, diag=False):
     """Compulsory bytes of one Y = L X: row pointers, column indices and
-    values once, X read once and Y written once."""
-    return 8 * (n + 1) + nnz * (4 + s) + 2 * n * k * s
+    values once (and the diagonal, for D - W), X read once and Y written once."""
+    return 8 * (n + 1) + nnz * (4 + s) + 2 * n * k * s + (n * s if diag else 0)
 
 
 def spmm_traffic(cfg_name, launches_bytes):
@@ -57,7 +57,7 @@ def spmm_traffic(cfg_name, launches_bytes):
         return None
 
 
-def cpu_baseline(g0, cfg, gpu_iters, sample_div=(128, 64)):
+def cpu_baseline(g0, cfg, gpu_iters, sample_div=(128, 64), combinatorial=False):
     """Oracle timed on the host, on a bounded sample of the workload: its
     graph build and Laplacian on the full graph, then its LOBPCG start-up and
     one iteration on two smaller graphs of the same generator (n/128 and
@@ -69,9 +69,12 @@ def cpu_baseline(g0, cfg, gpu_iters, sample_div=(128, 64)):
     import oracle
     from synth import dcsbm, gaussian_block
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    def lap(g):
+        return oracle.laplacian_combinatorial(g) if combinatorial else (oracle.laplacian(g)[0], None)
+
     t0 = time.perf_counter()
     g = oracle.graph_build(g0.n, g0.src, g0.dst)
-    val, _ = oracle.laplacian(g)
+    val, _ = lap(g)
     t_graph = time.perf_counter() - t0
     del g, val
     pts = []
@@ -80,13 +83,13 @@ def cpu_baseline(g0, cfg, gpu_iters, sample_div=(128, 64)):
         gs0 = dcsbm(ns, cfg["blocks"], cfg["mean_degree"], cfg["intra"], cfg["sizes"],
                     cfg["alpha"], 1)
         gs = oracle.graph_build(gs0.n, gs0.src, gs0.dst)
-        vs, _ = oracle.laplacian(gs)
+        vs, ds = lap(gs)
         X0 = gaussian_block(gs0.n, cfg["k"], 1)
         t1 = time.perf_counter()
-        oracle.lobpcg(gs, vs, X0, 0)             # CholQR2 + SpMM + initial Rayleigh-Ritz
+        oracle.lobpcg(gs, vs, X0, 0, diag=ds)    # CholQR2 + SpMM + initial Rayleigh-Ritz
         t_init = time.perf_counter() - t1
         t2 = time.perf_counter()
-        oracle.lobpcg(gs, vs, X0, 1)
+        oracle.lobpcg(gs, vs, X0, 1, diag=ds)
         t_one = max(time.perf_counter() - t2 - t_init, 1e-9)
         pts.append((ns, t_init, t_one))
     (n1, i1, o1), (n2, i2, o2) = pts
@@ -234,6 +237,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")
+    ap.add_argument("--laplacian", default="normalized", choices=["normalized", "combinatorial"],
+                    help="operator: I - D^-1/2 W D^-1/2 (default) or D - W (relres scaled by "
+                         "2 max degree)")
     ap.add_argument("--compare", action="store_true",
                     help="also solve the same graph from the same start block in FP64 and report "
                          "speedup, eigenvalue error, subspace sine and accuracy of both")
@@ -241,6 +247,8 @@ def main():
                     help="after the timed steps, run a plain 512 MiB device copy three times "
                          "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
+    if args.laplacian == "combinatorial" and args.compare:
+        ap.error("--compare runs the normalised Laplacian only")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs a single solve per GPU and has "
@@ -276,11 +284,18 @@ def main():
     draws = torch.from_numpy(draws_h.view(np.int64)).to(dev)
     ctx = api.Context(0)
 
+    comb = args.laplacian == "combinatorial"
+
     def step():
         gd = api.graph_build(ctx, n, src, dst)
-        v64, v32, _ = api.laplacian_csr(ctx, gd, fp64, not fp64)
+        diag = None
+        if comb:
+            v64, v32, d32 = api.laplacian_combinatorial(ctx, gd, fp64, not fp64)
+            diag = gd.degree if fp64 else d32
+        else:
+            v64, v32, _ = api.laplacian_csr(ctx, gd, fp64, not fp64)
         val = v64 if fp64 else v32
-        res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec)
+        res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag)
         km = api.kmeans_assign(ctx, res.X, k, draws, max_iter=100)
         return gd, res, km
 
@@ -312,7 +327,7 @@ def main():
     ms_per_step = 1000.0 * total / args.steps
     es = 8 if fp64 else 4
     spmm = prof.get("spmm", {"avg_ms": float("nan"), "launches": 0})
-    alg_bytes = spmm_algorithmic_bytes(n, gd.nnz, k, es)
+    alg_bytes = spmm_algorithmic_bytes(n, gd.nnz, k, es, comb)
     achieved = alg_bytes / (spmm["avg_ms"] * 1e-3) / 1e9
     lob_ms = sum(prof.get(x, {}).get("total_ms", 0.0) for x in
                  ("spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual"))
@@ -333,7 +348,8 @@ def main():
         "config": {"workload": (f"degree-corrected SBM n={n} m={g0.m} blocks={cfg['blocks']} "
                                 f"mean_degree={cfg['mean_degree']} intra={cfg['intra']} "
                                 f"sizes={cfg['sizes']}({cfg['alpha']}); LOBPCG k={k} "
-                                f"maxit={cfg['maxit']} tol={cfg['tol']} {prec}; k-means "
+                                f"maxit={cfg['maxit']} tol={cfg['tol']} {prec}"
+                                f"{'; Laplacian D - W' if comb else ''}; k-means "
                                 f"restarts={restarts}"),
                    "name": args.config, "n": n, "nnz": gd.nnz, "k": k},
         "lobpcg_iterations": res.iterations,
@@ -379,7 +395,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         try:
-            out["cpu_baseline"] = cpu_baseline(g0, cfg, res.iterations)
+            out["cpu_baseline"] = cpu_baseline(g0, cfg, res.iterations, combinatorial=comb)
         except Exception as e:  # the GPU result stands on its own
             out["cpu_baseline"] = {"value": None, "error": str(e)}
     print(json.dumps(out), flush=True)

@@ -123,6 +123,25 @@ sc_status sc_laplacian_csr(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* r
                            double* val64, float* val32, double* dinv_sqrt);
 
 /*
+ * The graph Laplacian L = D - W as Section II-A introduces it (Section III
+ * applies it matrix-free with the degrees as pre-computed diagonal), on the
+ * pattern of sc_graph_build: val_p = -w_p (exact; -1 for unit weights), and
+ * the diagonal d_i, which is `degree` itself for FP64 products.
+ *   row_ptr, degree  from sc_graph_build (device)
+ *   w_sym    float64 [nnz] or NULL (unit weights)
+ *   val64    float64 [nnz] (out) or NULL
+ *   val32    float32 [nnz] (out) or NULL: val64 rounded to nearest
+ *   diag32   float32 [n] (out) or NULL: the degrees rounded to nearest, the
+ *            diagonal of FP32 products
+ * Pass the diagonal to sc_spmm_diag / sc_lobpcg_opts.diag, with
+ * sc_lobpcg_opts.op_norm = 2 max_i d_i (Gershgorin bound of ||D - W||).
+ * No synchronisation.
+ */
+sc_status sc_laplacian_combinatorial(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                     const double* w_sym, const double* degree, double* val64,
+                                     float* val32, float* diag32);
+
+/*
  * Y = L X: the one multiplication by the graph Laplacian per LOBPCG
  * iteration (Section III).  For every row i and column j < k,
  *   y_ij = x_ij, then over row i in ascending column order
@@ -133,6 +152,18 @@ sc_status sc_laplacian_csr(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* r
 sc_status sc_spmm(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                   const int32_t* col, const void* val, int fp64, int k, const void* X,
                   int64_t ldx, void* Y, int64_t ldy);
+
+/*
+ * Y = L X with an explicit diagonal a (L = D - W: a = the degrees):
+ *   y_ij = a_i x_ij (one rounded product), then over row i in ascending
+ *   column order y_ij = fma(val_p, x_{col_p, j}, y_ij).
+ * diag: n entries of the product's type (float64 if fp64 else float32), device,
+ * or NULL for the unit diagonal (then identical to sc_spmm).  Other arguments
+ * as sc_spmm.  No synchronisation.
+ */
+sc_status sc_spmm_diag(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                       const int32_t* col, const void* val, const void* diag, int fp64, int k,
+                       const void* X, int64_t ldx, void* Y, int64_t ldy);
 
 /* ------------------------------------------------------------------------
  * LOBPCG without preconditioning for the k smallest eigenpairs of L.
@@ -147,6 +178,11 @@ typedef struct {
                               (0 = default: 1e-13 in FP64, 1e-6 otherwise) */
     double chol_tol;       /* relative pivot floor of every Cholesky
                               (0 = default: 1e-14 in FP64, 1e-6 otherwise) */
+    const void* diag;      /* diagonal of L, n entries (float64 in FP64 mode, else
+                              float32), device; NULL = unit diagonal, i.e. the
+                              normalised Laplacian I - D^-1/2 W D^-1/2 */
+    double op_norm;        /* upper bound of ||L|| in relres_j = ||r_j|| / (op_norm
+                              ||x_j||) (0 = default 2, the normalised Laplacian's) */
 } sc_lobpcg_opts;
 
 typedef struct {
@@ -167,9 +203,11 @@ sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobp
 
 /*
  * Block LOBPCG (Knyazev 2001) with T = I for the smallest k eigenpairs of
- * L = I + offdiag(val).  Iteration, with S = [X W P] and LS = L S:
+ * L = diag(a) + offdiag(val): a = 1 (opts.diag NULL, the normalised
+ * Laplacian) or a = opts.diag (L = D - W).  Iteration, with S = [X W P] and
+ * LS = L S (N = opts.op_norm, 2 by default):
  *   init: X <- CholQR2(X0); LX = L X; Rayleigh-Ritz on span(X);
- *   each iteration: R = LX - X diag(theta); relres_j = ||R_j|| / (2 ||x_j||);
+ *   each iteration: R = LX - X diag(theta); relres_j = ||R_j|| / (N ||x_j||);
  *     stop if max relres <= tol; W <- CholQR(R without locked columns);
  *     LW = L W; P, LP <- CholQR(P) (P dropped for this iteration if that
  *     Cholesky fails); Gram matrices S'LS and S'S (3k x 3k); Rayleigh-Ritz in
@@ -185,7 +223,7 @@ sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobp
  * for FP32, 2^-5 for BF16); where it fails, both are recomputed from the
  * FP32 data widened to FP64 (exact products, FP64 accumulation) and the
  * ordinary Rayleigh-Ritz runs on those (info.gram_fallbacks).  An iterate
- * whose Ritz values leave [0, 2] by more than 1e-3, or with a relres above 1
+ * whose Ritz values leave [0, N] by more than N * 5e-4, or with a relres above 1
  * (impossible while LX = L X holds), shows that the recurrence for LX has
  * drifted: it is not accepted as converged, and the next iteration restarts
  * explicitly (X <- CholQR2(X), LX = L X, Rayleigh-Ritz on span(X), P

@@ -30,7 +30,7 @@ _size = C.c_size_t
 
 class sc_lobpcg_opts(C.Structure):
     _fields_ = [("k", _int), ("maxit", _int), ("tol", _dbl), ("prec", _int), ("ldx", _i64),
-                ("lock_tol", _dbl), ("chol_tol", _dbl)]
+                ("lock_tol", _dbl), ("chol_tol", _dbl), ("diag", _p), ("op_norm", _dbl)]
 
 
 class sc_lobpcg_info(C.Structure):
@@ -63,7 +63,9 @@ SIGNATURES = {
     "sc_graph_build": (_int, [_p, _i64, _i64, _p, _p, _p, _int, _p, _p, _p, _p,
                               C.POINTER(_i64), C.POINTER(_i64), _p, _size]),
     "sc_laplacian_csr": (_int, [_p, _i64, _i64, _p, _p, _p, _p, _p, _p, _p]),
+    "sc_laplacian_combinatorial": (_int, [_p, _i64, _i64, _p, _p, _p, _p, _p, _p]),
     "sc_spmm": (_int, [_p, _i64, _i64, _p, _p, _p, _int, _int, _p, _i64, _p, _i64]),
+    "sc_spmm_diag": (_int, [_p, _i64, _i64, _p, _p, _p, _p, _int, _int, _p, _i64, _p, _i64]),
     "sc_lobpcg_workspace": (_int, [_p, _i64, _i64, C.POINTER(sc_lobpcg_opts), C.POINTER(_size)]),
     "sc_lobpcg_solve": (_int, [_p, _i64, _i64, _p, _p, _p, C.POINTER(sc_lobpcg_opts), _p, _p,
                                _p, _p, C.POINTER(sc_lobpcg_info), _p, _size]),

@@ -123,16 +123,31 @@ def laplacian_csr(ctx: Context, g: DeviceCSR, fp64: bool = True, fp32: bool = Fa
     return val64, val32, dis
 
 
+def laplacian_combinatorial(ctx: Context, g: DeviceCSR, fp64: bool = True, fp32: bool = False):
+    """L = D - W: off-diagonal values (FP64 and/or FP32) and the FP32 diagonal
+    (the FP64 diagonal is g.degree itself)."""
+    dev = g.row_ptr.device
+    val64 = torch.empty(max(g.nnz, 1), dtype=torch.float64, device=dev) if fp64 else None
+    val32 = torch.empty(max(g.nnz, 1), dtype=torch.float32, device=dev) if fp32 else None
+    diag32 = torch.empty(g.n, dtype=torch.float32, device=dev) if fp32 else None
+    ctx.check(lib().sc_laplacian_combinatorial(ctx.handle, g.n, g.nnz, _ptr(g.row_ptr),
+                                               _ptr(g.w_sym), _ptr(g.degree), _ptr(val64),
+                                               _ptr(val32), _ptr(diag32)),
+              "sc_laplacian_combinatorial")
+    return val64, val32, diag32
+
+
 def spmm(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
-         Y: torch.Tensor | None = None) -> torch.Tensor:
+         Y: torch.Tensor | None = None, diag: torch.Tensor | None = None) -> torch.Tensor:
     n, k = X.shape
     if Y is None:
         Y = torch.empty_like(X)
     fp64 = X.dtype == torch.float64
-    if val.dtype != X.dtype or Y.dtype != X.dtype:
-        raise TypeError("val, X and Y must share one dtype")
-    ctx.check(lib().sc_spmm(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
-                            int(fp64), k, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0)), "sc_spmm")
+    if val.dtype != X.dtype or Y.dtype != X.dtype or (diag is not None and diag.dtype != X.dtype):
+        raise TypeError("val, diag, X and Y must share one dtype")
+    ctx.check(lib().sc_spmm_diag(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
+                                 _ptr(diag), int(fp64), k, _ptr(X), X.stride(0), _ptr(Y),
+                                 Y.stride(0)), "sc_spmm_diag")
     return Y
 
 
@@ -151,8 +166,10 @@ class LobpcgResult:
     restarts: int = 0
 
 
-def lobpcg_opts(k, maxit, tol, precision, ldx, lock_tol=0.0, chol_tol=0.0):
-    return _lib.sc_lobpcg_opts(k, maxit, tol, PRECISIONS[precision], ldx, lock_tol, chol_tol)
+def lobpcg_opts(k, maxit, tol, precision, ldx, lock_tol=0.0, chol_tol=0.0, diag=None,
+                op_norm=0.0):
+    return _lib.sc_lobpcg_opts(k, maxit, tol, PRECISIONS[precision], ldx, lock_tol, chol_tol,
+                               _ptr(diag), op_norm)
 
 
 def lobpcg_workspace(ctx: Context, n, nnz, opts) -> int:
@@ -165,10 +182,18 @@ def lobpcg_workspace(ctx: Context, n, nnz, opts) -> int:
 def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor, maxit: int,
                  tol: float = 0.0, precision: str = "fp64", lock_tol: float = 0.0,
                  chol_tol: float = 0.0, history: bool = True, ws: torch.Tensor | None = None,
-                 X_out: torch.Tensor | None = None) -> LobpcgResult:
+                 X_out: torch.Tensor | None = None, diag: torch.Tensor | None = None,
+                 op_norm: float = 0.0) -> LobpcgResult:
+    """diag None: the normalised Laplacian (unit diagonal, op_norm 2).  With a
+    diagonal (L = D - W) op_norm defaults to 2 max(diag), the Gershgorin bound."""
     import numpy as np
     n, k = X0.shape
-    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol)
+    if diag is not None:
+        if diag.dtype != X0.dtype:
+            raise TypeError("diag must have X0's dtype")
+        if op_norm <= 0.0:
+            op_norm = 2.0 * float(diag.max()) if diag.numel() else 2.0
+    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol, diag, op_norm)
     nb = lobpcg_workspace(ctx, n, g.nnz, opts)
     if ws is None or ws.numel() < nb:
         ws = ctx.workspace(nb)

@@ -346,7 +346,8 @@ __global__ void k_gram_reduce(int c, int chunks, int nout, const double* __restr
 // Cholesky QR factor of a small Gram matrix (one workgroup).
 // ---------------------------------------------------------------------------
 constexpr int CQ_TH = 1024;
-// Ritz values further than this outside [0, 2] mark an inconsistent iterate
+// Ritz values further than this (relative to op_norm / 2, i.e. absolute for the
+// normalised Laplacian's [0, 2]) outside [0, op_norm] mark an inconsistent iterate
 constexpr double RESTART_THETA_SLACK = 1e-3;
 constexpr int CQ_MAX = 256;
 
@@ -788,7 +789,8 @@ k_residual_colsum(int nblocks, int kp, double* __restrict__ partial) {
 }
 
 __global__ void __launch_bounds__(256)
-k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ partial, double lock_tol,
+k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ partial, double op_norm,
+                    double lock_tol,
                     double* __restrict__ relres, double* __restrict__ hist_row, int* __restrict__ wmask,
                     int* status, double* out_max, int* out_all_locked,
                     const double* __restrict__ theta, int* __restrict__ out_restart) {
@@ -805,18 +807,18 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
             xx += partial[((int64_t)b * 2 + 1) * kp + j];
         }
         if (j < k) {
-            const double rel = sqrt(rr) / (2.0 * sqrt(xx));
+            const double rel = sqrt(rr) / (op_norm * sqrt(xx));
             if (!isfinite(rel)) atomicOr(status, DEV_NUMERIC);
             relres[j] = rel;
             if (hist_row) hist_row[j] = rel;
             const int active = rel > lock_tol;
             wmask[j] = active;
-            // a consistent iterate has theta in [0, 2] (spectrum of L) and
-            // ||Lx - theta x|| <= 2 ||x||, i.e. relres <= 1
+            // a consistent iterate has theta in [0, op_norm] (spectrum of L)
+            // and ||Lx - theta x|| <= op_norm ||x||, i.e. relres <= 1
             if (out_restart) {
                 const double th = theta[j];
-                if (!(th >= -RESTART_THETA_SLACK && th <= 2.0 + RESTART_THETA_SLACK) || rel > 1.0)
-                    my_bad = 1;
+                const double slack = RESTART_THETA_SLACK * 0.5 * op_norm;
+                if (!(th >= -slack && th <= op_norm + slack) || rel > 1.0) my_bad = 1;
             }
             my_all &= !active;
             my_max = fmax(my_max, rel);
@@ -1164,7 +1166,7 @@ template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, float*, co
                                           const double*, double*, int*);
 
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, double* partial,
-                                   double lock_tol, double* relres, double* hist_row, int* wmask,
+                                   double op_norm, double lock_tol, double* relres, double* hist_row, int* wmask,
                                    int* status, double* out_max, int* out_all_locked,
                                    const double* theta, int* out_restart) {
     if (nblocks > 1) {
@@ -1173,7 +1175,7 @@ sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, doub
         nblocks = 1;
     }
     hipLaunchKernelGGL(k_residual_finalize, dim3(1), dim3(256), 0, ctx->stream, nblocks, kp, k,
-                       partial, lock_tol, relres, hist_row, wmask, status, out_max,
+                       partial, op_norm, lock_tol, relres, hist_row, wmask, status, out_max,
                        out_all_locked, theta, out_restart);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;

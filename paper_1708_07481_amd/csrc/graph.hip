@@ -116,6 +116,22 @@ __global__ void k_laplacian(int64_t n, const int64_t* __restrict__ row_ptr,
     }
 }
 
+// L = D - W (Section II-A): off-diagonal -w_p (exact), diagonal the degrees;
+// diag32 is the FP32 copy of the diagonal for the FP32 product
+__global__ void k_laplacian_comb(int64_t n, const int64_t* __restrict__ row_ptr,
+                                 const double* __restrict__ w_sym, const double* __restrict__ degree,
+                                 double* __restrict__ val64, float* __restrict__ val32,
+                                 float* __restrict__ diag32) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (diag32) diag32[i] = (float)degree[i];
+    for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        const double v = -(w_sym ? w_sym[p] : 1.0);
+        if (val64) val64[p] = v;
+        if (val32) val32[p] = (float)v;
+    }
+}
+
 struct GraphWs {
     uint64_t *keys, *keys_alt, *flag, *radix_tmp, *scan_tmp;
     uint32_t *vals, *vals_alt;
@@ -221,6 +237,21 @@ extern "C" sc_status sc_laplacian_csr(sc_ctx* ctx, int64_t n, int64_t nnz, const
     SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(k_laplacian, dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, row_ptr,
                        col, w_sym, degree, val64, val32, dinv_sqrt);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
+extern "C" sc_status sc_laplacian_combinatorial(sc_ctx* ctx, int64_t n, int64_t nnz,
+                                                const int64_t* row_ptr, const double* w_sym,
+                                                const double* degree, double* val64, float* val32,
+                                                float* diag32) {
+    if (!ctx) return SC_E_INVAL;
+    if (n <= 0 || nnz < 0)
+        return sc_fail(ctx, SC_E_INVAL, "laplacian_combinatorial: need n > 0, nnz >= 0");
+    if (!row_ptr || !degree) return sc_fail(ctx, SC_E_INVAL, "laplacian_combinatorial: null pointer argument");
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_laplacian_comb, dim3(ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n, row_ptr,
+                       w_sym, degree, val64, val32, diag32);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }

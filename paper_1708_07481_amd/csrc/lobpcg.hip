@@ -60,8 +60,10 @@ struct sc_lobpcg_state {
     const int64_t* row_ptr = nullptr;
     const int32_t* col = nullptr;
     const void* val = nullptr;
+    const void* diag = nullptr;     // diagonal of L (nullptr: unit, normalised Laplacian)
     int k = 0, kp = 0, K3 = 0, maxit = 0;
     double tol = 0, lock_tol = 0, chol_tol = 0;
+    double op_norm = 2.0;           // bound on ||L|| scaling the relative residual
     sc_precision prec = SC_PREC_FP64;
     int64_t ldx = 0;
     // workspace views
@@ -175,6 +177,7 @@ struct Solver {
     static T* S(sc_lobpcg_state* s) { return static_cast<T*>(s->S); }
     static T* LS(sc_lobpcg_state* s) { return static_cast<T*>(s->LS); }
     static const T* val(sc_lobpcg_state* s) { return static_cast<const T*>(s->val); }
+    static const T* diag(sc_lobpcg_state* s) { return static_cast<const T*>(s->diag); }
 
     // W/X/P block CholQR with mask `m` (kp columns at column offset `off`)
     static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int mode,
@@ -251,7 +254,7 @@ struct Solver {
             ProfScope ps(ctx, SC_KIND_RESIDUAL);
             SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
                                       s->res_part, &nb));
-            SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->lock_tol,
+            SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->op_norm, s->lock_tol,
                                             s->relres, s->hist + (int64_t)s->t * s->kp,
                                             s->act + s->kp, s->status, s->out_max,
                                             s->all_locked, s->theta,
@@ -327,7 +330,7 @@ struct Solver {
         }
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld));
         }
         // Rayleigh-Ritz on span(X) alone
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
@@ -358,7 +361,7 @@ struct Solver {
         }
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s), ld, LS(s), ld));
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld));
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
         SC_CHECK_LAUNCH(ctx);
@@ -385,7 +388,7 @@ struct Solver {
             SC_TRY(cholqr(ctx, s, kp, 0, CQ_DROP_DEPENDENT, s->wdrops));
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), s->k, S(s) + kp, ld,
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s) + kp, ld,
                                   LS(s) + kp, ld));
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
@@ -479,6 +482,8 @@ extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const 
     s->row_ptr = row_ptr;
     s->col = col;
     s->val = val;
+    s->diag = opts->diag;
+    s->op_norm = opts->op_norm > 0 ? opts->op_norm : 2.0;
     s->k = opts->k;
     s->maxit = opts->maxit;
     s->tol = opts->tol;

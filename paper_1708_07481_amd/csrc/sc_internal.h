@@ -152,7 +152,8 @@ sc_status radix_sort_pairs(sc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t
 // ---------------------------------------------------------------------------
 template <class T>
 sc_status launch_spmm(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col,
-                      const T* val, int k, const T* X, int64_t ldx, T* Y, int64_t ldy);
+                      const T* val, const T* diag, int k, const T* X, int64_t ldx, T* Y,
+                      int64_t ldy);
 
 // Gram products G1 = A^T B1 (and G2 = A^T B2 when B2 != nullptr), ca x cb,
 // upper triangle computed, mirrored; FP64 results.  A/B1/B2 are n x c blocks
@@ -206,11 +207,12 @@ sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* 
                           const double* theta, double* partial, int* nblocks_out);
 // Finalise: column totals of the block partials (in place), then relres,
 // history row, W mask, flags; out[0] = max relres, out_flags[0] = all columns
-// locked.  With out_restart non-null it is set to
-// 1 when the iterate is inconsistent (a Ritz value outside [0, 2] by more than
-// 1e-3, or relres > 1, impossible when LX = L X), else 0.
+// locked.  relres_j = ||r_j|| / (op_norm ||x_j||), op_norm >= ||L|| (2 for the
+// normalised Laplacian).  With out_restart non-null it is set to 1 when the
+// iterate is inconsistent (a Ritz value outside [0, op_norm] by more than
+// op_norm * 5e-4, or relres > 1, impossible when LX = L X), else 0.
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k,
-                                   double* partial, double lock_tol, double* relres,
+                                   double* partial, double op_norm, double lock_tol, double* relres,
                                    double* hist_row, int* wmask, int* status, double* out_max,
                                    int* out_all_locked, const double* theta, int* out_restart);
 

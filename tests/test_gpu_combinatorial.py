@@ -1,0 +1,166 @@
+"""GPU parity for the graph Laplacian L = D - W (Section II-A; Section III
+applies it with the degrees as pre-computed diagonal) against the oracle.
+
+Bar: off-diagonal values and the FP32 diagonal bit-exact; the FP64 product
+bit-exact (same rounded diagonal product, same fma chain); FP64 LOBPCG Ritz
+values within max(1e-8 |theta|, 1e-12 N / 2) with N = 2 max d the operator-norm
+bound (the normalised Laplacian's floor 1e-12 scaled to this operator's
+range), subspace sine <= 1e-6, same iteration count, relres history; FP32
+mode against the FP64 oracle to FP32-level tolerances; labels end to end."""
+import numpy as np
+import pytest
+
+from paper_1708_07481_amd.metrics import canonical_labels, partition_scores
+from synth import dcsbm, gaussian_block, kmeans_draws
+from tests import graphs
+from tests.gpu_common import gpu_ctx, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _sine(Xg, Xo):
+    return np.linalg.norm(Xg - Xo @ (Xo.T @ Xg), 2)
+
+
+def _pair(orc, ctx, n, src, dst, w=None, algebraic=False):
+    from paper_1708_07481_amd import api
+    go = orc.graph_build(n, src, dst, w, algebraic)
+    vo, do = orc.laplacian_combinatorial(go)
+    gd = api.graph_build(ctx, n, to_dev(src), to_dev(dst), None if w is None else to_dev(w),
+                         algebraic)
+    v64, v32, d32 = api.laplacian_combinatorial(ctx, gd, True, True)
+    return go, vo, do, gd, v64, v32, d32
+
+
+GRAPHS = [
+    ("sbm1k", lambda: (lambda g: (g.n, g.src, g.dst, None))(dcsbm(1000, 8, 20.0, 0.8, seed=1))),
+    ("multigraph", lambda: graphs.random_multigraph(3000, 40000, 3) + (None,)),
+    ("weighted", lambda: (lambda r: (2000, r.integers(0, 2000, 30000).astype(np.int32),
+                                     r.integers(0, 2000, 30000).astype(np.int32),
+                                     r.integers(1, 9, 30000).astype(np.float64)))(
+        np.random.default_rng(8))),
+]
+
+
+@pytest.mark.parametrize("name,make", GRAPHS, ids=[g[0] for g in GRAPHS])
+def test_combinatorial_values_bit_exact(orc, ctx, name, make):
+    n, src, dst, w = make()
+    go, vo, do, gd, v64, v32, d32 = _pair(orc, ctx, n, src, dst, w, algebraic=w is not None)
+    assert gd.nnz == go.nnz
+    assert np.array_equal(host(v64)[: go.nnz], vo)
+    assert np.array_equal(host(v32)[: go.nnz], vo.astype(np.float32))
+    assert np.array_equal(host(d32), do.astype(np.float32))
+    assert np.array_equal(host(gd.degree), do)
+
+
+@pytest.mark.parametrize("k", [1, 8, 44, 160])
+def test_combinatorial_spmm_fp64_bit_exact(orc, ctx, k):
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(3001, 13, 30.0, 0.7, "dirichlet", 2.0, seed=4)
+    go, vo, do, gd, v64, _, _ = _pair(orc, ctx, g0.n, g0.src, g0.dst)
+    X = np.random.default_rng(k).standard_normal((g0.n, k))
+    Yo = orc.spmm(go, vo, X, do)
+    Yd = host(api.spmm(ctx, gd, v64, to_dev(X), diag=gd.degree))
+    assert np.array_equal(Yd, Yo)
+    # L 1 = 0 exactly
+    ones = api.spmm(ctx, gd, v64, to_dev(np.ones((g0.n, 4))), diag=gd.degree)
+    assert np.all(host(ones) == 0.0)
+
+
+def test_combinatorial_spmm_fp32(orc, ctx):
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(5000, 19, 40.0, 0.75, "dirichlet", 5.0, seed=2)
+    go, vo, do, gd, _, v32, d32 = _pair(orc, ctx, g0.n, g0.src, g0.dst)
+    X = np.random.default_rng(1).standard_normal((g0.n, 19)).astype(np.float32)
+    Yo = orc.spmm(go, vo, X.astype(np.float64), do)
+    Yd = host(api.spmm(ctx, gd, v32, to_dev(X), diag=d32)).astype(np.float64)
+    # FP32 chain: |err| <= (deg + 2) 2^-24 (d |x_i| + sum |v x|), per row
+    absmag = orc.spmm(go, np.abs(vo), np.abs(X.astype(np.float64)), do)
+    deg = np.diff(go.row_ptr)[:, None]
+    assert np.all(np.abs(Yd - Yo) <= (deg + 2) * 2.0 ** -24 * 2 * absmag + 1e-30)
+
+
+def _theta_ok(tg, to, N):
+    return np.all(np.abs(tg - to) <= np.maximum(1e-8 * np.abs(to), 1e-12 * N / 2))
+
+
+CASES = [
+    ("sbm1k-k8-20it", lambda: dcsbm(1000, 8, 20.0, 0.8, seed=1), 8, 20, 0.0),
+    ("sbm5k-k19-tol", lambda: dcsbm(5000, 19, 40.0, 0.75, "dirichlet", 5.0, seed=2), 19, 30, 1e-3),
+    ("sbm3k-k13-ragged", lambda: dcsbm(3001, 13, 30.0, 0.7, "dirichlet", 2.0, seed=4), 13, 12, 0.0),
+]
+
+
+@pytest.mark.parametrize("name,make,k,maxit,tol", CASES, ids=[c[0] for c in CASES])
+def test_combinatorial_lobpcg_fp64_parity(orc, ctx, name, make, k, maxit, tol):
+    from paper_1708_07481_amd import api
+    g0 = make()
+    go, vo, do, gd, v64, _, _ = _pair(orc, ctx, g0.n, g0.src, g0.dst)
+    X0 = gaussian_block(g0.n, k, 11)
+    ro = orc.lobpcg(go, vo, X0, maxit, tol, diag=do)
+    rg = api.lobpcg_solve(ctx, gd, v64, to_dev(X0), maxit, tol, "fp64", diag=gd.degree)
+    N = 2 * do.max()
+    tg, Xg = host(rg.theta), host(rg.X)
+    print(name, "iters", ro.iterations, rg.iterations, "relres", ro.max_relres, rg.max_relres)
+    assert rg.iterations == ro.iterations
+    assert _theta_ok(tg, ro.theta, N), np.abs(tg - ro.theta).max()
+    assert _sine(Xg, ro.X) <= 1e-6
+    assert np.allclose(Xg.T @ Xg, np.eye(k), atol=1e-10)
+    assert np.allclose(rg.relres_hist, ro.relres_hist, rtol=1e-5, atol=1e-12)
+
+
+def test_combinatorial_cliques_null_space(orc, ctx):
+    from paper_1708_07481_amd import api
+    sizes = [12, 15, 18, 21]
+    n, src, dst = graphs.cliques(sizes)
+    go, vo, do, gd, v64, _, _ = _pair(orc, ctx, n, src, dst)
+    rg = api.lobpcg_solve(ctx, gd, v64, to_dev(gaussian_block(n, 4, 2)), 80, 1e-13, "fp64",
+                          diag=gd.degree)
+    assert np.all(np.abs(host(rg.theta)) < 1e-10)
+    ind = np.zeros((n, 4))
+    off = 0
+    for b, s in enumerate(sizes):
+        ind[off:off + s, b] = 1.0 / np.sqrt(s)
+        off += s
+    assert _sine(host(rg.X), ind) < 1e-8
+
+
+def test_combinatorial_fp32_against_fp64_oracle(orc, ctx):
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(5000, 19, 40.0, 0.75, "dirichlet", 5.0, seed=2)
+    go, vo, do, gd, _, v32, d32 = _pair(orc, ctx, g0.n, g0.src, g0.dst)
+    X0 = gaussian_block(g0.n, 19, 11)
+    # a fixed number of iterations on both sides: FP32 multivectors stall near
+    # relres 1e-3 of this operator's range 2 max d, whose bottom is far below it
+    ro = orc.lobpcg(go, vo, X0, 25, 0.0, diag=do)
+    N = 2 * do.max()
+    for prec in ("fp32", "fp32_bf16gram"):
+        rg = api.lobpcg_solve(ctx, gd, v32, to_dev(X0.astype(np.float32)), 25, 0.0, prec,
+                              diag=d32)
+        assert rg.iterations == 25 and rg.max_relres < 1e-2, (prec, rg.max_relres)
+        th = host(rg.theta)
+        assert np.all(np.isfinite(th)) and th.min() >= -1e-3 * N and th.max() <= N
+        # FP32 multivectors: Ritz values to ~1e-5 of the operator's range
+        assert np.max(np.abs(th - ro.theta)) < 1e-4 * N, (prec, np.max(np.abs(th - ro.theta)))
+
+
+def test_combinatorial_end_to_end_labels(orc, ctx):
+    """Same graph, X0 and draws: labels from each side's own L = D - W solve
+    agree up to a permutation of the cluster ids."""
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(1000, 8, 20.0, 0.8, seed=1)
+    X0 = gaussian_block(g0.n, 8, 1)
+    draws = kmeans_draws(10, 8, 1)
+    go, vo, do, gd, v64, _, _ = _pair(orc, ctx, g0.n, g0.src, g0.dst)
+    ro = orc.lobpcg(go, vo, X0, 30, 1e-4, diag=do)
+    ko = orc.kmeans(ro.X, 8, draws, max_iter=100)
+    rg = api.lobpcg_solve(ctx, gd, v64, to_dev(X0), 30, 1e-4, "fp64", diag=gd.degree)
+    kg = api.kmeans_assign(ctx, rg.X, 8, to_dev(draws.view(np.int64)))
+    lg = host(kg.labels)
+    assert np.array_equal(canonical_labels(lg), canonical_labels(ko.labels))
+    print("PM vs truth (D - W):", partition_scores(g0.truth, lg)["PM"])
