@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")
+    ap.add_argument("--tol", type=float, default=None, help="override the workload's tolerance")
+    ap.add_argument("--maxit", type=int, default=None, help="override the workload's iteration cap")
     ap.add_argument("--laplacian", default="normalized", choices=["normalized", "combinatorial"],
                     help="operator: I - D^-1/2 W D^-1/2 (default) or D - W (relres scaled by "
                          "2 max degree)")
@@ -266,6 +268,10 @@ def main():
     from synth.configs import config, graph_for
 
     cfg = config(args.config)
+    if args.tol is not None:
+        cfg["tol"] = args.tol
+    if args.maxit is not None:
+        cfg["maxit"] = args.maxit
     restarts = args.restarts if args.restarts is not None else cfg["restarts"]
     prec = args.precision or cfg["precision"]
     fp64 = prec == "fp64"
