@@ -83,6 +83,8 @@ def _declare(L):
     L.orc_kmeans.restype = _int
     L.orc_kmeans.argtypes = [_i64, _int, _p, _i64, _int, _int, _int, _p, _p, _int, _p, _p,
                              _p, _p, _p, _p]
+    L.orc_cpqr_labels.restype = _int
+    L.orc_cpqr_labels.argtypes = [_i64, _int, _p, _i64, _p, _p, _p]
     L.orc_row_normalize.restype = None
     L.orc_row_normalize.argtypes = [_i64, _int, _p, _i64, _p]
 
@@ -292,6 +294,24 @@ def kmeans(X, n_clusters, draws=None, restarts=None, max_iter=100, normalize=Tru
                             _ptr(init), int(bool(normalize)), _ptr(labels), _ptr(cent),
                             _ptr(inertia), _ptr(iq), _ptr(br), _ptr(li)), "kmeans")
     return KmeansResult(labels, cent, float(inertia[0]), int(iq[0]), int(br[0]), int(li[0]))
+
+
+@dataclass
+class CpqrResult:
+    pivots: np.ndarray
+    labels: np.ndarray
+    Q: np.ndarray
+
+
+def cpqr_labels(X) -> CpqrResult:
+    """Labels by QR with column pivoting of X' (pivots, polar factor Q, argmax |X Q|)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, k = X.shape
+    piv = np.zeros(k, dtype=np.int32)
+    lab = np.zeros(n, dtype=np.int32)
+    Q = np.zeros((k, k))
+    _check(lib().orc_cpqr_labels(n, k, _ptr(X), k, _ptr(piv), _ptr(lab), _ptr(Q)), "cpqr_labels")
+    return CpqrResult(piv, lab, Q)
 
 
 def row_normalize(X):

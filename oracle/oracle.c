@@ -31,6 +31,8 @@
  *                     Section III; Knyazev 2001 with explicit Gram basis)
  *   orc_kmeans        row normalisation + k-means++ seeding + Lloyd
  *                     (Section II-A names k-means++ as the classic labelling)
+ *   orc_cpqr_labels   labels by QR with column pivoting of the eigenvector
+ *                     block (Section II-A's own labelling)
  */
 #include <math.h>
 #include <stdint.h>
@@ -832,6 +834,129 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     if (lloyd_iters) *lloyd_iters = best_iters;
     free(Y); free(Cc); free(D2); free(pref); free(lab); free(nl); free(cnt); free(rank); free(bs);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cluster labels by QR with column pivoting of X' (Section II-A: the        */
+/* multi-way partition is read off the approximate eigenvectors by a pivoted */
+/* QR; Damle, Minden & Ying, the method it cites).                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * X: n x k row-major (row i holds vertex i's k coordinates), row stride ldx.
+ * 1. Businger-Golub pivoting over the columns of X' (the rows of X):
+ *      res_i = ||x_i||^2 (fma over the coordinates in order);
+ *      step s: p_s = argmax of res_i over the rows not chosen yet (ties: lowest i);
+ *        a_t = q_t . x_{p_s} for t < s (fma over the coordinates in order);
+ *        r_d = x_{p_s, d}, then r_d = fma(-a_t, q_{t,d}, r_d) for t = 0 .. s-1;
+ *        q_s = r / ||r|| (ordered fma sum, IEEE sqrt and division);
+ *        every row: c = q_s . x_i (fma in order), res_i = fma(-c, c, res_i).
+ *      A chosen residual that is not positive is a breakdown (rank < k).
+ * 2. B = the pivot rows (k x k, row s = x_{p_s}).  The orthogonal polar factor
+ *    of B' is Q = B' (B B')^-1/2; with B B' = W diag(l) W' (cyclic Jacobi),
+ *    M = W diag(1/sqrt(l)) W' and Q = B' M (fma sums in index order).
+ * 3. label_i = argmax_j |(X Q)_ij| (fma over the coordinates in order; ties:
+ *    lowest j).
+ * pivots [k], labels [n] and Q (k x k row-major, Q[d*k + j]) are outputs.
+ */
+int orc_cpqr_labels(int64_t n, int k, const double* X, int64_t ldx, int32_t* pivots,
+                    int32_t* labels, double* Qout) {
+    if (n <= 0 || k <= 0 || k > n || ldx < k) return ORC_E_INVAL;
+    int status = ORC_OK;
+    double* res = (double*)malloc(sizeof(double) * (size_t)n);
+    char* chosen = (char*)calloc((size_t)n, 1);
+    double* q = (double*)malloc(sizeof(double) * (size_t)k * k);     /* q_t rows */
+    double* a = (double*)malloc(sizeof(double) * (size_t)k);
+    double* r = (double*)malloc(sizeof(double) * (size_t)k);
+    double* B = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* G = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* W = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* l = (double*)malloc(sizeof(double) * (size_t)k);
+    double* M = (double*)malloc(sizeof(double) * (size_t)k * k);
+    if (!res || !chosen || !q || !a || !r || !B || !G || !W || !l || !M) { status = ORC_E_NOMEM; goto out; }
+    for (int64_t i = 0; i < n; ++i) {
+        const double* x = X + i * ldx;
+        double t = 0.0;
+        for (int d = 0; d < k; ++d) {
+            if (!isfinite(x[d])) { status = ORC_E_NUMERIC; goto out; }
+            t = fma(x[d], x[d], t);
+        }
+        res[i] = t;
+    }
+    for (int st = 0; st < k; ++st) {
+        int64_t p = -1;
+        double best = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            if (!chosen[i] && (p < 0 || res[i] > best)) { p = i; best = res[i]; }
+        if (!(best > 0.0)) { status = ORC_E_BREAKDOWN; goto out; }
+        chosen[p] = 1;
+        pivots[st] = (int32_t)p;
+        const double* xp = X + p * ldx;
+        for (int t = 0; t < st; ++t) {
+            double dot = 0.0;
+            for (int d = 0; d < k; ++d) dot = fma(q[(int64_t)t * k + d], xp[d], dot);
+            a[t] = dot;
+        }
+        for (int d = 0; d < k; ++d) {
+            double v = xp[d];
+            for (int t = 0; t < st; ++t) v = fma(-a[t], q[(int64_t)t * k + d], v);
+            r[d] = v;
+        }
+        double nr2 = 0.0;
+        for (int d = 0; d < k; ++d) nr2 = fma(r[d], r[d], nr2);
+        const double nr = sqrt(nr2);
+        if (!(nr > 0.0)) { status = ORC_E_BREAKDOWN; goto out; }
+        for (int d = 0; d < k; ++d) q[(int64_t)st * k + d] = r[d] / nr;
+        const double* qs = q + (int64_t)st * k;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            const double* x = X + i * ldx;
+            double c = 0.0;
+            for (int d = 0; d < k; ++d) c = fma(qs[d], x[d], c);
+            res[i] = fma(-c, c, res[i]);
+        }
+    }
+    for (int s2 = 0; s2 < k; ++s2)
+        memcpy(B + (int64_t)s2 * k, X + (int64_t)pivots[s2] * ldx, sizeof(double) * (size_t)k);
+    for (int u = 0; u < k; ++u)
+        for (int v = 0; v < k; ++v) {
+            double t = 0.0;
+            for (int d = 0; d < k; ++d) t = fma(B[(int64_t)u * k + d], B[(int64_t)v * k + d], t);
+            G[(int64_t)u * k + v] = t;
+        }
+    status = orc_symeig(k, G, l, W);
+    if (status != ORC_OK) goto out;
+    for (int j = 0; j < k; ++j) {
+        if (!(l[j] > 0.0)) { status = ORC_E_BREAKDOWN; goto out; }
+        l[j] = 1.0 / sqrt(l[j]);
+    }
+    for (int u = 0; u < k; ++u)
+        for (int v = 0; v < k; ++v) {
+            double t = 0.0;
+            for (int j = 0; j < k; ++j) t = fma(W[(int64_t)u * k + j] * l[j], W[(int64_t)v * k + j], t);
+            M[(int64_t)u * k + v] = t;
+        }
+    for (int d = 0; d < k; ++d)
+        for (int j = 0; j < k; ++j) {
+            double t = 0.0;
+            for (int u = 0; u < k; ++u) t = fma(B[(int64_t)u * k + d], M[(int64_t)u * k + j], t);
+            Qout[(int64_t)d * k + j] = t;
+        }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* x = X + i * ldx;
+        int bj = 0;
+        double bv = -1.0;
+        for (int j = 0; j < k; ++j) {
+            double z = 0.0;
+            for (int d = 0; d < k; ++d) z = fma(x[d], Qout[(int64_t)d * k + j], z);
+            if (fabs(z) > bv) { bv = fabs(z); bj = j; }
+        }
+        labels[i] = bj;
+    }
+out:
+    free(res); free(chosen); free(q); free(a); free(r); free(B); free(G); free(W); free(l); free(M);
+    return status;
 }
 
 /* Row normalisation alone (exposed for the tests). */
