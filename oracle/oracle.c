@@ -851,7 +851,9 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
  *        r_d = x_{p_s, d}, then r_d = fma(-a_t, q_{t,d}, r_d) for t = 0 .. s-1;
  *        q_s = r / ||r|| (ordered fma sum, IEEE sqrt and division);
  *        every row: c = q_s . x_i (fma in order), res_i = fma(-c, c, res_i).
- *      A chosen residual that is not positive is a breakdown (rank < k).
+ *      A chosen residual at or below CPQR_RANK_TOL times the first pivot's
+ *      (1e-5 relative in norm, far above the downdates' rounding noise of about
+ *      1e-15) is a breakdown: the block has rank below k.
  * 2. B = the pivot rows (k x k, row s = x_{p_s}).  The orthogonal polar factor
  *    of B' is Q = B' (B B')^-1/2; with B B' = W diag(l) W' (cyclic Jacobi),
  *    M = W diag(1/sqrt(l)) W' and Q = B' M (fma sums in index order).
@@ -859,8 +861,10 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
  *    lowest j).
  * pivots [k], labels [n] and Q (k x k row-major, Q[d*k + j]) are outputs.
  */
+#define CPQR_RANK_TOL 1e-10
 int orc_cpqr_labels(int64_t n, int k, const double* X, int64_t ldx, int32_t* pivots,
                     int32_t* labels, double* Qout) {
+    double floor_res = 0.0;
     if (n <= 0 || k <= 0 || k > n || ldx < k) return ORC_E_INVAL;
     int status = ORC_OK;
     double* res = (double*)malloc(sizeof(double) * (size_t)n);
@@ -888,7 +892,8 @@ int orc_cpqr_labels(int64_t n, int k, const double* X, int64_t ldx, int32_t* piv
         double best = 0.0;
         for (int64_t i = 0; i < n; ++i)
             if (!chosen[i] && (p < 0 || res[i] > best)) { p = i; best = res[i]; }
-        if (!(best > 0.0)) { status = ORC_E_BREAKDOWN; goto out; }
+        if (!(best > floor_res)) { status = ORC_E_BREAKDOWN; goto out; }
+        if (st == 0) floor_res = best * CPQR_RANK_TOL;
         chosen[p] = 1;
         pivots[st] = (int32_t)p;
         const double* xp = X + p * ldx;

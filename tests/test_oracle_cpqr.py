@@ -52,10 +52,19 @@ def test_ideal_blocks_recovered_and_rotation_invariant(orc):
 
 
 def test_rank_deficient_is_breakdown(orc):
-    X = np.random.default_rng(0).standard_normal((100, 5))
-    X[:, 4] = X[:, 0] + X[:, 1]
-    with pytest.raises(orc.OracleError):
-        orc.cpqr_labels(X)
+    """A dependent column leaves only rounding noise (about 1e-15 of ||x||^2)
+    in the downdated residuals: below the rank floor (1e-10 of the first
+    pivot's), a breakdown.  A small but real fifth direction passes."""
+    rng = np.random.default_rng(0)
+    for make in (lambda X: X[:, 0] + X[:, 1], lambda X: X[:, 0] - 2 * X[:, 2],
+                 lambda X: 0.0 * X[:, 3]):
+        X = rng.standard_normal((100, 5))
+        X[:, 4] = make(X)
+        with pytest.raises(orc.OracleError):
+            orc.cpqr_labels(X)
+    X = rng.standard_normal((100, 5))
+    X[:, 4] = X[:, 0] + 1e-3 * X[:, 4]
+    assert len(set(orc.cpqr_labels(X).pivots.tolist())) == 5
 
 
 def test_sbm_eigenvectors_recover_blocks(orc):
