@@ -26,6 +26,7 @@ import json
 import os
 import sys
 import time
+from types import SimpleNamespace
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
@@ -237,6 +238,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")
+    ap.add_argument("--cluster", default="kmeans", choices=["kmeans", "cpqr"],
+                    help="labelling: k-means++ with restarts (default) or QR with column pivoting")
     ap.add_argument("--tol", type=float, default=None, help="override the workload's tolerance")
     ap.add_argument("--maxit", type=int, default=None, help="override the workload's iteration cap")
     ap.add_argument("--laplacian", default="normalized", choices=["normalized", "combinatorial"],
@@ -302,7 +305,11 @@ def main():
             v64, v32, _ = api.laplacian_csr(ctx, gd, fp64, not fp64)
         val = v64 if fp64 else v32
         res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag)
-        km = api.kmeans_assign(ctx, res.X, k, draws, max_iter=100)
+        if args.cluster == "cpqr":
+            cq = api.cpqr_labels(ctx, res.X)
+            km = SimpleNamespace(labels=cq.labels, lloyd_iterations=None)
+        else:
+            km = api.kmeans_assign(ctx, res.X, k, draws, max_iter=100)
         return gd, res, km
 
     for w in range(args.warmup):
@@ -355,8 +362,9 @@ def main():
                                 f"mean_degree={cfg['mean_degree']} intra={cfg['intra']} "
                                 f"sizes={cfg['sizes']}({cfg['alpha']}); LOBPCG k={k} "
                                 f"maxit={cfg['maxit']} tol={cfg['tol']} {prec}"
-                                f"{'; Laplacian D - W' if comb else ''}; k-means "
-                                f"restarts={restarts}"),
+                                f"{'; Laplacian D - W' if comb else ''}; "
+                                + ("labels by QR with column pivoting" if args.cluster == "cpqr"
+                                   else f"k-means restarts={restarts}")),
                    "name": args.config, "n": n, "nnz": gd.nnz, "k": k},
         "lobpcg_iterations": res.iterations,
         "kmeans_lloyd_iterations": km.lloyd_iterations,

@@ -340,6 +340,30 @@ sc_status sc_ctx_profile(sc_ctx* ctx, int kind, int64_t* launches, double* total
 sc_status sc_ctx_profile_reset(sc_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Cluster labels by QR with column pivoting of the eigenvector block
+ * (Section II-A: the paper reads its multi-way partition off the approximate
+ * eigenvectors with a pivoted QR, the method of Damle, Minden & Ying).
+ * X: n x k (ldx >= k, float64, or float32 with x_fp32 != 0), device, rows =
+ * vertices; 1 <= k <= min(n, 256), n < 2^31.
+ *   1. pivots: Businger-Golub over the rows of X.  res_i = ||x_i||^2; step s
+ *      takes p_s = argmax res_i over rows not yet chosen (ties: lowest i),
+ *      a_t = q_t . x_{p_s} (t < s), r = x_{p_s} - sum_t a_t q_t, q_s =
+ *      r / ||r||, then res_i = fma(-c, c, res_i) with c = q_s . x_i; every dot
+ *      product is the ordered fma chain over the coordinates;
+ *   2. Q = orthogonal polar factor of B' (B = pivot rows): B B' = W diag(l) W',
+ *      Q = B' W diag(1/sqrt l) W';
+ *   3. labels_i = argmax_j |(X Q)_ij| (ties: lowest j).
+ * pivots int32 [k], labels int32 [n], Q float64 k x k row-major (Q[d*k+j]),
+ * all device outputs.  Synchronises.  A block of rank below k (a chosen
+ * squared residual at or below 1e-10 of the first pivot's, i.e. 1e-5 relative
+ * in norm, or an eigenvalue of B B' that is not positive) is SC_E_BREAKDOWN;
+ * NaN or Inf in X is SC_E_NUMERIC.
+ * ------------------------------------------------------------------------ */
+sc_status sc_cpqr_workspace(sc_ctx* ctx, int64_t n, int k, int x_fp32, size_t* bytes);
+sc_status sc_cpqr_labels(sc_ctx* ctx, int64_t n, int k, const void* X, int64_t ldx, int x_fp32,
+                         int32_t* pivots, int32_t* labels, double* Q, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
  * Dense FP64 symmetric eigensolver used inside the Rayleigh-Ritz step,
  * exposed for testing: the k smallest eigenpairs of the m x m symmetric A
  * (row-major, device).  w float64 [k] ascending, V float64 m x k row-major

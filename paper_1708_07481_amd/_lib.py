@@ -82,6 +82,8 @@ SIGNATURES = {
     "sc_ctx_set_profiling": (_int, [_p, C.c_uint]),
     "sc_ctx_profile": (_int, [_p, _int, C.POINTER(_i64), C.POINTER(_dbl)]),
     "sc_ctx_profile_reset": (_int, [_p]),
+    "sc_cpqr_workspace": (_int, [_p, _i64, _int, _int, C.POINTER(_size)]),
+    "sc_cpqr_labels": (_int, [_p, _i64, _int, _p, _i64, _int, _p, _p, _p, _p, _size]),
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
 }

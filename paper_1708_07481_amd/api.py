@@ -272,6 +272,31 @@ def kmeans_assign(ctx: Context, X: torch.Tensor, n_clusters: int, draws: torch.T
     return KmeansResult(labels, cent, inertia.value, iq.value, br.value, its.value)
 
 
+@dataclass
+class CpqrResult:
+    pivots: torch.Tensor
+    labels: torch.Tensor
+    Q: torch.Tensor
+
+
+def cpqr_labels(ctx: Context, X: torch.Tensor, ws: torch.Tensor | None = None) -> CpqrResult:
+    """Labels by QR with column pivoting of X' (rows of X = vertices)."""
+    n, k = X.shape
+    if X.dtype not in (torch.float64, torch.float32) or X.stride(1) != 1:
+        raise TypeError("X must be float64 or float32 with unit column stride")
+    fp32 = int(X.dtype == torch.float32)
+    nb = C.c_size_t()
+    ctx.check(lib().sc_cpqr_workspace(ctx.handle, n, k, fp32, C.byref(nb)), "sc_cpqr_workspace")
+    if ws is None or ws.numel() < nb.value:
+        ws = ctx.workspace(nb.value)
+    piv = torch.empty(k, dtype=torch.int32, device=X.device)
+    lab = torch.empty(n, dtype=torch.int32, device=X.device)
+    Q = torch.empty((k, k), dtype=torch.float64, device=X.device)
+    ctx.check(lib().sc_cpqr_labels(ctx.handle, n, k, _ptr(X), X.stride(0), fp32, _ptr(piv),
+                                   _ptr(lab), _ptr(Q), _ptr(ws), nb.value), "sc_cpqr_labels")
+    return CpqrResult(piv, lab, Q)
+
+
 def symeig(ctx: Context, A: torch.Tensor, k: int, ws: torch.Tensor | None = None):
     m = A.shape[0]
     nb = C.c_size_t()

@@ -1,0 +1,98 @@
+"""GPU parity: labels by QR with column pivoting (Section II-A) against the
+oracle.  Bar: pivots bit-exact (every pivot is an argmax over residuals that
+both sides compute with the same ordered fma chains); the polar factor Q to
+FP64 rounding (the two sides factor B B' with different eigensolvers); labels
+identical wherever the oracle's two largest |(XQ)_ij| differ by more than
+1e-9 of the row's scale, and one of the two top clusters elsewhere."""
+import numpy as np
+import pytest
+
+from paper_1708_07481_amd.metrics import partition_scores
+from synth import dcsbm, gaussian_block
+from tests.gpu_common import gpu_ctx, host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return gpu_ctx()
+
+
+def _check_labels(X, ro, lg):
+    Z = np.abs(X @ ro.Q)
+    top = np.sort(Z, axis=1)
+    margin = top[:, -1] - top[:, -2]
+    clear = margin > 1e-9 * np.maximum(top[:, -1], 1e-300)
+    assert np.array_equal(lg[clear], ro.labels[clear]), np.flatnonzero(lg[clear] != ro.labels[clear])[:5]
+    two = np.argsort(Z, axis=1)[:, -2:]
+    amb = ~clear
+    assert np.all((lg[amb] == two[amb, 0]) | (lg[amb] == two[amb, 1]))
+
+
+def _compare(orc, ctx, X64, Xdev):
+    from paper_1708_07481_amd import api
+    ro = orc.cpqr_labels(X64)
+    rg = api.cpqr_labels(ctx, Xdev)
+    assert np.array_equal(host(rg.pivots), ro.pivots)
+    assert np.allclose(host(rg.Q), ro.Q, atol=1e-9, rtol=0)
+    _check_labels(X64, ro, host(rg.labels))
+    return ro, rg
+
+
+@pytest.mark.parametrize("n,k,seed", [(40, 3, 0), (500, 8, 1), (3001, 19, 2), (20000, 44, 3),
+                                      (5000, 160, 4), (300, 256, 5)])
+def test_cpqr_random_fp64(orc, ctx, n, k, seed):
+    X = np.random.default_rng(seed).standard_normal((n, k))
+    _compare(orc, ctx, X, to_dev(X))
+
+
+def test_cpqr_fp32_strided(orc, ctx):
+    rng = np.random.default_rng(9)
+    n, k = 7001, 24
+    X32 = rng.standard_normal((n, k)).astype(np.float32)
+    big = np.zeros((n, k + 7), np.float32)
+    big[:, :k] = X32
+    Xd = to_dev(big)[:, :k]
+    _compare(orc, ctx, X32.astype(np.float64), Xd)
+
+
+def test_cpqr_ties_take_lowest_index(orc, ctx):
+    """Duplicated rows give exactly equal residuals; both sides take the
+    lowest index, and a duplicate is never chosen twice (its residual drops
+    to zero)."""
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((600, 6))
+    X[[17, 250, 431]] = 3.0 * X[5]
+    X[[90, 91]] = 2.5 * X[300]
+    ro, rg = _compare(orc, ctx, X, to_dev(X))
+    piv = host(rg.pivots)
+    assert len(set(piv.tolist())) == 6
+
+
+@pytest.mark.parametrize("k", [8, 19])
+def test_cpqr_on_sbm_eigenvectors(orc, ctx, k):
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(1000 if k == 8 else 5000, k, 20.0 if k == 8 else 40.0, 0.8,
+               "equal" if k == 8 else "dirichlet", 5.0, seed=1)
+    g = orc.graph_build(g0.n, g0.src, g0.dst)
+    val, _ = orc.laplacian(g)
+    X = orc.lobpcg(g, val, gaussian_block(g0.n, k, 1), 60, 1e-8).X
+    ro, rg = _compare(orc, ctx, X, to_dev(X))
+    pm = partition_scores(g0.truth, host(rg.labels))["PM"]
+    print("cpqr PM", k, pm)
+    assert pm > 0.95
+
+
+def test_cpqr_errors(ctx):
+    from paper_1708_07481_amd import api
+    X = np.random.default_rng(0).standard_normal((100, 5))
+    X[:, 4] = X[:, 0] - 2 * X[:, 2]
+    with pytest.raises(api.SpectralError):
+        api.cpqr_labels(ctx, to_dev(X))
+    Y = np.random.default_rng(1).standard_normal((50, 4))
+    Y[7, 2] = np.nan
+    with pytest.raises(api.SpectralError):
+        api.cpqr_labels(ctx, to_dev(Y))
+    with pytest.raises(api.SpectralError):
+        api.cpqr_labels(ctx, to_dev(np.ones((3, 4))))      # k > n

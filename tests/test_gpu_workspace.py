@@ -87,3 +87,20 @@ def test_symeig_workspace_independent():
     assert np.array_equal(host(r[0][0]), host(r[1][0]))
     assert np.array_equal(host(r[0][1]), host(r[1][1]))
     assert np.all(np.isfinite(host(r[1][1])))
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_cpqr_workspace_independent(graph, fp32):
+    ctx, g0, g = graph
+    X = np.random.default_rng(3).standard_normal((g0.n, 12))
+    Xd = to_dev(X.astype(np.float32) if fp32 else X)
+    import ctypes as C
+    from paper_1708_07481_amd._lib import lib
+    nb = C.c_size_t()
+    ctx.check(lib().sc_cpqr_workspace(ctx.handle, g0.n, 12, int(fp32), C.byref(nb)), "ws")
+    out = []
+    for byte in (0, 0xFF):
+        r = api.cpqr_labels(ctx, Xd, ws=_ws(nb.value, byte))
+        out.append((host(r.pivots), host(r.labels), host(r.Q)))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
