@@ -85,6 +85,8 @@ def _declare(L):
                              _p, _p, _p, _p]
     L.orc_cpqr_labels.restype = _int
     L.orc_cpqr_labels.argtypes = [_i64, _int, _p, _i64, _p, _p, _p]
+    L.orc_eigengap.restype = _int
+    L.orc_eigengap.argtypes = [_int, _p, _dbl, C.POINTER(_dbl)]
     L.orc_row_normalize.restype = None
     L.orc_row_normalize.argtypes = [_i64, _int, _p, _i64, _p]
 
@@ -312,6 +314,14 @@ def cpqr_labels(X) -> CpqrResult:
     Q = np.zeros((k, k))
     _check(lib().orc_cpqr_labels(n, k, _ptr(X), k, _ptr(piv), _ptr(lab), _ptr(Q)), "cpqr_labels")
     return CpqrResult(piv, lab, Q)
+
+
+def eigengap(theta, frac=0.5):
+    """(count, ratio): clusters below the first increment >= frac * largest."""
+    t = np.ascontiguousarray(theta, dtype=np.float64)
+    r = C.c_double()
+    c = lib().orc_eigengap(len(t), _ptr(t), frac, C.byref(r))
+    return c, r.value
 
 
 def row_normalize(X):

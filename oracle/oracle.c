@@ -33,6 +33,7 @@
  *                     (Section II-A names k-means++ as the classic labelling)
  *   orc_cpqr_labels   labels by QR with column pivoting of the eigenvector
  *                     block (Section II-A's own labelling)
+ *   orc_eigengap      number of clusters from the gap in the eigenvalues
  */
 #include <math.h>
 #include <stdint.h>
@@ -962,6 +963,45 @@ int orc_cpqr_labels(int64_t n, int k, const double* X, int64_t ldx, int32_t* piv
 out:
     free(res); free(chosen); free(q); free(a); free(r); free(B); free(G); free(W); free(l); free(M);
     return status;
+}
+
+/*
+ * Number of clusters from the gap in the smallest eigenvalues (Section II-A:
+ * the first significantly large increment; the count of eigenvalues below it).
+ * theta ascending, k >= 2.  Increments g_j = theta_{j+1} - theta_j,
+ * j = 0 .. k-2; the gap is the first j with g_j >= frac * max_j' g_j' (frac in
+ * (0, 1]); the count is j + 1.  *ratio (optional) = g_j / the median increment,
+ * a confidence figure (large: a clear gap).  k == 1 gives 1.
+ */
+int orc_eigengap(int k, const double* theta, double frac, double* ratio) {
+    if (k <= 1) { if (ratio) *ratio = 0.0; return k; }
+    double gmax = 0.0;
+    for (int j = 0; j + 1 < k; ++j) {
+        const double g = theta[j + 1] - theta[j];
+        if (g > gmax) gmax = g;
+    }
+    int jj = k - 2;
+    for (int j = 0; j + 1 < k; ++j)
+        if (theta[j + 1] - theta[j] >= frac * gmax) { jj = j; break; }
+    if (ratio) {
+        /* median increment (insertion sort of a copy) */
+        double* g = (double*)malloc(sizeof(double) * (size_t)(k - 1));
+        if (g) {
+            for (int j = 0; j + 1 < k; ++j) g[j] = theta[j + 1] - theta[j];
+            for (int a = 1; a < k - 1; ++a) {
+                double v = g[a];
+                int b = a - 1;
+                while (b >= 0 && g[b] > v) { g[b + 1] = g[b]; --b; }
+                g[b + 1] = v;
+            }
+            const double med = (k - 1) % 2 ? g[(k - 1) / 2] : 0.5 * (g[(k - 1) / 2 - 1] + g[(k - 1) / 2]);
+            *ratio = med > 0.0 ? (theta[jj + 1] - theta[jj]) / med : INFINITY;
+            free(g);
+        } else {
+            *ratio = 0.0;
+        }
+    }
+    return jj + 1;
 }
 
 /* Row normalisation alone (exposed for the tests). */

@@ -74,3 +74,27 @@ def test_sbm_eigenvectors_recover_blocks(orc):
     res = orc.lobpcg(g, val, gaussian_block(g0.n, 8, 1), 40, 1e-6)
     r = orc.cpqr_labels(res.X)
     assert partition_scores(g0.truth, r.labels)["PM"] > 0.97
+
+
+def test_eigengap_hand_examples(orc):
+    assert orc.eigengap([0.0, 0.1, 0.12, 0.9, 0.95])[0] == 3
+    # the first increment at least half the largest one, not the largest
+    assert orc.eigengap([0.0, 0.5, 0.6, 1.0])[0] == 1
+    assert orc.eigengap([0.0, 0.1, 0.2, 0.3])[0] == 1          # no gap: the first increment
+    assert orc.eigengap([0.7])[0] == 1
+    c, ratio = orc.eigengap([0.0, 0.01, 0.02, 0.03, 0.5, 0.52, 0.54])
+    assert c == 4 and ratio > 20
+
+
+def test_eigengap_counts_components_and_blocks(orc):
+    from tests import graphs
+    n, src, dst = graphs.cliques([9, 11, 14, 17, 20])
+    g = orc.graph_build(n, src, dst)
+    val, _ = orc.laplacian(g)
+    ev = np.linalg.eigvalsh(orc.dense_laplacian(g, val))
+    assert orc.eigengap(ev[:8])[0] == 5
+    gg = dcsbm(400, 4, 24.0, 0.9, seed=2)
+    g = orc.graph_build(gg.n, gg.src, gg.dst)
+    val, _ = orc.laplacian(g)
+    ev = np.linalg.eigvalsh(orc.dense_laplacian(g, val))
+    assert orc.eigengap(ev[:7])[0] == 4
