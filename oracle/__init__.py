@@ -316,11 +316,12 @@ def cpqr_labels(X) -> CpqrResult:
     return CpqrResult(piv, lab, Q)
 
 
-def eigengap(theta, frac=0.5):
-    """(count, ratio): clusters below the first increment >= frac * largest."""
+def eigengap(theta, sig=10.0):
+    """(count, ratio): clusters below the first increment more than sig times
+    the mean of the increments before it (else below the largest)."""
     t = np.ascontiguousarray(theta, dtype=np.float64)
     r = C.c_double()
-    c = lib().orc_eigengap(len(t), _ptr(t), frac, C.byref(r))
+    c = lib().orc_eigengap(len(t), _ptr(t), sig, C.byref(r))
     return c, r.value
 
 

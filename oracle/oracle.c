@@ -968,21 +968,31 @@ out:
 /*
  * Number of clusters from the gap in the smallest eigenvalues (Section II-A:
  * the first significantly large increment; the count of eigenvalues below it).
- * theta ascending, k >= 2.  Increments g_j = theta_{j+1} - theta_j,
- * j = 0 .. k-2; the gap is the first j with g_j >= frac * max_j' g_j' (frac in
- * (0, 1]); the count is j + 1.  *ratio (optional) = g_j / the median increment,
- * a confidence figure (large: a clear gap).  k == 1 gives 1.
+ * theta ascending.  Increments g_j = theta_{j+1} - theta_j, j = 0 .. k-2; the
+ * gap is the first j >= 1 with g_j > 1e-8 (theta_{k-1} - theta_0) (above the
+ * rounding noise of eigenvalues that are equal in exact arithmetic) and
+ * g_j > sig * (g_0 + .. + g_{j-1}) / j (significantly larger than the
+ * increments before it); if none, the largest
+ * increment (the first of equals).  The count is j + 1; k == 1 gives 1.
+ * *ratio (optional) = g_j / the median increment, a confidence figure.
  */
-int orc_eigengap(int k, const double* theta, double frac, double* ratio) {
+int orc_eigengap(int k, const double* theta, double sig, double* ratio) {
     if (k <= 1) { if (ratio) *ratio = 0.0; return k; }
-    double gmax = 0.0;
-    for (int j = 0; j + 1 < k; ++j) {
+    int jj = -1;
+    const double tiny = 1e-8 * (theta[k - 1] - theta[0]);
+    double sum = theta[1] - theta[0];
+    for (int j = 1; j + 1 < k; ++j) {
         const double g = theta[j + 1] - theta[j];
-        if (g > gmax) gmax = g;
+        if (g > tiny && g > sig * (sum / (double)j)) { jj = j; break; }
+        sum += g;
     }
-    int jj = k - 2;
-    for (int j = 0; j + 1 < k; ++j)
-        if (theta[j + 1] - theta[j] >= frac * gmax) { jj = j; break; }
+    if (jj < 0) {
+        double gmax = -INFINITY;
+        for (int j = 0; j + 1 < k; ++j) {
+            const double g = theta[j + 1] - theta[j];
+            if (g > gmax) { gmax = g; jj = j; }
+        }
+    }
     if (ratio) {
         /* median increment (insertion sort of a copy) */
         double* g = (double*)malloc(sizeof(double) * (size_t)(k - 1));

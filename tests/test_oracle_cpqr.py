@@ -77,10 +77,12 @@ def test_sbm_eigenvectors_recover_blocks(orc):
 
 
 def test_eigengap_hand_examples(orc):
-    assert orc.eigengap([0.0, 0.1, 0.12, 0.9, 0.95])[0] == 3
-    # the first increment at least half the largest one, not the largest
+    assert orc.eigengap([0.0, 0.1, 0.12, 0.9, 0.95])[0] == 3     # 0.78 > 10 * 0.06
+    # the trivial eigenvalue's own increment is not a gap when a larger one follows
+    assert orc.eigengap([0.0, 0.24, 0.245, 0.25, 0.26, 0.7])[0] == 5
+    # no increment stands out: the largest one (first of equals)
     assert orc.eigengap([0.0, 0.5, 0.6, 1.0])[0] == 1
-    assert orc.eigengap([0.0, 0.1, 0.2, 0.3])[0] == 1          # no gap: the first increment
+    assert orc.eigengap([0.0, 0.1, 0.2, 0.3])[0] == 1
     assert orc.eigengap([0.7])[0] == 1
     c, ratio = orc.eigengap([0.0, 0.01, 0.02, 0.03, 0.5, 0.52, 0.54])
     assert c == 4 and ratio > 20
