@@ -360,6 +360,20 @@ sc_status sc_ctx_profile_reset(sc_ctx* ctx);
  * NaN or Inf in X is SC_E_NUMERIC.
  * ------------------------------------------------------------------------ */
 sc_status sc_cpqr_workspace(sc_ctx* ctx, int64_t n, int k, int x_fp32, size_t* bytes);
+
+/*
+ * Number of clusters from the gap in the smallest eigenvalues (Section II-A:
+ * the count of eigenvalues below the first significantly large increment).
+ * theta float64 [k] ascending (device, e.g. the Ritz values of a solve with
+ * k above the expected count), 1 <= k <= 256.  With g_j = theta_{j+1} -
+ * theta_j, the gap is the first j >= 1 with g_j > 1e-8 (theta_{k-1} - theta_0)
+ * and g_j > sig * mean(g_0 .. g_{j-1}) (sig > 0, e.g. 10), else the largest
+ * g_j (first of equals);
+ * count (int32, device, out) = j + 1 (1 when k == 1); ratio (float64, device,
+ * out) = g_j / median(g), large for a clear gap.  No synchronisation.
+ */
+sc_status sc_eigengap(sc_ctx* ctx, int k, const double* theta, double sig, int* count,
+                      double* ratio);
 sc_status sc_cpqr_labels(sc_ctx* ctx, int64_t n, int k, const void* X, int64_t ldx, int x_fp32,
                          int32_t* pivots, int32_t* labels, double* Q, void* ws, size_t ws_bytes);
 

@@ -84,6 +84,7 @@ SIGNATURES = {
     "sc_ctx_profile_reset": (_int, [_p]),
     "sc_cpqr_workspace": (_int, [_p, _i64, _int, _int, C.POINTER(_size)]),
     "sc_cpqr_labels": (_int, [_p, _i64, _int, _p, _i64, _int, _p, _p, _p, _p, _size]),
+    "sc_eigengap": (_int, [_p, _int, _p, _dbl, _p, _p]),
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
 }

@@ -297,6 +297,18 @@ def cpqr_labels(ctx: Context, X: torch.Tensor, ws: torch.Tensor | None = None) -
     return CpqrResult(piv, lab, Q)
 
 
+def eigengap(ctx: Context, theta: torch.Tensor, sig: float = 10.0):
+    """(count, ratio): number of Ritz values below the first increment more
+    than sig times the mean of the ones before it (else below the largest),
+    and that increment over the median one."""
+    k = theta.numel()
+    cnt = torch.empty(1, dtype=torch.int32, device=theta.device)
+    ratio = torch.empty(1, dtype=torch.float64, device=theta.device)
+    ctx.check(lib().sc_eigengap(ctx.handle, k, _ptr(theta), sig, _ptr(cnt), _ptr(ratio)),
+              "sc_eigengap")
+    return int(cnt.item()), float(ratio.item())
+
+
 def symeig(ctx: Context, A: torch.Tensor, k: int, ws: torch.Tensor | None = None):
     m = A.shape[0]
     nb = C.c_size_t()

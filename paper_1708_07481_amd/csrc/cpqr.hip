@@ -276,6 +276,55 @@ k_cpqr_labels(int64_t n, int k, int kpad, const TT* __restrict__ Xt, const doubl
     labels[i] = bj;
 }
 
+// number of clusters from the gap in the ascending Ritz values (one thread):
+// the first increment g_j (j >= 1) above 1e-8 of the spread theta_{k-1} -
+// theta_0 (the rounding noise of equal eigenvalues) and above sig times the
+// mean of the increments before it, else the largest increment; ratio = that
+// increment over the median increment
+__global__ void k_eigengap(int k, const double* __restrict__ theta, double sig,
+                           int* __restrict__ count, double* __restrict__ ratio) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (k <= 1) {
+        *count = k;
+        *ratio = 0.0;
+        return;
+    }
+    double g[CP_MAXK];
+    for (int j = 0; j + 1 < k; ++j) g[j] = theta[j + 1] - theta[j];
+    int jj = -1;
+    const double tiny = 1e-8 * (theta[k - 1] - theta[0]);
+    double sum = g[0];
+    for (int j = 1; j + 1 < k; ++j) {
+        if (g[j] > tiny && g[j] > sig * (sum / (double)j)) {
+            jj = j;
+            break;
+        }
+        sum += g[j];
+    }
+    if (jj < 0) {
+        double gmax = -INFINITY;
+        for (int j = 0; j + 1 < k; ++j)
+            if (g[j] > gmax) {
+                gmax = g[j];
+                jj = j;
+            }
+    }
+    const double gap = g[jj];
+    for (int a = 1; a < k - 1; ++a) {            // insertion sort for the median
+        const double v = g[a];
+        int b = a - 1;
+        while (b >= 0 && g[b] > v) {
+            g[b + 1] = g[b];
+            --b;
+        }
+        g[b + 1] = v;
+    }
+    const int m = k - 1;
+    const double med = m % 2 ? g[m / 2] : 0.5 * (g[m / 2 - 1] + g[m / 2]);
+    *count = jj + 1;
+    *ratio = med > 0.0 ? gap / med : INFINITY;
+}
+
 int cp_kpad(int k) { return (int)ceil_div(k, CP_JB) * CP_JB; }
 
 struct CpWs {
@@ -381,4 +430,16 @@ extern "C" sc_status sc_cpqr_labels(sc_ctx* ctx, int64_t n, int k, const void* X
     if (x_fp32)
         return cp_run<float>(ctx, n, k, static_cast<const float*>(X), ldx, pivots, labels, Q, w);
     return cp_run<double>(ctx, n, k, static_cast<const double*>(X), ldx, pivots, labels, Q, w);
+}
+
+extern "C" sc_status sc_eigengap(sc_ctx* ctx, int k, const double* theta, double sig, int* count,
+                                 double* ratio) {
+    if (!ctx) return SC_E_INVAL;
+    if (k <= 0 || k > CP_MAXK || !(sig > 0.0))
+        return sc_fail(ctx, SC_E_INVAL, "eigengap: need 0 < k <= %d and sig > 0", CP_MAXK);
+    if (!theta || !count || !ratio) return sc_fail(ctx, SC_E_INVAL, "eigengap: null pointer argument");
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_eigengap, dim3(1), dim3(64), 0, ctx->stream, k, theta, sig, count, ratio);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
 }

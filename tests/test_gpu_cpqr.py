@@ -96,3 +96,32 @@ def test_cpqr_errors(ctx):
         api.cpqr_labels(ctx, to_dev(Y))
     with pytest.raises(api.SpectralError):
         api.cpqr_labels(ctx, to_dev(np.ones((3, 4))))      # k > n
+
+
+@pytest.mark.parametrize("theta", [[0.0, 0.1, 0.12, 0.9, 0.95], [0.0, 0.5, 0.6, 1.0], [0.7],
+                                   [0.0, 0.1, 0.2, 0.3], [0.0, 0.01, 0.02, 0.03, 0.5, 0.52, 0.54]])
+def test_eigengap_matches_oracle(orc, ctx, theta):
+    from paper_1708_07481_amd import api
+    c, ratio = api.eigengap(ctx, to_dev(np.array(theta)))
+    co, ro = orc.eigengap(theta)
+    assert c == co
+    assert ratio == ro or (np.isinf(ratio) and np.isinf(ro))
+
+
+def test_eigengap_then_cpqr_on_sbm(orc, ctx):
+    """Solve with l = B + 3 columns, count the clusters below the Ritz values'
+    gap, then label with CPQR on the first `count` columns (the paper's own
+    clustering path, Section II-A)."""
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(5000, 19, 40.0, 0.75, "dirichlet", 5.0, seed=2)
+    gd = api.graph_build(ctx, g0.n, to_dev(g0.src), to_dev(g0.dst))
+    v64, _, _ = api.laplacian_csr(ctx, gd)
+    r = api.lobpcg_solve(ctx, gd, v64, to_dev(gaussian_block(g0.n, 22, 1)), 60, 1e-2, "fp64")
+    c, ratio = api.eigengap(ctx, r.theta)
+    co, ro = orc.eigengap(host(r.theta))
+    assert (c, ratio) == (co, ro)
+    assert c == 19 and ratio > 5, (c, ratio)
+    lab = host(api.cpqr_labels(ctx, r.X[:, :c]).labels)
+    pm = partition_scores(g0.truth, lab)["PM"]
+    print("eigengap", c, "ratio", ratio, "PM", pm)
+    assert pm > 0.95
