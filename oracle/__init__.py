@@ -54,7 +54,7 @@ _dbl = C.c_double
 
 class LobpcgOpts(C.Structure):
     _fields_ = [("k", _int), ("maxit", _int), ("tol", _dbl), ("lock_tol", _dbl),
-                ("chol_tol", _dbl), ("op_norm", _dbl)]
+                ("chol_tol", _dbl), ("op_norm", _dbl), ("k_conv", _int)]
 
 
 class LobpcgInfo(C.Structure):
@@ -230,7 +230,7 @@ def op_norm_bound(diag) -> float:
 
 
 def lobpcg(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL,
-           diag=None) -> LobpcgResult:
+           diag=None, k_conv=0) -> LobpcgResult:
     """Smallest-k eigenpairs of L by block LOBPCG without preconditioning
     (diag None: the normalised Laplacian; else L = diag + offdiag(val))."""
     X0 = np.ascontiguousarray(X0, dtype=np.float64)
@@ -239,7 +239,7 @@ def lobpcg(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL
     theta = np.zeros(k)
     rh = np.zeros((maxit + 1, k))
     th = np.zeros((maxit + 1, k))
-    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol, op_norm_bound(diag))
+    o = LobpcgOpts(k, maxit, tol, lock_tol, chol_tol, op_norm_bound(diag), k_conv)
     info = LobpcgInfo()
     v = np.ascontiguousarray(val, dtype=np.float64)
     d = None if diag is None else np.ascontiguousarray(diag, dtype=np.float64)

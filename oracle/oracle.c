@@ -473,6 +473,8 @@ typedef struct {
     double lock_tol;   /* columns with relres_j <= lock_tol leave the W block */
     double chol_tol;   /* relative pivot floor of every Cholesky */
     double op_norm;    /* upper bound of ||L|| scaling the relative residual (0: 2) */
+    int k_conv;        /* the convergence test covers columns 0 .. k_conv-1 (0: all k);
+                          a block wider than the wanted pairs (Section IV: l > k) */
 } orc_lobpcg_opts;
 
 typedef struct {
@@ -617,9 +619,10 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
         }
         double mx = 0.0;
         int all_locked = 1;
+        const int kc = (o->k_conv > 0 && o->k_conv < k) ? o->k_conv : k;
         for (int j = 0; j < k; ++j) {
             if (!isfinite(relres[j])) { status = ORC_E_NUMERIC; goto out; }
-            if (relres[j] > mx) mx = relres[j];
+            if (j < kc && relres[j] > mx) mx = relres[j];
             if (relres[j] > o->lock_tol) all_locked = 0;
         }
         if (relres_hist) for (int j = 0; j < k; ++j) relres_hist[(int64_t)t * k + j] = relres[j];

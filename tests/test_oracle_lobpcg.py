@@ -179,3 +179,22 @@ def test_sbm_recovers_blocks(orc):
     assert r.max_relres < 1e-2
     km = orc.kmeans(r.X, 8, kmeans_draws(10, 8, 1))
     assert partition_scores(gg.truth, km.labels)["PM"] > 0.99
+
+
+def test_wider_block_converges_on_the_leading_columns(orc, sbm_small):
+    """l = k + 2 columns with the convergence test on the first k (Section IV
+    uses a block slightly wider than the clusters): the solve stops as soon as
+    the k wanted pairs meet the tolerance, no later than the full test, and
+    those k Ritz values are the dense ones."""
+    gg, g, val, dis, L = sbm_small
+    ev = np.linalg.eigvalsh(L)
+    X0 = gaussian_block(gg.n, 6, 21)
+    full = orc.lobpcg(g, val, X0, 300, 1e-9)
+    lead = orc.lobpcg(g, val, X0, 300, 1e-9, k_conv=4)
+    assert lead.converged and full.converged
+    assert lead.iterations <= full.iterations
+    assert np.all(lead.relres_hist[-1][:4] <= 1e-9)
+    assert lead.max_relres == lead.relres_hist[-1][:4].max()
+    assert np.allclose(lead.theta[:4], ev[:4], atol=1e-12)
+    # identical iterates up to the earlier stop
+    assert np.array_equal(lead.theta_hist, full.theta_hist[: lead.iterations + 1])
