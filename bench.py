@@ -240,6 +240,10 @@ def main():
                     help="override the workload's precision")
     ap.add_argument("--cluster", default="kmeans", choices=["kmeans", "cpqr"],
                     help="labelling: k-means++ with restarts (default) or QR with column pivoting")
+    ap.add_argument("--extra-cols", type=int, default=0,
+                    help="LOBPCG block of k + E columns, stopping test and labels on the first k")
+    ap.add_argument("--lock-tol", type=float, default=0.0,
+                    help="soft locking: W columns with relres at or below this leave the basis")
     ap.add_argument("--tol", type=float, default=None, help="override the workload's tolerance")
     ap.add_argument("--maxit", type=int, default=None, help="override the workload's iteration cap")
     ap.add_argument("--laplacian", default="normalized", choices=["normalized", "combinatorial"],
@@ -252,8 +256,8 @@ def main():
                     help="after the timed steps, run a plain 512 MiB device copy three times "
                          "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
-    if args.laplacian == "combinatorial" and args.compare:
-        ap.error("--compare runs the normalised Laplacian only")
+    if args.compare and (args.laplacian == "combinatorial" or args.extra_cols or args.lock_tol):
+        ap.error("--compare runs the default operator, block width and locking only")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs a single solve per GPU and has "
@@ -283,7 +287,8 @@ def main():
     t = time.perf_counter()
     g0 = graph_for(args.config, seed=1)
     log(f"graph: m={g0.m} in {time.perf_counter() - t:.1f} s")
-    X0h = gaussian_block(n, k, 1)
+    kb = k + args.extra_cols
+    X0h = gaussian_block(n, kb, 1)
     draws_h = kmeans_draws(restarts, k, 1)
 
     dev = torch.device("cuda:0")
@@ -304,12 +309,14 @@ def main():
         else:
             v64, v32, _ = api.laplacian_csr(ctx, gd, fp64, not fp64)
         val = v64 if fp64 else v32
-        res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag)
+        res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag,
+                               lock_tol=args.lock_tol, k_conv=k if kb > k else 0)
+        Xk = res.X[:, :k]
         if args.cluster == "cpqr":
-            cq = api.cpqr_labels(ctx, res.X)
+            cq = api.cpqr_labels(ctx, Xk)
             km = SimpleNamespace(labels=cq.labels, lloyd_iterations=None)
         else:
-            km = api.kmeans_assign(ctx, res.X, k, draws, max_iter=100)
+            km = api.kmeans_assign(ctx, Xk, k, draws, max_iter=100)
         return gd, res, km
 
     for w in range(args.warmup):
@@ -362,6 +369,8 @@ def main():
                                 f"mean_degree={cfg['mean_degree']} intra={cfg['intra']} "
                                 f"sizes={cfg['sizes']}({cfg['alpha']}); LOBPCG k={k} "
                                 f"maxit={cfg['maxit']} tol={cfg['tol']} {prec}"
+                                f"{f' block {kb}' if kb > k else ''}"
+                                f"{f' lock_tol={args.lock_tol}' if args.lock_tol > 0 else ''}"
                                 f"{'; Laplacian D - W' if comb else ''}; "
                                 + ("labels by QR with column pivoting" if args.cluster == "cpqr"
                                    else f"k-means restarts={restarts}")),

@@ -183,6 +183,9 @@ typedef struct {
                               normalised Laplacian I - D^-1/2 W D^-1/2 */
     double op_norm;        /* upper bound of ||L|| in relres_j = ||r_j|| / (op_norm
                               ||x_j||) (0 = default 2, the normalised Laplacian's) */
+    int k_conv;            /* the stopping test (and info.max_relres) covers columns
+                              0 .. k_conv-1 only (0 = all k): a block wider than the
+                              wanted pairs, as Section IV runs l slightly above k */
 } sc_lobpcg_opts;
 
 typedef struct {

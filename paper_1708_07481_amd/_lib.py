@@ -30,7 +30,8 @@ _size = C.c_size_t
 
 class sc_lobpcg_opts(C.Structure):
     _fields_ = [("k", _int), ("maxit", _int), ("tol", _dbl), ("prec", _int), ("ldx", _i64),
-                ("lock_tol", _dbl), ("chol_tol", _dbl), ("diag", _p), ("op_norm", _dbl)]
+                ("lock_tol", _dbl), ("chol_tol", _dbl), ("diag", _p), ("op_norm", _dbl),
+                ("k_conv", _int)]
 
 
 class sc_lobpcg_info(C.Structure):

@@ -167,9 +167,9 @@ class LobpcgResult:
 
 
 def lobpcg_opts(k, maxit, tol, precision, ldx, lock_tol=0.0, chol_tol=0.0, diag=None,
-                op_norm=0.0):
+                op_norm=0.0, k_conv=0):
     return _lib.sc_lobpcg_opts(k, maxit, tol, PRECISIONS[precision], ldx, lock_tol, chol_tol,
-                               _ptr(diag), op_norm)
+                               _ptr(diag), op_norm, k_conv)
 
 
 def lobpcg_workspace(ctx: Context, n, nnz, opts) -> int:
@@ -183,7 +183,7 @@ def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor
                  tol: float = 0.0, precision: str = "fp64", lock_tol: float = 0.0,
                  chol_tol: float = 0.0, history: bool = True, ws: torch.Tensor | None = None,
                  X_out: torch.Tensor | None = None, diag: torch.Tensor | None = None,
-                 op_norm: float = 0.0) -> LobpcgResult:
+                 op_norm: float = 0.0, k_conv: int = 0) -> LobpcgResult:
     """diag None: the normalised Laplacian (unit diagonal, op_norm 2).  With a
     diagonal (L = D - W) op_norm defaults to 2 max(diag), the Gershgorin bound."""
     import numpy as np
@@ -193,7 +193,8 @@ def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor
             raise TypeError("diag must have X0's dtype")
         if op_norm <= 0.0:
             op_norm = 2.0 * float(diag.max()) if diag.numel() else 2.0
-    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol, diag, op_norm)
+    opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol, diag, op_norm,
+                       k_conv)
     nb = lobpcg_workspace(ctx, n, g.nnz, opts)
     if ws is None or ws.numel() < nb:
         ws = ctx.workspace(nb)

@@ -789,7 +789,8 @@ k_residual_colsum(int nblocks, int kp, double* __restrict__ partial) {
 }
 
 __global__ void __launch_bounds__(256)
-k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ partial, double op_norm,
+k_residual_finalize(int nblocks, int kp, int k, int k_conv, const double* __restrict__ partial,
+                    double op_norm,
                     double lock_tol,
                     double* __restrict__ relres, double* __restrict__ hist_row, int* __restrict__ wmask,
                     int* status, double* out_max, int* out_all_locked,
@@ -821,7 +822,7 @@ k_residual_finalize(int nblocks, int kp, int k, const double* __restrict__ parti
                 if (!(th >= -slack && th <= op_norm + slack) || rel > 1.0) my_bad = 1;
             }
             my_all &= !active;
-            my_max = fmax(my_max, rel);
+            if (j < k_conv) my_max = fmax(my_max, rel);
         } else {
             relres[j] = 0.0;
             wmask[j] = 0;
@@ -1165,8 +1166,8 @@ template sc_status launch_residual<double>(sc_ctx*, int64_t, int, int, double*, 
 template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, float*, const float*, int64_t,
                                           const double*, double*, int*);
 
-sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, double* partial,
-                                   double op_norm, double lock_tol, double* relres, double* hist_row, int* wmask,
+sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, int k_conv,
+                                   double* partial, double op_norm, double lock_tol, double* relres, double* hist_row, int* wmask,
                                    int* status, double* out_max, int* out_all_locked,
                                    const double* theta, int* out_restart) {
     if (nblocks > 1) {
@@ -1175,7 +1176,7 @@ sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, doub
         nblocks = 1;
     }
     hipLaunchKernelGGL(k_residual_finalize, dim3(1), dim3(256), 0, ctx->stream, nblocks, kp, k,
-                       partial, op_norm, lock_tol, relres, hist_row, wmask, status, out_max,
+                       k_conv, partial, op_norm, lock_tol, relres, hist_row, wmask, status, out_max,
                        out_all_locked, theta, out_restart);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;

@@ -64,6 +64,7 @@ struct sc_lobpcg_state {
     int k = 0, kp = 0, K3 = 0, maxit = 0;
     double tol = 0, lock_tol = 0, chol_tol = 0;
     double op_norm = 2.0;           // bound on ||L|| scaling the relative residual
+    int k_conv = 0;                 // columns covered by the stopping test
     sc_precision prec = SC_PREC_FP64;
     int64_t ldx = 0;
     // workspace views
@@ -254,7 +255,8 @@ struct Solver {
             ProfScope ps(ctx, SC_KIND_RESIDUAL);
             SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
                                       s->res_part, &nb));
-            SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->res_part, s->op_norm, s->lock_tol,
+            SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->k_conv, s->res_part, s->op_norm,
+                                            s->lock_tol,
                                             s->relres, s->hist + (int64_t)s->t * s->kp,
                                             s->act + s->kp, s->status, s->out_max,
                                             s->all_locked, s->theta,
@@ -484,6 +486,7 @@ extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const 
     s->val = val;
     s->diag = opts->diag;
     s->op_norm = opts->op_norm > 0 ? opts->op_norm : 2.0;
+    s->k_conv = (opts->k_conv > 0 && opts->k_conv < opts->k) ? opts->k_conv : opts->k;
     s->k = opts->k;
     s->maxit = opts->maxit;
     s->tol = opts->tol;

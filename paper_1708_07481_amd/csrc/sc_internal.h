@@ -211,7 +211,7 @@ sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* 
 // normalised Laplacian).  With out_restart non-null it is set to 1 when the
 // iterate is inconsistent (a Ritz value outside [0, op_norm] by more than
 // op_norm * 5e-4, or relres > 1, impossible when LX = L X), else 0.
-sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k,
+sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, int k_conv,
                                    double* partial, double op_norm, double lock_tol, double* relres,
                                    double* hist_row, int* wmask, int* status, double* out_max,
                                    int* out_all_locked, const double* theta, int* out_restart);

@@ -197,3 +197,20 @@ def test_lobpcg_failure_paths(orc, ctx):
     r = api.lobpcg_solve(ctx, gd, v64, to_dev(X0), 0)
     ro = orc.lobpcg(go, vo, X0, 0)
     assert r.iterations == 0 and _theta_ok(host(r.theta), ro.theta)
+
+
+def test_lobpcg_wider_block_leading_convergence(orc, ctx):
+    """l = k + 3 columns, stopping on the first k (k_conv): same iterations,
+    Ritz values and residual history as the oracle."""
+    from paper_1708_07481_amd import api
+    g0 = dcsbm(5000, 19, 40.0, 0.75, "dirichlet", 5.0, seed=2)
+    go, vo, gd, v64, _ = _graph_pair(orc, ctx, g0.n, g0.src, g0.dst)
+    X0 = gaussian_block(g0.n, 22, 5)
+    ro = orc.lobpcg(go, vo, X0, 40, 1e-4, k_conv=19)
+    rg = api.lobpcg_solve(ctx, gd, v64, to_dev(X0), 40, 1e-4, "fp64", k_conv=19)
+    assert rg.converged and ro.converged and rg.iterations == ro.iterations
+    assert abs(rg.max_relres - ro.max_relres) <= 1e-6 * ro.max_relres
+    assert _theta_ok(host(rg.theta), ro.theta)
+    assert np.allclose(rg.relres_hist, ro.relres_hist, rtol=1e-5, atol=1e-12)
+    full = api.lobpcg_solve(ctx, gd, v64, to_dev(X0), 40, 1e-4, "fp64")
+    assert rg.iterations <= full.iterations
