@@ -42,6 +42,23 @@ def spmm_algorithmic_bytes(n, nnz, k, s, diag=False):
     return 8 * (n + 1) + nnz * (4 + s) + 2 * n * k * s + (n * s if diag else 0)
 
 
+def gram_counters(cfg_name):
+    """Counter record of the Gram kernel (MFMA busy fraction, HBM traffic) if it
+    was taken on the current dense.hip; else None."""
+    path = os.path.join(HERE, "profiles", f"gram_{cfg_name}_counters.json")
+    src = os.path.join(HERE, "paper_1708_07481_amd", "csrc", "dense.hip")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if t.get("dense_source_sha256") != sha:
+            return None
+        return {"mfma_busy_frac": t["mfma_busy_frac"], "mfma_flop_per_launch": t["mfma_flop_per_launch"],
+                "traffic": t["traffic_bytes_per_launch"]}
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def spmm_traffic(cfg_name, launches_bytes):
     """HBM bytes per SpMM launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
@@ -404,7 +421,8 @@ def main():
             "kernel": "gram (S'LS and S'S)", "bound": "mfma", "unit": "TFLOP/s",
             "achieved": round(gflop / gram_ms, 2), "peak": peak,
             "frac": round(gflop / gram_ms / peak, 4), "ms_per_rr": round(gram_ms, 3),
-            "algorithmic_gflop": round(gflop, 1)}]
+            "algorithmic_gflop": round(gflop, 1),
+            "counters": gram_counters(args.config) if (prec == "fp32" and k == 160) else None}]
     if args.compare and not fp64:
         out["precision_comparison"] = compare_fp64(args, api, ctx, cfg, n, k, src, dst, X0h, draws,
                                                    res, km, total / args.steps, g0.truth)
