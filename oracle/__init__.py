@@ -87,6 +87,8 @@ def _declare(L):
     L.orc_cpqr_labels.argtypes = [_i64, _int, _p, _i64, _p, _p, _p]
     L.orc_eigengap.restype = _int
     L.orc_eigengap.argtypes = [_int, _p, _dbl, C.POINTER(_dbl)]
+    L.orc_warm_fill.restype = None
+    L.orc_warm_fill.argtypes = [_i64, _i64, _p, _p, _int, _p, _i64]
     L.orc_row_normalize.restype = None
     L.orc_row_normalize.argtypes = [_i64, _int, _p, _i64, _p]
 
@@ -323,6 +325,15 @@ def eigengap(theta, sig=10.0):
     r = C.c_double()
     c = lib().orc_eigengap(len(t), _ptr(t), sig, C.byref(r))
     return c, r.value
+
+
+def warm_fill(g: CSR, n_old, X):
+    """Start block for a stage that adds vertices: rows >= n_old become the mean
+    of their old neighbours' rows (zero without one)."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    n, k = X.shape
+    lib().orc_warm_fill(n, n_old, _ptr(g.row_ptr), _ptr(g.col), k, _ptr(X), k)
+    return X
 
 
 def row_normalize(X):

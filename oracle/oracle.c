@@ -34,6 +34,7 @@
  *   orc_cpqr_labels   labels by QR with column pivoting of the eigenvector
  *                     block (Section II-A's own labelling)
  *   orc_eigengap      number of clusters from the gap in the eigenvalues
+ *   orc_warm_fill     start rows of the vertices a streaming stage adds
  */
 #include <math.h>
 #include <stdint.h>
@@ -1015,6 +1016,34 @@ int orc_eigengap(int k, const double* theta, double sig, double* ratio) {
         }
     }
     return jj + 1;
+}
+
+/*
+ * Warm start for a stage that adds vertices (Section III: the approximate
+ * eigenvectors of the previous graph start the solve for the next; the
+ * entries of vertices the previous graph lacked must be filled in).  Vertices
+ * 0 .. n_old-1 keep their rows of X; each new vertex i >= n_old gets the mean
+ * of the rows of its neighbours j < n_old in the current graph: the sum in
+ * FP64 over the row's entries in ascending column order, starting from 0.0,
+ * divided by their count (IEEE division).  A new vertex with no old
+ * neighbour keeps a zero row.  X row-major n x k, row stride ldx, in place.
+ */
+void orc_warm_fill(int64_t n, int64_t n_old, const int64_t* row_ptr, const int32_t* col, int k,
+                   double* X, int64_t ldx) {
+    for (int64_t i = n_old; i < n; ++i) {
+        double* xi = X + i * ldx;
+        int64_t cnt = 0;
+        for (int d = 0; d < k; ++d) xi[d] = 0.0;
+        for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const int64_t j = col[p];
+            if (j >= n_old) continue;
+            const double* xj = X + j * ldx;
+            for (int d = 0; d < k; ++d) xi[d] += xj[d];
+            ++cnt;
+        }
+        if (cnt > 0)
+            for (int d = 0; d < k; ++d) xi[d] = xi[d] / (double)cnt;
+    }
 }
 
 /* Row normalisation alone (exposed for the tests). */
