@@ -145,7 +145,8 @@ def run_serve(args):
     budget = int(args.budget_gb * (1 << 30))
 
     # warm-up: one small solve loads every kernel
-    be = LibraryBackend(args.slots, precision="fp64", maxit=30, tol=1e-2, restarts=10)
+    be = LibraryBackend(args.slots, precision="fp64", maxit=30, tol=1e-2, restarts=10,
+                        warm_fill=args.warm_fill)
     small = min(reqs, key=lambda r: r.n)
     Server(be, slots=1, hbm_budget=budget).run([_clone(small, arrival=0.0, stage=0, warm=False)])
     torch.cuda.synchronize()
@@ -185,7 +186,7 @@ def run_serve(args):
                                 f"until the previous stage finishes; {args.slots} slots, "
                                 f"{args.budget_gb} GB admission budget; maxit 30, tol 1e-2"),
                    "name": "serve"},
-        "serving": {"warm": w, "cold": c,
+        "serving": {"warm": w, "cold": c, "warm_fill": args.warm_fill,
                     "iterations_saved": c["later_stage_iterations"] - w["later_stage_iterations"]},
         "roofline": None,
         "cpu_baseline": None,
@@ -252,6 +253,8 @@ def main():
     ap.add_argument("--stage-rate", type=float, default=10.0, help="serve: stage arrivals per second")
     ap.add_argument("--stages", type=int, default=10)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--warm-fill", default="neighbors", choices=["neighbors", "zero"],
+                    help="serve: start rows of the vertices a snowball stage adds")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")

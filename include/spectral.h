@@ -343,6 +343,21 @@ sc_status sc_ctx_profile(sc_ctx* ctx, int kind, int64_t* launches, double* total
 sc_status sc_ctx_profile_reset(sc_ctx* ctx);
 
 /* ------------------------------------------------------------------------
+ * Warm start for a streaming stage that adds vertices (Section III: the
+ * previous graph's eigenvectors start the next solve; the entries of the new
+ * vertices must be filled in).  X: n x k start block (ldx >= k, float64, or
+ * float32 with x_fp32 != 0), device, in place, whose rows 0 .. n_old-1 hold the
+ * previous stage's block (old vertices keep their ids and come first).  Each
+ * row i >= n_old becomes the mean of the rows of its neighbours j < n_old in
+ * the current CSR (row_ptr, col from sc_graph_build): FP64 sum in ascending
+ * column order from 0.0, divided by the count, rounded once to X's type; a new
+ * vertex without such a neighbour gets a zero row.  1 <= k <= 256.  No
+ * synchronisation.
+ * ------------------------------------------------------------------------ */
+sc_status sc_warm_fill(sc_ctx* ctx, int64_t n, int64_t n_old, const int64_t* row_ptr,
+                       const int32_t* col, int k, void* X, int64_t ldx, int x_fp32);
+
+/* ------------------------------------------------------------------------
  * Cluster labels by QR with column pivoting of the eigenvector block
  * (Section II-A: the paper reads its multi-way partition off the approximate
  * eigenvectors with a pivoted QR, the method of Damle, Minden & Ying).

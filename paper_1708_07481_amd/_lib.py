@@ -86,6 +86,7 @@ SIGNATURES = {
     "sc_cpqr_workspace": (_int, [_p, _i64, _int, _int, C.POINTER(_size)]),
     "sc_cpqr_labels": (_int, [_p, _i64, _int, _p, _i64, _int, _p, _p, _p, _p, _size]),
     "sc_eigengap": (_int, [_p, _int, _p, _dbl, _p, _p]),
+    "sc_warm_fill": (_int, [_p, _i64, _i64, _p, _p, _int, _p, _i64, _int]),
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
 }

@@ -298,6 +298,17 @@ def cpqr_labels(ctx: Context, X: torch.Tensor, ws: torch.Tensor | None = None) -
     return CpqrResult(piv, lab, Q)
 
 
+def warm_fill(ctx: Context, g: DeviceCSR, X: torch.Tensor, n_old: int) -> torch.Tensor:
+    """In place: rows >= n_old of the start block X become the mean of their
+    old neighbours' rows (zero without one)."""
+    n, k = X.shape
+    if X.dtype not in (torch.float64, torch.float32) or X.stride(1) != 1:
+        raise TypeError("X must be float64 or float32 with unit column stride")
+    ctx.check(lib().sc_warm_fill(ctx.handle, n, n_old, _ptr(g.row_ptr), _ptr(g.col), k, _ptr(X),
+                                 X.stride(0), int(X.dtype == torch.float32)), "sc_warm_fill")
+    return X
+
+
 def eigengap(ctx: Context, theta: torch.Tensor, sig: float = 10.0):
     """(count, ratio): number of Ritz values below the first increment more
     than sig times the mean of the ones before it (else below the largest),

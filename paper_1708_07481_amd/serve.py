@@ -358,7 +358,8 @@ class LibraryBackend:
     """Drives the HIP library: one context (own HIP stream) per slot."""
 
     def __init__(self, slots: int, precision: str = "fp32", maxit: int = 30, tol: float = 1e-2,
-                 restarts: int = 10, kmeans_iters: int = 100, device: int = 0):
+                 restarts: int = 10, kmeans_iters: int = 100, device: int = 0,
+                 warm_fill: str = "neighbors"):
         import torch
         from . import api
         self.torch = torch
@@ -368,6 +369,9 @@ class LibraryBackend:
         self.ctxs = [api.Context(device, stream=s) for s in self.streams]
         self.precision = precision
         self.maxit, self.tol, self.restarts, self.kmeans_iters = maxit, tol, restarts, kmeans_iters
+        if warm_fill not in ("neighbors", "zero"):
+            raise ValueError(f"warm_fill must be 'neighbors' or 'zero', not {warm_fill!r}")
+        self.warm_fill = warm_fill   # rows of vertices a snowball stage adds
 
     def _prec(self, req: Request):
         prec = req.precision or self.precision
@@ -391,9 +395,11 @@ class LibraryBackend:
                   "sc_kmeans_workspace")
         return footprint_bytes(req.n, nnz_cap, req.k, elem, self.restarts, lw, kw.value)
 
-    def x0(self, req: Request, warm, stream=None):
-        """Start block: the previous stage's eigenvectors (zero rows for the
-        vertices a snowball stage adds) or a seeded Gaussian block."""
+    def x0(self, req: Request, warm, stream=None, ctx=None, g=None):
+        """Start block: the previous stage's eigenvectors or a seeded Gaussian
+        block.  The rows of vertices a snowball stage adds are the mean of
+        their old neighbours' rows (warm_fill "neighbors", with the stage's
+        graph g on ctx) or zero."""
         torch = self.torch
         _, _, dtype = self._prec(req)
         if warm is not None:
@@ -403,7 +409,9 @@ class LibraryBackend:
             if n_prev == req.n and block.dtype == dtype:
                 return block, True
             x0 = torch.zeros((req.n, req.k), dtype=dtype, device=self.dev)
-            x0[:n_prev].copy_(block)        # snowball: old vertices first, zero fill-in
+            x0[:n_prev].copy_(block)        # snowball: old vertices first
+            if self.warm_fill == "neighbors" and g is not None:
+                self.api.warm_fill(ctx, g, x0, n_prev)
             return x0, True
         from synth import gaussian_block
         return torch.from_numpy(gaussian_block(req.n, req.k, req.seed)).to(dtype).to(self.dev), False
@@ -420,7 +428,7 @@ class LibraryBackend:
             g = api.graph_build(ctx, req.n, src, dst)
             v64, v32, _ = api.laplacian_csr(ctx, g, elem == 8, elem == 4)
             val = v64 if elem == 8 else v32
-            x0, warm_ok = self.x0(req, warm, self.streams[slot])
+            x0, warm_ok = self.x0(req, warm, self.streams[slot], ctx, g)
             opts = api.lobpcg_opts(req.k, self.maxit, self.tol, prec, req.k)
             nb = api.lobpcg_workspace(ctx, req.n, g.nnz, opts)
             ws = ctx.workspace(nb)

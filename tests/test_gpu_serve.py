@@ -76,3 +76,31 @@ def test_warm_start_saves_iterations(requests):
     print(f"later-stage iterations: warm {wi}, cold {ci}", flush=True)
     assert all(not v.warm_started for v in cold.values())
     assert wi < ci
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_warm_fill_bit_exact(orc, fp32):
+    """Start rows of the vertices a snowball stage adds: the mean of their old
+    neighbours' rows, bit for bit the oracle's (FP32 blocks: the oracle's FP64
+    mean rounded once)."""
+    import torch
+    from paper_1708_07481_amd import api
+    from synth import dcsbm, snowball_stages
+    from tests.gpu_common import gpu_ctx, host, to_dev
+    ctx = gpu_ctx()
+    g0 = dcsbm(4000, 10, 20.0, 0.8, seed=7)
+    stages, _ = snowball_stages(g0, 10, seed=2)
+    (n1, _, _), (n2, s2, d2) = stages[4], stages[5]
+    rng = np.random.default_rng(1)
+    X = np.zeros((n2, 10))
+    X[:n1] = rng.standard_normal((n1, 10))
+    if fp32:
+        X = X.astype(np.float32).astype(np.float64)
+    go = orc.graph_build(n2, s2, d2)
+    want = orc.warm_fill(go, n1, X)
+    gd = api.graph_build(ctx, n2, to_dev(s2), to_dev(d2))
+    Xd = to_dev(X.astype(np.float32) if fp32 else X)
+    api.warm_fill(ctx, gd, Xd, n1)
+    got = host(Xd)
+    assert np.array_equal(got, want.astype(np.float32) if fp32 else want)
+    assert np.any(got[n1:] != 0)
