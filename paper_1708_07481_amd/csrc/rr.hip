@@ -163,8 +163,9 @@ __device__ inline int sturm_count(int m, const double* d, const double* e, doubl
 //                 pivoted LU of T - shift I (3 steps from a fixed
 //                 pseudo-random start); coincident eigenvalues get shifts
 //                 pulled apart by 10 eps ||T||;
-//   k_tri_mgs     vectors of eigenvalues closer than 1e-4 ||T|| are
-//                 re-orthogonalised by modified Gram-Schmidt (twice).
+//   k_tri_bcgs    vectors of eigenvalues closer than 1e-4 ||T|| are
+//                 re-orthogonalised by block Gram-Schmidt (twice, Cholesky
+//                 QR within blocks of eight).
 // Layout of the tridiagonal block `tri` (doubles): d[MAXM], e[MAXM],
 // tau[MAXM], params[8].
 // ---------------------------------------------------------------------------
@@ -416,13 +417,27 @@ k_tri_invit(int k, const int* __restrict__ info, const double* __restrict__ tri,
 // forms four dot products per sweep over the rows, and the update keeps four
 // independent partial sums, so the loads of the earlier members overlap.
 // Wt holds >= k * m doubles (vector q at Wt + q m).
-constexpr int MGS_U = 4;
+// Clusters of close eigenvalues: their inverse-iteration vectors are made
+// orthonormal by block classical Gram-Schmidt with reorthogonalisation
+// (BCGS2): blocks of BCG_B vectors, each projected twice against the
+// cluster's earlier vectors (in chunks of BCG_PC, the coefficients of a chunk
+// from the block as the previous chunk left it) and orthonormalised after each
+// projection by Cholesky QR of its BCG_B x BCG_B Gram matrix.  Every earlier
+// vector is read once per block and pass instead of once per vector, which is
+// what bounds this one-workgroup kernel.  A block whose Gram matrix is not
+// safely positive definite (pivot below 1e-14 of the largest diagonal entry)
+// is orthonormalised vector by vector instead (Gram-Schmidt, twice).
+constexpr int BCG_B = 8;
+constexpr int BCG_PC = 128;
+
 __global__ void __launch_bounds__(NT)
-k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
-          const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ Wt) {
+k_tri_bcgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
+           const double* __restrict__ w, double* __restrict__ V, int ldv, double* __restrict__ Wt) {
     __shared__ double red[NWAVE + 1];
-    __shared__ double dots[MAXM];
-    __shared__ double vl[MAXM];
+    __shared__ double blk[BCG_B][MAXM];
+    __shared__ double cf[BCG_PC][BCG_B];
+    __shared__ double G[BCG_B][BCG_B], Li[BCG_B][BCG_B];
+    __shared__ int fail;
     const int m = info[0];
     if (m == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -438,49 +453,140 @@ k_tri_mgs(int k, const int* __restrict__ info, const double* __restrict__ tri,
                 Wt[(int64_t)q * m + r] = V[(int64_t)r * ldv + q];
             }
             __syncthreads();
-            for (int q = c0; q < c1; ++q) {
-                double* vq = Wt + (int64_t)q * m;
-                for (int r = tid; r < m; r += NT) vl[r] = vq[r];
-                __syncthreads();
-                for (int pass = 0; pass < 2 && q > c0; ++pass) {
-                    // dots with the earlier members, MGS_U members per wave sweep
-                    for (int p0 = c0 + wave * MGS_U; p0 < q; p0 += NWAVE * MGS_U) {
-                        double part[MGS_U];
-                        const double* vp[MGS_U];
-#pragma unroll
-                        for (int u = 0; u < MGS_U; ++u) {
-                            part[u] = 0.0;
-                            vp[u] = Wt + (int64_t)min(p0 + u, q - 1) * m;
-                        }
-                        for (int r = lane; r < m; r += 64) {
-                            const double y = vl[r];
-#pragma unroll
-                            for (int u = 0; u < MGS_U; ++u) part[u] = fma(vp[u][r], y, part[u]);
-                        }
-#pragma unroll
-                        for (int u = 0; u < MGS_U; ++u) {
-                            const double t = sc_wave_sum(part[u]);
-                            if (lane == 0 && p0 + u < q) dots[p0 + u - c0] = t;
-                        }
-                    }
-                    __syncthreads();
-                    for (int r = tid; r < m; r += NT) {
-                        double acc[MGS_U] = {};
-                        int pp = c0;
-                        for (; pp + MGS_U <= q; pp += MGS_U) {
-#pragma unroll
-                            for (int u = 0; u < MGS_U; ++u)
-                                acc[u] = fma(dots[pp + u - c0], Wt[(int64_t)(pp + u) * m + r], acc[u]);
-                        }
-                        for (; pp < q; ++pp) acc[0] = fma(dots[pp - c0], Wt[(int64_t)pp * m + r], acc[0]);
-                        vl[r] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
-                    }
-                    __syncthreads();
+            for (int b0 = c0; b0 < c1; b0 += BCG_B) {
+                const int nb = min(BCG_B, c1 - b0);
+                for (int e = tid; e < BCG_B * m; e += NT) {
+                    const int u = e / m, r = e % m;
+                    blk[u][r] = u < nb ? Wt[(int64_t)(b0 + u) * m + r] : 0.0;
                 }
-                double part = 0.0;
-                for (int r = tid; r < m; r += NT) part = fma(vl[r], vl[r], part);
-                const double inv = 1.0 / sqrt(block_sum(part, red));
-                for (int r = tid; r < m; r += NT) vq[r] = vl[r] * inv;
+                __syncthreads();
+                for (int rep = 0; rep < 2; ++rep) {
+                    // projection against the cluster's earlier vectors
+                    for (int p0 = c0; p0 < b0; p0 += BCG_PC) {
+                        const int np = min(BCG_PC, b0 - p0);
+                        for (int pi = wave; pi < np; pi += NWAVE) {
+                            const double* q = Wt + (int64_t)(p0 + pi) * m;
+                            double part[BCG_B];
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u) part[u] = 0.0;
+                            for (int r = lane; r < m; r += 64) {
+                                const double qv = q[r];
+#pragma unroll
+                                for (int u = 0; u < BCG_B; ++u) part[u] = fma(qv, blk[u][r], part[u]);
+                            }
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u) {
+                                const double t = sc_wave_sum(part[u]);
+                                if (lane == 0) cf[pi][u] = t;
+                            }
+                        }
+                        __syncthreads();
+                        for (int r = tid; r < m; r += NT) {
+                            double acc[BCG_B];
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u) acc[u] = 0.0;
+                            for (int pi = 0; pi < np; ++pi) {
+                                const double qv = Wt[(int64_t)(p0 + pi) * m + r];
+#pragma unroll
+                                for (int u = 0; u < BCG_B; ++u) acc[u] = fma(cf[pi][u], qv, acc[u]);
+                            }
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u)
+                                if (u < nb) blk[u][r] -= acc[u];
+                        }
+                        __syncthreads();
+                    }
+                    // Gram matrix of the block: one wave per (u, v) pair, u <= v
+                    for (int pr = wave; pr < BCG_B * BCG_B; pr += NWAVE) {
+                        const int u = pr / BCG_B, v = pr % BCG_B;
+                        if (u > v || v >= nb) continue;                  // wave-uniform
+                        double part = 0.0;
+                        for (int r = lane; r < m; r += 64) part = fma(blk[u][r], blk[v][r], part);
+                        const double t = sc_wave_sum(part);
+                        if (lane == 0) {
+                            G[u][v] = t;
+                            G[v][u] = t;
+                        }
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        // G = L L', Li = L^-1 (nb x nb)
+                        double gmax = 0.0;
+                        for (int u = 0; u < nb; ++u) gmax = fmax(gmax, G[u][u]);
+                        int bad = !(gmax > 0.0) || !isfinite(gmax);
+                        for (int j = 0; j < nb && !bad; ++j) {
+                            double d = G[j][j];
+                            for (int t = 0; t < j; ++t) d -= G[j][t] * G[j][t];
+                            if (!(d > 1e-14 * gmax)) {
+                                bad = 1;
+                                break;
+                            }
+                            const double ljj = sqrt(d);
+                            G[j][j] = ljj;
+                            for (int i = j + 1; i < nb; ++i) {
+                                double x = G[i][j];
+                                for (int t = 0; t < j; ++t) x -= G[i][t] * G[j][t];
+                                G[i][j] = x / ljj;
+                            }
+                        }
+                        if (!bad)
+                            for (int c = 0; c < nb; ++c)
+                                for (int i = 0; i < nb; ++i) {
+                                    if (i < c) {
+                                        Li[i][c] = 0.0;
+                                        continue;
+                                    }
+                                    double x = i == c ? 1.0 : 0.0;
+                                    for (int t = c; t < i; ++t) x -= G[i][t] * Li[t][c];
+                                    Li[i][c] = x / G[i][i];
+                                }
+                        fail = bad;
+                    }
+                    __syncthreads();
+                    if (!fail) {
+                        // Q = V R^-1 with R = L': q_u = sum_{t <= u} Li[u][t] v_t
+                        for (int r = tid; r < m; r += NT) {
+                            double x[BCG_B], y[BCG_B];
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u) x[u] = blk[u][r];
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u) {
+                                double a = 0.0;
+#pragma unroll
+                                for (int t = 0; t < BCG_B; ++t)
+                                    if (t <= u) a = fma(Li[u][t], x[t], a);
+                                y[u] = a;
+                            }
+#pragma unroll
+                            for (int u = 0; u < BCG_B; ++u)
+                                if (u < nb) blk[u][r] = y[u];
+                        }
+                        __syncthreads();
+                    } else {
+                        // vector by vector: Gram-Schmidt against the block's earlier
+                        // members, twice, then normalisation
+                        for (int u = 0; u < nb; ++u) {
+                            for (int pass = 0; pass < 2; ++pass)
+                                for (int t = 0; t < u; ++t) {
+                                    double part = 0.0;
+                                    for (int r = tid; r < m; r += NT) part = fma(blk[t][r], blk[u][r], part);
+                                    const double d = block_sum(part, red);
+                                    for (int r = tid; r < m; r += NT) blk[u][r] = fma(-d, blk[t][r], blk[u][r]);
+                                    __syncthreads();
+                                }
+                            double part = 0.0;
+                            for (int r = tid; r < m; r += NT) part = fma(blk[u][r], blk[u][r], part);
+                            const double nrm = sqrt(block_sum(part, red));
+                            const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+                            for (int r = tid; r < m; r += NT) blk[u][r] *= inv;
+                            __syncthreads();
+                        }
+                    }
+                }
+                for (int e = tid; e < nb * m; e += NT) {
+                    const int u = e / m, r = e % m;
+                    Wt[(int64_t)(b0 + u) * m + r] = blk[u][r];
+                }
                 __syncthreads();
             }
             for (int e = tid; e < cs * m; e += NT) {
@@ -1135,7 +1241,7 @@ static void eig_pipeline(hipStream_t st, int m_max, int k, const int* info, cons
     hipLaunchKernelGGL(k_tri_invit, dim3((unsigned)ceil_div(k, IV_T)), dim3(IV_T), 0, st, k, info,
                        tri, w, V, k, lu);
     // the inverse-iteration LU arrays (5 MAXM k doubles) are free again: cluster scratch
-    hipLaunchKernelGGL(k_tri_mgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k, lu);
+    hipLaunchKernelGGL(k_tri_bcgs, dim3(32), dim3(NT), 0, st, k, info, tri, w, V, k, lu);
     if (m_max <= 512)
         hipLaunchKernelGGL((k_rr_back<8>), dim3((unsigned)ceil_div(k, BK_W)), dim3(BK_W * 64), 0, st, k,
                            info, M, tri, V);
