@@ -260,6 +260,9 @@ def main():
                     help="override the workload's precision")
     ap.add_argument("--cluster", default="kmeans", choices=["kmeans", "cpqr"],
                     help="labelling: k-means++ with restarts (default) or QR with column pivoting")
+    ap.add_argument("--eigengap", action="store_true",
+                    help="cluster count from the gap in the Ritz values (use with --extra-cols), "
+                         "labels on that many leading columns")
     ap.add_argument("--extra-cols", type=int, default=0,
                     help="LOBPCG block of k + E columns, stopping test and labels on the first k")
     ap.add_argument("--lock-tol", type=float, default=0.0,
@@ -331,12 +334,16 @@ def main():
         val = v64 if fp64 else v32
         res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag,
                                lock_tol=args.lock_tol, k_conv=k if kb > k else 0)
-        Xk = res.X[:, :k]
+        kc = k
+        if args.eigengap:
+            kc, _ = api.eigengap(ctx, res.theta)
+        Xk = res.X[:, :kc]
         if args.cluster == "cpqr":
             cq = api.cpqr_labels(ctx, Xk)
-            km = SimpleNamespace(labels=cq.labels, lloyd_iterations=None)
+            km = SimpleNamespace(labels=cq.labels, lloyd_iterations=None, clusters=kc)
         else:
-            km = api.kmeans_assign(ctx, Xk, k, draws, max_iter=100)
+            km = api.kmeans_assign(ctx, Xk, kc, draws[:, :kc].contiguous(), max_iter=100)
+            km.clusters = kc
         return gd, res, km
 
     for w in range(args.warmup):
@@ -396,6 +403,7 @@ def main():
                                    else f"k-means restarts={restarts}")),
                    "name": args.config, "n": n, "nnz": gd.nnz, "k": k},
         "lobpcg_iterations": res.iterations,
+        "clusters": getattr(km, "clusters", k),
         "kmeans_lloyd_iterations": km.lloyd_iterations,
         "converged": res.converged,
         "max_relres": res.max_relres,

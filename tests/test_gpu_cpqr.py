@@ -125,3 +125,17 @@ def test_eigengap_then_cpqr_on_sbm(orc, ctx):
     pm = partition_scores(g0.truth, lab)["PM"]
     print("eigengap", c, "ratio", ratio, "PM", pm)
     assert pm > 0.95
+
+
+def test_cpqr_square_block_and_eigengap_errors(orc, ctx):
+    """k == n: every row is a pivot; labels still the oracle's.  Invalid
+    eigengap arguments are rejected."""
+    from paper_1708_07481_amd import api
+    X = np.random.default_rng(11).standard_normal((12, 12))
+    ro, rg = _compare(orc, ctx, X, to_dev(X))
+    assert sorted(host(rg.pivots).tolist()) == list(range(12))
+    th = to_dev(np.array([0.0, 0.1, 0.5]))
+    with pytest.raises(api.SpectralError):
+        api.eigengap(ctx, th, sig=0.0)
+    with pytest.raises(api.SpectralError):
+        api.eigengap(ctx, to_dev(np.zeros(300)))

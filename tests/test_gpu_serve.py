@@ -104,3 +104,19 @@ def test_warm_fill_bit_exact(orc, fp32):
     got = host(Xd)
     assert np.array_equal(got, want.astype(np.float32) if fp32 else want)
     assert np.any(got[n1:] != 0)
+
+
+def test_warm_fill_edge_cases(orc):
+    """n_old == n changes nothing; n_old == 0 has no old neighbours: zero rows."""
+    from paper_1708_07481_amd import api
+    from synth import dcsbm
+    from tests.gpu_common import gpu_ctx, host, to_dev
+    ctx = gpu_ctx()
+    g0 = dcsbm(500, 4, 10.0, 0.8, seed=3)
+    gd = api.graph_build(ctx, g0.n, to_dev(g0.src), to_dev(g0.dst))
+    X = np.random.default_rng(2).standard_normal((g0.n, 4))
+    Xd = to_dev(X)
+    api.warm_fill(ctx, gd, Xd, g0.n)
+    assert np.array_equal(host(Xd), X)
+    api.warm_fill(ctx, gd, Xd, 0)
+    assert np.all(host(Xd) == 0.0)
