@@ -226,6 +226,14 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y
 // min(D2, dist(y_i, c_j)); then the integer weights.  One pass over Y serves
 // up to RB restarts.
 constexpr int RB = 16;
+// the accumulator width a seeding pass uses for R restarts
+inline int seed_width(int R) {
+    return R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : R <= 8 ? 8 : R <= 10 ? 10 : R <= 12 ? 12 : RB;
+}
+// Row stride of the dimension-major centres: a whole number of passes, and no
+// wider, so that the rows a pass reads through the scalar cache stay compact
+// (160 dimensions x 10 restarts: 12.8 KB rather than 20 KB at stride 16).
+inline int seed_stride(int R) { return R <= RB ? seed_width(R) : (R + RB - 1) / RB * RB; }
 // WB restarts per pass over the points (WB <= RB; the launch picks the
 // smallest width covering the restarts, so no accumulator is wasted)
 template <int WB, class TT>
@@ -1297,7 +1305,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.brj = c.take<int>((size_t)w.max_blocks);
     w.bidx = c.take<int>((size_t)w.max_blocks);
     w.bsum = c.take<double>((size_t)w.max_blocks * dim);
-    w.Rpad = (R + RB - 1) / RB * RB;
+    w.Rpad = seed_stride(R);
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
     w.hsv = c.take<double>((size_t)R * K * K);
     w.secf = c.take<float>((size_t)nr);
@@ -1361,13 +1369,15 @@ void final_d2_go(sc_ctx* ctx, int64_t n, int dim, int K, int Kpad, int R, const 
 }
 
 void seed_d2(sc_ctx* ctx, int64_t n, int dim, int R, int Rpad, int j, const KmWs& w, int shift) {
-    if (R <= 1) seed_d2_go<1>(ctx, n, dim, R, Rpad, j, w, shift);
-    else if (R <= 2) seed_d2_go<2>(ctx, n, dim, R, Rpad, j, w, shift);
-    else if (R <= 4) seed_d2_go<4>(ctx, n, dim, R, Rpad, j, w, shift);
-    else if (R <= 8) seed_d2_go<8>(ctx, n, dim, R, Rpad, j, w, shift);
-    else if (R <= 10) seed_d2_go<10>(ctx, n, dim, R, Rpad, j, w, shift);
-    else if (R <= 12) seed_d2_go<12>(ctx, n, dim, R, Rpad, j, w, shift);
-    else seed_d2_go<16>(ctx, n, dim, R, Rpad, j, w, shift);
+    switch (seed_width(R)) {
+    case 1: seed_d2_go<1>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    case 2: seed_d2_go<2>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    case 4: seed_d2_go<4>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    case 8: seed_d2_go<8>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    case 10: seed_d2_go<10>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    case 12: seed_d2_go<12>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    default: seed_d2_go<RB>(ctx, n, dim, R, Rpad, j, w, shift); break;
+    }
 }
 
 template <int JB>
