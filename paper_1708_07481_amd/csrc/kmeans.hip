@@ -1083,8 +1083,9 @@ __global__ void k_block_list(int m, const int* __restrict__ nblk, const int* __r
     }
 }
 
-// block sums: thread (slot, d), dimensions fastest (a member row is read
-// contiguously by consecutive threads)
+// block sums: a slot is ceil(dim / 64) whole waves, lane = dimension within the
+// wave's 64, so the member ids and their divisors are wave-uniform (scalar
+// loads) and a member row is read contiguously by the wave's lanes
 template <class TT>
 __global__ void __launch_bounds__(TH)
 k_centroid_blocks(int dim, int m, const TT* __restrict__ Y, int64_t ldy, const YDiv* __restrict__ dv,
@@ -1092,30 +1093,36 @@ k_centroid_blocks(int dim, int m, const TT* __restrict__ Y, int64_t ldy, const Y
                   const int64_t* __restrict__ seg, const int* __restrict__ boff,
                   const int* __restrict__ brj, const int* __restrict__ bidx,
                   double* __restrict__ bsum) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t slot = e / dim;
+    const int wps = (dim + 63) / 64;
+    const int wv = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int slot = uniform(wv / wps);
     if (slot >= boff[m]) return;
-    const int d = (int)(e % dim);
+    const int d = (wv - slot * wps) * 64 + (int)(threadIdx.x & 63);
+    const bool dl = d < dim;
+    const int dd = dl ? d : dim - 1;
     const int rj = brj[slot];
     const int64_t lo = seg[2 * (int64_t)rj] + (int64_t)bidx[slot] * KM_BLOCK;
     const int64_t hi = min(seg[2 * (int64_t)rj + 1], lo + KM_BLOCK);
     const uint32_t* mem = members + lo;
-    const int64_t cnt = hi - lo;
+    const int cnt = (int)(hi - lo);
     double s = 0.0;
-    int64_t p = 0;
+    int p = 0;
     constexpr int U = 16;
     for (; p + U <= cnt; p += U) {
         uint32_t id[U];
         TT v[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) id[q] = mem[p + q];
+        for (int q = 0; q < U; ++q) id[q] = uniform((int)mem[p + q]);
 #pragma unroll
-        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * ldy + d];
+        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * ldy + dd];
 #pragma unroll
         for (int q = 0; q < U; ++q) s += ycoord(v[q], ydiv_of<TT>(dv, id[q]));
     }
-    for (; p < cnt; ++p) s += ycoord(Y[(int64_t)mem[p] * ldy + d], ydiv_of<TT>(dv, mem[p]));
-    bsum[slot * dim + d] = s;
+    for (; p < cnt; ++p) {
+        const uint32_t id = uniform((int)mem[p]);
+        s += ycoord(Y[(int64_t)id * ldy + dd], ydiv_of<TT>(dv, id));
+    }
+    if (dl) bsum[(int64_t)slot * dim + d] = s;
 }
 
 // centroid (r, j), dimension d: block sums in order, divided by the count
@@ -1546,7 +1553,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
             hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(TH), 0, st, m, w.nblk, w.boff);
             hipLaunchKernelGGL(k_block_list, dim3(ceil_div(m, TH)), dim3(TH), 0, st, m, w.nblk,
                                w.boff, w.brj, w.bidx);
-            const dim3 gblk((unsigned)ceil_div(w.max_blocks * dim, TH));
+            const dim3 gblk((unsigned)ceil_div(w.max_blocks * ceil_div(dim, 64) * 64, TH));
             if (w.yt32)
                 hipLaunchKernelGGL(k_centroid_blocks<float>, gblk, dim3(TH), 0, st, dim, m,
                                    static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.vals, w.seg,
