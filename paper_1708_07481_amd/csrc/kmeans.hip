@@ -552,8 +552,9 @@ __device__ inline void pr_store(TT (*ys)[65], const TT (&v)[DC], int lane) {
 template <int JB, class TT>
 __global__ void __launch_bounds__(TH)
 k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, int64_t ldy,
-                const YDiv* __restrict__ dv, const double* __restrict__ Ct, const double* __restrict__ hsv,
-                const uint16_t* __restrict__ hsi, const uint32_t* __restrict__ pts,
+                const YDiv* __restrict__ dv, const double* __restrict__ Ct, const double* __restrict__ C,
+                const double* __restrict__ hsv, const uint16_t* __restrict__ hsi,
+                const uint32_t* __restrict__ pts,
                 const int* __restrict__ cnt, const int* __restrict__ active,
                 int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
                 int* __restrict__ changed, int* __restrict__ dirty, uint32_t* __restrict__ fl,
@@ -590,6 +591,7 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, i
     const int a = lab[e];
     const YDiv mdv = ydiv_of<TT>(dv, i);
     const double* Ctr = Ct + (int64_t)r * dim * Kpad;
+    const double* Cr = C + (int64_t)r * K * dim;
     __builtin_amdgcn_wave_barrier();
     // 1. exact distance to the assigned centre
     double own = 0.0;
@@ -699,10 +701,10 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, i
             for (int dd = 0; dd < DC; ++dd) {
                 if (dd < nd) {
                     const double y = ycoord(ys[wave][dd][lane], mdv);
-                    const double* crow = Ctr + (int64_t)(d0 + dd) * Kpad;
 #pragma unroll
                     for (int u2 = 0; u2 < JB; ++u2) {
-                        const double diff = y - crow[cj[u2]];
+                        // centre-major rows: a candidate's coordinates are contiguous
+                        const double diff = y - Cr[(int64_t)cj[u2] * dim + d0 + dd];
                         acc[u2] = fma(diff, diff, acc[u2]);
                     }
                 }
@@ -1394,12 +1396,12 @@ void launch_pruned(sc_ctx* ctx, int64_t n, int dim, int K, int R, const KmWs& w,
     if (w.yt32)
         hipLaunchKernelGGL((k_assign_pruned<JB, float>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
                            assign_kpad(K), static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.Ct,
-                           w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
+                           w.C, w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
                            w.dirty, w.fl, w.fcnt);
     else
         hipLaunchKernelGGL((k_assign_pruned<JB, double>), grid, dim3(TH), 0, ctx->stream, n, dim, K,
                            assign_kpad(K), static_cast<const double*>(w.Ysrc), w.ldy, w.dv, w.Ct,
-                           w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
+                           w.C, w.hsv, w.hsi, list, w.cnt, w.active, w.lab, w.ub, w.lb, w.changed,
                            w.dirty, w.fl, w.fcnt);
 }
 
