@@ -103,6 +103,25 @@ def test_kmeans_bit_exact_fp32_input(orc, ctx, n, dim, K, R, seed, norm, scan):
     _same(ko, kg)
 
 
+@pytest.mark.parametrize("R", [7, 12, 13, 20])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_kmeans_bit_exact_restart_widths(orc, ctx, R, fp32):
+    """Restart counts that take each seeding width (8, 12 and 16 restarts per
+    pass over the points) and, at 20, two passes; the seeding's centre rows are
+    strided by that width."""
+    from paper_1708_07481_amd import api
+    rng = np.random.default_rng(40 + R)
+    n, dim, K = 3001, 12, 9
+    centers = rng.standard_normal((K, dim))
+    X = centers[rng.integers(0, K, n)] + 0.4 * rng.standard_normal((n, dim))
+    if fp32:
+        X = X.astype(np.float32)
+    draws = kmeans_draws(R, K, R)
+    ko = orc.kmeans(X.astype(np.float64), K, draws, max_iter=100)
+    kg = api.kmeans_assign(ctx, to_dev(X), K, to_dev(draws.view(np.int64)), max_iter=100)
+    _same(ko, kg)
+
+
 def test_kmeans_edge_cases(orc, ctx):
     from paper_1708_07481_amd import api
     # zero rows, duplicate points, K == n, max_iter = 0, no normalisation
