@@ -160,6 +160,7 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y
     __shared__ int64_t pick;
     __shared__ int64_t tile_s;
     __shared__ uint64_t base_s;
+    __shared__ int owner_s;
     const int r = blockIdx.x, tid = threadIdx.x;
     const uint64_t u = draws[(int64_t)r * K + j];
     if (tid == 0) pick = (int64_t)mulhi64(u, (uint64_t)n);
@@ -183,15 +184,34 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y
         if (T > 0) {
             const uint64_t t = mulhi64(u, T);
             const uint64_t lo = part[tid] - mine;            // prefix before this thread's tiles
-            if (lo <= t && t < part[tid]) {
-                uint64_t acc = lo;
-                for (int64_t q = t0; q < t1; ++q) {
-                    if (t < acc + ts[q]) {
-                        tile_s = q;
-                        base_s = acc;
+            if (lo <= t && t < part[tid]) owner_s = tid;     // exactly one thread's range holds t
+            __syncthreads();
+            // the owner's tiles, 64 at a time by wave 0: the first whose inclusive
+            // prefix exceeds t, and the prefix before it
+            if (tid < 64) {
+                const int ow = owner_s;
+                const int64_t a0 = min((int64_t)ow * per, ntiles), a1 = min(a0 + per, ntiles);
+                uint64_t acc = ow > 0 ? part[ow - 1] : 0;     // prefix before the owner's tiles
+                for (int64_t c0 = a0; c0 < a1; c0 += 64) {
+                    const int64_t q = c0 + tid;
+                    const uint64_t w = q < a1 ? ts[q] : 0;
+                    uint64_t incl = w;
+#pragma unroll
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint64_t x = __shfl_up(incl, o);
+                        if (tid >= o) incl += x;
+                    }
+                    const unsigned long long m = __ballot(q < a1 && t < acc + incl);
+                    if (m) {
+                        const int f = __ffsll((long long)m) - 1;
+                        const uint64_t before = __shfl(incl - w, f);
+                        if (tid == 0) {
+                            tile_s = c0 + f;
+                            base_s = acc + before;
+                        }
                         break;
                     }
-                    acc += ts[q];
+                    acc += __shfl(incl, 63);
                 }
             }
             __syncthreads();
