@@ -47,9 +47,6 @@
 #define ORC_E_BREAKDOWN (-4)
 #define ORC_E_NUMERIC (-5)
 
-/* members per block of the k-means centroid sums */
-#define ORC_KM_BLOCK 256
-
 /* ------------------------------------------------------------------------ */
 /* Graph symmetrisation (Section II-A).                                      */
 /* ------------------------------------------------------------------------ */
@@ -681,11 +678,9 @@ static uint64_t qweight(double d2, int shift) {
  *              w_i = floor(D2_i 2^s), T = sum w, t = mulhi(u_j, T),
  *              c_j = y[min i : prefix_i > t] (T == 0: y[mulhi(u_j, n)]);
  *   Lloyd:     assign (argmin, ties to the lowest cluster), update centroids
- *              (the members of a cluster, in ascending vertex order, are cut
- *              into consecutive blocks of ORC_KM_BLOCK; each block is summed
- *              in order from 0.0, the block sums are added in order from
- *              0.0, and the total is divided by the count; an empty cluster
- *              keeps its centroid), stop when no label changes;
+ *              (each dimension is one FP64 sum from 0.0 over the members in
+ *              ascending vertex order, divided by the member count; an empty
+ *              cluster keeps its centroid), stop when no label changes;
  *   choice:    restart with the least integer inertia sum_i floor(mind_i 2^s),
  *              ties to the lowest restart.
  * If init_centroids != NULL it replaces the seeding (restarts must be 1).
@@ -704,9 +699,7 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     int32_t* lab = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t* nl = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
-    int64_t* rank = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
-    double* bs = (double*)malloc(sizeof(double) * (size_t)K * dim);
-    if (!Y || !Cc || !D2 || !pref || !lab || !nl || !cnt || !rank || !bs) return ORC_E_NOMEM;
+    if (!Y || !Cc || !D2 || !pref || !lab || !nl || !cnt) return ORC_E_NOMEM;
     double m2 = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         const double* x = X + i * ldx;
@@ -738,6 +731,7 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
         } else {
             int64_t c0 = (int64_t)mulhi64(u[0], (uint64_t)n);
             memcpy(Cc, Y + c0 * dim, sizeof(double) * (size_t)dim);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) D2[i] = sqdist(dim, Y + i * dim, Cc);
             for (int j = 1; j < K; ++j) {
                 uint64_t T = 0;
@@ -755,6 +749,7 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
                     pick = lo;
                 }
                 memcpy(Cc + (int64_t)j * dim, Y + pick * dim, sizeof(double) * (size_t)dim);
+#pragma omp parallel for schedule(static)
                 for (int64_t i = 0; i < n; ++i) {
                     double dd = sqdist(dim, Y + i * dim, Cc + (int64_t)j * dim);
                     if (dd < D2[i]) D2[i] = dd;
@@ -778,30 +773,18 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
             for (int j = 0; j < K; ++j) cnt[j] = 0;
             for (int64_t i = 0; i < n; ++i) cnt[lab[i]]++;
             for (int j = 0; j < K; ++j) {
-                rank[j] = 0;
                 if (cnt[j] == 0) continue;
                 double* c = Cc + (int64_t)j * dim;
-                double* b = bs + (int64_t)j * dim;
-                for (int d = 0; d < dim; ++d) c[d] = b[d] = 0.0;
+                for (int d = 0; d < dim; ++d) c[d] = 0.0;
             }
             for (int64_t i = 0; i < n; ++i) {
-                const int j = lab[i];
-                double* c = Cc + (int64_t)j * dim;
-                double* b = bs + (int64_t)j * dim;
+                double* c = Cc + (int64_t)lab[i] * dim;
                 const double* y = Y + i * dim;
-                for (int d = 0; d < dim; ++d) b[d] += y[d];
-                if (++rank[j] % ORC_KM_BLOCK == 0)      /* a block is complete */
-                    for (int d = 0; d < dim; ++d) {
-                        c[d] += b[d];
-                        b[d] = 0.0;
-                    }
+                for (int d = 0; d < dim; ++d) c[d] += y[d];
             }
             for (int j = 0; j < K; ++j) {
                 if (cnt[j] == 0) continue;
                 double* c = Cc + (int64_t)j * dim;
-                const double* b = bs + (int64_t)j * dim;
-                if (rank[j] % ORC_KM_BLOCK != 0)        /* the last, partial block */
-                    for (int d = 0; d < dim; ++d) c[d] += b[d];
                 for (int d = 0; d < dim; ++d) c[d] = c[d] / (double)cnt[j];
             }
             int64_t changed = 0;
@@ -837,7 +820,7 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     if (inertia_q) *inertia_q = best_q;
     if (best_restart) *best_restart = best_r;
     if (lloyd_iters) *lloyd_iters = best_iters;
-    free(Y); free(Cc); free(D2); free(pref); free(lab); free(nl); free(cnt); free(rank); free(bs);
+    free(Y); free(Cc); free(D2); free(pref); free(lab); free(nl); free(cnt);
     return ORC_OK;
 }
 

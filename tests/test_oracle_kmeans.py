@@ -114,10 +114,9 @@ def test_pure_assignment_with_given_centroids(orc):
 @pytest.mark.parametrize("sizes", [(1000, 257, 256), (255, 513, 1)])
 def test_centroid_is_exact_mean_of_large_clusters(orc, sizes):
     """Centroids are member means.  Coordinates are multiples of 2^-10 below
-    2^4, so every partial sum is exact whatever the grouping: the centroid
-    must equal the exact rational mean rounded once (by the division).  A
-    block of members dropped or added twice by the blocked summation, or a
-    member counted in the wrong cluster, changes the result."""
+    2^4, so every partial sum is exact whatever the order: the centroid must
+    equal the exact rational mean rounded once (by the division).  A member
+    dropped, added twice or counted in the wrong cluster changes the result."""
     from fractions import Fraction
     rng = np.random.default_rng(7)
     centres = np.array([[100.0, 0.0, 0.0], [0.0, 100.0, 0.0], [0.0, 0.0, 100.0]])
@@ -136,3 +135,62 @@ def test_centroid_is_exact_mean_of_large_clusters(orc, sizes):
         for d in range(3):
             exact = sum(Fraction(float(v)) for v in mem[:, d]) / len(mem)
             assert r.centroids[j, d] == float(exact), (j, d)
+
+
+def _rn(q):
+    """Round an exact rational to the nearest double (ties to even)."""
+    from fractions import Fraction
+    return float(Fraction(q))
+
+
+def test_centroid_sum_is_one_ordered_chain(orc):
+    """Each centroid coordinate is one FP64 chain from 0.0 over the members
+    in ascending vertex order, then divided by the count.  The chain is
+    replayed here with exact rationals, every addition rounded to the nearest
+    double, on coordinates that are not dyadic, so the rounding of every step
+    shows.  The data are chosen so that the replay tells the orders apart: a
+    sum in blocks of 256 members, a descending order and the exactly rounded
+    mean each differ from the ordered chain in some coordinate, and the
+    oracle must equal the ordered chain in every coordinate.  Its distance to
+    the exact mean stays within the chain's error bound."""
+    from fractions import Fraction
+    rng = np.random.default_rng(17)
+    sizes = (700, 513, 300)
+    dim = 4
+    centres = np.zeros((3, dim))
+    centres[:, :3] = 1e7 * np.eye(3)
+    pts, truth = [], []
+    for j, s in enumerate(sizes):
+        pts.append(centres[j] + rng.standard_normal((s, dim)) * np.array([3.0, 1e-3, 7e5, 0.1]))
+        truth += [j] * s
+    X = np.concatenate(pts)
+    perm = rng.permutation(X.shape[0])
+    X, truth = X[perm], np.array(truth)[perm]
+    r = orc.kmeans(X, 3, init_centroids=centres, max_iter=1, normalize=False)
+    assert np.array_equal(r.labels, truth)
+
+    def chain(vals):
+        s = 0.0
+        for v in vals:
+            s = _rn(Fraction(s) + Fraction(float(v)))
+        return s
+
+    diffs = {"blocked": 0, "descending": 0, "exact": 0}
+    eps = 2.0 ** -53
+    for j in range(3):
+        mem = X[truth == j]          # ascending vertex order (a boolean mask keeps order)
+        cnt = len(mem)
+        for d in range(dim):
+            col = mem[:, d]
+            seq = chain(col)
+            want = _rn(Fraction(seq) / cnt)
+            assert r.centroids[j, d] == want, (j, d, r.centroids[j, d], want)
+            blocks = [chain(col[b:b + 256]) for b in range(0, cnt, 256)]
+            diffs["blocked"] += _rn(Fraction(chain(blocks)) / cnt) != want
+            diffs["descending"] += _rn(Fraction(chain(col[::-1])) / cnt) != want
+            exact = sum(Fraction(float(v)) for v in col) / cnt
+            diffs["exact"] += _rn(exact) != want
+            # |fl(chain) - sum| <= (cnt - 1) eps sum|y| (+ the division's half ulp)
+            bound = (cnt - 1) * eps * float(np.abs(col).sum()) / cnt + abs(want) * eps
+            assert abs(Fraction(want) - exact) <= Fraction(bound) * 1.01, (j, d)
+    assert all(v > 0 for v in diffs.values()), diffs
