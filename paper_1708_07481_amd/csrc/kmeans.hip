@@ -35,7 +35,8 @@ __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v);
 // The normalised rows y_i = x_i / ||x_i|| are read in two layouts: row-major
 // (Lloyd scans, centroid sums, seeding picks) and dimension-major (the
 // point-per-lane seeding and final distances).  FP64 input: both are
-// materialised as FP64.  FP32 input: the row-major source is the caller's X
+// materialised as FP64.  FP32 input: the row-major FP64 copy serves the
+// centroid sums only; the Lloyd scans and seeding picks read the caller's X
 // itself and the dimension-major copy is a transposed FP32 X (half the bytes of
 // every pass), with the divisor b_i of each row (its norm, or 1.0 for a zero
 // row or without normalisation) and r_i = RN(1/b_i); the kernels redo the
@@ -119,7 +120,7 @@ k_rownorm(int64_t n, int dim, const TX* __restrict__ X, int64_t ldx, int normali
                         const int dd = q / TH, r = q % TH;
                         if (dd < nd && row0 + r < n) Yt[(int64_t)(d0 + dd) * n + row0 + r] = (TX)xs[dd][r];
                     }
-                if (!RAW)
+                if (Y)
                     for (int q = t; q < TH * RN_DC; q += TH) { // row-major: dimensions fastest
                         const int r = q / RN_DC, dd = q % RN_DC;
                         if (dd < nd && row0 + r < n) Y[(row0 + r) * dim + d0 + dd] = xs[dd][r];
@@ -1043,126 +1044,91 @@ k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
     }
 }
 
-// Centroid update.  The members of cluster (r, j), in ascending vertex order
-// (the stable sort by label keeps vertex order), are cut into consecutive
-// blocks of KM_BLOCK; each block is summed in order from 0.0 by one thread per
-// dimension, then the block sums are added in order and divided by the count.
-// Only clusters whose member list changed since their last update are summed
-// again (an unchanged list gives a bitwise identical sum).
-constexpr int KM_BLOCK = 256;
-
+// Centroid update.  Dimension d of centroid (r, j) is one FP64 chain: from
+// 0.0, y_id of every member i of cluster j added in ascending vertex order
+// (the stable sort by label keeps vertex order within a label), then divided
+// by the member count.  A wave owns one cluster and 64 consecutive
+// dimensions (lane = dimension): the member ids and their row divisors are
+// wave-uniform scalar loads, a member's coordinates are one contiguous read
+// across the lanes, and the loads of U members are issued ahead of their
+// additions.  Only clusters whose member list changed since their last update
+// are summed again (an unchanged list gives a bitwise identical sum); an empty
+// cluster keeps its centroid.
 __device__ inline bool km_needs_update(int64_t rj, int K, const int* active, const int* dirty,
                                        const int64_t* seg) {
     return active[rj / K] && dirty[rj] && seg[2 * rj + 1] > seg[2 * rj];
 }
 
-// blocks per cluster (0 when the cluster is not recomputed)
-__global__ void k_block_counts(int K, int R, const int64_t* __restrict__ seg,
-                               const int* __restrict__ active, const int* __restrict__ dirty,
-                               int* __restrict__ nblk) {
-    const int64_t rj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (rj >= (int64_t)R * K) return;
-    const int64_t cnt = seg[2 * rj + 1] - seg[2 * rj];
-    nblk[rj] = km_needs_update(rj, K, active, dirty, seg) ? (int)((cnt + KM_BLOCK - 1) / KM_BLOCK) : 0;
-}
-
-// exclusive scan of the block counts (one workgroup); boff[m] = total
-__global__ void __launch_bounds__(TH)
-k_block_offsets(int m, const int* __restrict__ nblk, int* __restrict__ boff) {
-    __shared__ int part[TH];
-    const int per = (m + TH - 1) / TH;
-    const int lo = min(m, (int)threadIdx.x * per), hi = min(m, lo + per);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += nblk[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int t = 0; t < TH; ++t) {
-            const int v = part[t];
-            part[t] = acc;
-            acc += v;
-        }
-        boff[m] = acc;
-    }
-    __syncthreads();
-    int acc = part[threadIdx.x];
-    for (int i = lo; i < hi; ++i) {
-        boff[i] = acc;
-        acc += nblk[i];
-    }
-}
-
-// block list: slot -> (cluster, block index)
-__global__ void k_block_list(int m, const int* __restrict__ nblk, const int* __restrict__ boff,
-                             int* __restrict__ brj, int* __restrict__ bidx) {
-    const int rj = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rj >= m) return;
-    const int o = boff[rj];
-    for (int b = 0; b < nblk[rj]; ++b) {
-        brj[o + b] = rj;
-        bidx[o + b] = b;
-    }
-}
-
-// block sums: a slot is ceil(dim / 64) whole waves, lane = dimension within the
-// wave's 64, so the member ids and their divisors are wave-uniform (scalar
-// loads) and a member row is read contiguously by the wave's lanes
-template <class TT>
-__global__ void __launch_bounds__(TH)
-k_centroid_blocks(int dim, int m, const TT* __restrict__ Y, int64_t ldy, const YDiv* __restrict__ dv,
-                  const uint32_t* __restrict__ members,
-                  const int64_t* __restrict__ seg, const int* __restrict__ boff,
-                  const int* __restrict__ brj, const int* __restrict__ bidx,
-                  double* __restrict__ bsum) {
+// One wave per (cluster, 64-dimension slab).  The rows are the FP64 copy of
+// y (row stride dim), so the chain itself is one addition per member.  The
+// members come in batches of CS_B (one id per lane): the rows of batch b + 1
+// and the ids of batch b + 2 are requested before batch b is added, so the
+// chain rarely waits; every load is clamped to the last member.
+constexpr int CS_B = 32;
+__global__ void __launch_bounds__(64)
+k_centroid_sum(int dim, int K, int R, const double* __restrict__ Y,
+               const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
+               const int* __restrict__ active, const int* __restrict__ dirty,
+               double* __restrict__ C) {
     const int wps = (dim + 63) / 64;
-    const int wv = uniform((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    const int slot = uniform(wv / wps);
-    if (slot >= boff[m]) return;
-    const int d = (wv - slot * wps) * 64 + (int)(threadIdx.x & 63);
+    const int64_t rj = blockIdx.x / wps;
+    if (rj >= (int64_t)R * K) return;
+    if (!km_needs_update(rj, K, active, dirty, seg)) return;
+    const int lane = (int)threadIdx.x;
+    const int d = (int)(blockIdx.x - rj * wps) * 64 + lane;
     const bool dl = d < dim;
     const int dd = dl ? d : dim - 1;
-    const int rj = brj[slot];
-    const int64_t lo = seg[2 * (int64_t)rj] + (int64_t)bidx[slot] * KM_BLOCK;
-    const int64_t hi = min(seg[2 * (int64_t)rj + 1], lo + KM_BLOCK);
+    const int64_t lo = seg[2 * rj];
+    const int64_t cnt = seg[2 * rj + 1] - lo;       // >= 1
     const uint32_t* mem = members + lo;
-    const int cnt = (int)(hi - lo);
+    const double* Yd = Y + dd;
+    const int64_t nb = (cnt + CS_B - 1) / CS_B;
+    auto ids_of = [&](int64_t b) -> int {
+        return (int)mem[min<int64_t>(b * CS_B + (lane & (CS_B - 1)), cnt - 1)];
+    };
+    // two register sets: while one batch is added, the next one's rows are
+    // in flight (scheduling barriers keep the compiler from sinking the loads
+    // below the additions)
+    double va[CS_B], vb[CS_B];
+    auto rows = [&](double* v, int iv) {
+#pragma unroll
+        for (int q = 0; q < CS_B; ++q)
+            v[q] = Yd[(int64_t)(uint32_t)__builtin_amdgcn_readlane(iv, q) * dim];
+    };
+    // the ids of a batch are requested before the rows of the batch before
+    // it, so waiting for them never waits for rows still in flight
+    int i1 = ids_of(1);
+    rows(va, ids_of(0));                            // batch 0
     double s = 0.0;
-    int p = 0;
-    constexpr int U = 16;
-    for (; p + U <= cnt; p += U) {
-        uint32_t id[U];
-        TT v[U];
+    int64_t b = 0;
+    for (; b + 2 < nb; b += 2) {                    // batches b, b + 1 full; b + 2 exists
+        const int i2 = ids_of(b + 2);
+        rows(vb, i1);                               // batch b + 1
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < U; ++q) id[q] = uniform((int)mem[p + q]);
+        for (int q = 0; q < CS_B; ++q) s += va[q];  // batch b
+        __builtin_amdgcn_sched_barrier(0);
+        i1 = ids_of(b + 3);
+        rows(va, i2);                               // batch b + 2
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < U; ++q) v[q] = Y[(int64_t)id[q] * ldy + dd];
-#pragma unroll
-        for (int q = 0; q < U; ++q) s += ycoord(v[q], ydiv_of<TT>(dv, id[q]));
+        for (int q = 0; q < CS_B; ++q) s += vb[q];  // batch b + 1
+        __builtin_amdgcn_sched_barrier(0);
     }
-    for (; p < cnt; ++p) {
-        const uint32_t id = uniform((int)mem[p]);
-        s += ycoord(Y[(int64_t)id * ldy + dd], ydiv_of<TT>(dv, id));
+    // one or two batches left: b (in va; full if b + 1 < nb), then b + 1
+    if (b + 1 < nb) {
+        rows(vb, i1);
+#pragma unroll
+        for (int q = 0; q < CS_B; ++q) s += va[q];
+#pragma unroll
+        for (int q = 0; q < CS_B; ++q) va[q] = vb[q];
+        ++b;
     }
-    if (dl) bsum[(int64_t)slot * dim + d] = s;
-}
-
-// centroid (r, j), dimension d: block sums in order, divided by the count
-__global__ void __launch_bounds__(TH)
-k_centroid_total(int dim, int K, int R, const int64_t* __restrict__ seg,
-                 const int* __restrict__ active, const int* __restrict__ dirty,
-                 const int* __restrict__ nblk, const int* __restrict__ boff,
-                 const double* __restrict__ bsum, double* __restrict__ C) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)R * K * dim) return;
-    const int d = (int)(e % dim);
-    const int64_t rj = e / dim;
-    if (!km_needs_update(rj, K, active, dirty, seg)) return;
-    const int64_t cnt = seg[2 * rj + 1] - seg[2 * rj];
-    const int64_t o = boff[rj];
-    double c = 0.0;
-    for (int b = 0; b < nblk[rj]; ++b) c += bsum[(o + b) * dim + d];
-    C[e] = c / (double)cnt;
+    const int rest = (int)(cnt - b * CS_B);          // 1 .. CS_B members in the last batch
+#pragma unroll
+    for (int q = 0; q < CS_B; ++q)
+        if (q < rest) s += va[q];
+    if (dl) C[rj * dim + d] = s / (double)cnt;
 }
 
 // exact squared distance of every point to its assigned centre, reading the
@@ -1282,9 +1248,9 @@ struct KmWs {
     uint64_t *tsum, *lhist, *lscan_tmp;
     uint32_t *vals, *pts, *fl;
     int32_t* lab;
-    int *changed, *active, *cnt, *fcnt, *status, *dirty, *nblk, *boff, *brj, *bidx;
+    int *changed, *active, *cnt, *fcnt, *status, *dirty;
     int64_t* seg;
-    double *bsum, *ccur, *hsv;
+    double *ccur, *hsv;
     float* secf;
     uint16_t* hsi;
     void* Yt;        // dimension-major copy: FP64 y, or FP32 x with the divisors dv
@@ -1292,7 +1258,6 @@ struct KmWs {
     bool yt32;       // FP32 input: Ysrc is the caller's X (row stride ldy), Yt and dv as above
     const void* Ysrc;
     int64_t ldy;
-    int64_t max_blocks;
     int Rpad;
     unsigned long long *m2, *q;
 };
@@ -1327,13 +1292,6 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.status = c.take<int>(1);
     w.dirty = c.take<int>((size_t)R * K);
     w.seg = c.take<int64_t>(2 * (size_t)R * K);
-    // blocks of all clusters: sum over clusters of ceil(count / KM_BLOCK)
-    w.max_blocks = (int64_t)R * ceil_div(n, KM_BLOCK) + (int64_t)R * K;
-    w.nblk = c.take<int>((size_t)R * K);
-    w.boff = c.take<int>((size_t)R * K + 1);
-    w.brj = c.take<int>((size_t)w.max_blocks);
-    w.bidx = c.take<int>((size_t)w.max_blocks);
-    w.bsum = c.take<double>((size_t)w.max_blocks * dim);
     w.Rpad = seed_stride(R);
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
     w.hsv = c.take<double>((size_t)R * K * K);
@@ -1484,7 +1442,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     w.ldy = w.yt32 ? ldx : dim;
     if (opts->x_fp32)
         hipLaunchKernelGGL((k_rownorm<float>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
-                           static_cast<const float*>(X), ldx, opts->normalize_rows, nullptr,
+                           static_cast<const float*>(X), ldx, opts->normalize_rows, w.Y,
                            static_cast<float*>(w.Yt), w.dv, w.m2, w.status);
     else
         hipLaunchKernelGGL((k_rownorm<double>), dim3(ceil_div(n, TH)), dim3(TH), 0, st, n, dim,
@@ -1568,25 +1526,9 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                                nullptr, nullptr, w.lhist, lt, w.vals);
             SC_CHECK_LAUNCH(ctx);
         }
-        {
-            const int m = R * K;
-            hipLaunchKernelGGL(k_block_counts, dim3(ceil_div(m, TH)), dim3(TH), 0, st, K, R, w.seg,
-                               w.active, w.dirty, w.nblk);
-            hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(TH), 0, st, m, w.nblk, w.boff);
-            hipLaunchKernelGGL(k_block_list, dim3(ceil_div(m, TH)), dim3(TH), 0, st, m, w.nblk,
-                               w.boff, w.brj, w.bidx);
-            const dim3 gblk((unsigned)ceil_div(w.max_blocks * ceil_div(dim, 64) * 64, TH));
-            if (w.yt32)
-                hipLaunchKernelGGL(k_centroid_blocks<float>, gblk, dim3(TH), 0, st, dim, m,
-                                   static_cast<const float*>(w.Ysrc), w.ldy, w.dv, w.vals, w.seg,
-                                   w.boff, w.brj, w.bidx, w.bsum);
-            else
-                hipLaunchKernelGGL(k_centroid_blocks<double>, gblk, dim3(TH), 0, st, dim, m,
-                                   static_cast<const double*>(w.Ysrc), w.ldy, w.dv, w.vals, w.seg,
-                                   w.boff, w.brj, w.bidx, w.bsum);
-            hipLaunchKernelGGL(k_centroid_total, gcent, dim3(TH), 0, st, dim, K, R, w.seg, w.active,
-                               w.dirty, w.nblk, w.boff, w.bsum, w.C);
-        }
+        hipLaunchKernelGGL(k_centroid_sum, dim3((unsigned)((int64_t)R * K * ceil_div(dim, 64))),
+                           dim3(64), 0, st, dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+        SC_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(k_delta, dim3((unsigned)ceil_div((int64_t)R * K, TH / 64)), dim3(TH), 0, st, K,
                            R, dim, w.C, w.Cold, w.active, w.dirty, w.delta);
         hipLaunchKernelGGL(k_delta_max, dim3(R), dim3(64), 0, st, K, w.active, w.delta, w.dinfo);
