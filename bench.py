@@ -30,6 +30,7 @@ from types import SimpleNamespace
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+X0_SEED, X0_STREAM = 1, 2       # key of the start block's Philox stream
 
 
 def log(*a):
@@ -75,52 +76,123 @@ def spmm_traffic(cfg_name, launches_bytes):
         return None
 
 
-def cpu_baseline(g0, cfg, gpu_iters, sample_div=(128, 64), combinatorial=False):
-    """Oracle timed on the host, on a bounded sample of the workload: its
-    graph build and Laplacian on the full graph, then its LOBPCG start-up and
-    one iteration on two smaller graphs of the same generator (n/128 and
-    n/64 vertices, same k, degree and block structure).  Start-up and
-    per-iteration times are fitted as a + b n over the two samples and
-    extrapolated to the full n; one partition = graph + start-up + the GPU
-    solve's iteration count times the per-iteration time."""
-    import numpy as np
-    import oracle
-    from synth import dcsbm, gaussian_block
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    def lap(g):
-        return oracle.laplacian_combinatorial(g) if combinatorial else (oracle.laplacian(g)[0], None)
+def host_info():
+    """Host CPU of this run: logical CPUs, model name and sockets (lscpu)."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Thread(s) per core", "Core(s) per socket"):
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
 
+
+def cpu_record_path(name):
+    return os.path.join(HERE, "profiles", f"cpu_baseline_{name}.json")
+
+
+def record_cpu_baseline(args, cfg, g0):
+    """One-time full-size measurement of the oracle on this host, written to
+    profiles/cpu_baseline_<workload>.json: graph build + Laplacian, one SpMM
+    with the k-column block, LOBPCG start-up and one iteration, and k-means
+    (row normalisation, one restart's seeding with its first assignment, one
+    Lloyd update), all on the full graph and its k = B eigenvector block."""
+    import oracle
+    from synth import gaussian_block, kmeans_draws
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n, k = g0.n, cfg["k"]
+    os.environ.setdefault("ORC_TRACE", "1")
+    log(f"oracle on the full graph: n={n}, k={k}, {threads} threads")
     t0 = time.perf_counter()
     g = oracle.graph_build(g0.n, g0.src, g0.dst)
-    val, _ = lap(g)
+    val, _ = oracle.laplacian(g)
     t_graph = time.perf_counter() - t0
-    del g, val
-    pts = []
-    for div in sample_div:
-        ns = g0.n // div
-        gs0 = dcsbm(ns, cfg["blocks"], cfg["mean_degree"], cfg["intra"], cfg["sizes"],
-                    cfg["alpha"], 1)
-        gs = oracle.graph_build(gs0.n, gs0.src, gs0.dst)
-        vs, ds = lap(gs)
-        X0 = gaussian_block(gs0.n, cfg["k"], 1)
-        t1 = time.perf_counter()
-        oracle.lobpcg(gs, vs, X0, 0, diag=ds)    # CholQR2 + SpMM + initial Rayleigh-Ritz
-        t_init = time.perf_counter() - t1
-        t2 = time.perf_counter()
-        oracle.lobpcg(gs, vs, X0, 1, diag=ds)
-        t_one = max(time.perf_counter() - t2 - t_init, 1e-9)
-        pts.append((ns, t_init, t_one))
-    (n1, i1, o1), (n2, i2, o2) = pts
-    fit = lambda y1, y2: y1 + (y2 - y1) / (n2 - n1) * (g0.n - n1)
-    t_init_full, t_one_full = max(fit(i1, i2), i2), max(fit(o1, o2), o2)
-    est = t_graph + t_init_full + gpu_iters * t_one_full
-    return {"value": round(est, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle graph build + Laplacian on the full graph ({t_graph:.1f} s); "
-                       f"LOBPCG start-up and one iteration timed on graphs of n={n1} "
-                       f"({i1:.2f} s, {o1:.2f} s) and n={n2} ({i2:.2f} s, {o2:.2f} s) of the same "
-                       f"generator and k, extrapolated linearly in n to {t_init_full:.1f} s and "
-                       f"{t_one_full:.1f} s per iteration, times the GPU solve's {gpu_iters} "
-                       f"iterations; k-means not included")}
+    log(f"graph build + Laplacian {t_graph:.1f} s")
+    X0 = gaussian_block(n, k, 1)
+    t0 = time.perf_counter()
+    Y = oracle.spmm(g, val, X0)
+    t_spmm = time.perf_counter() - t0
+    del Y
+    log(f"SpMM {t_spmm:.1f} s")
+    r = oracle.lobpcg(g, val, X0, 1, 0.0)
+    del X0
+    log(f"LOBPCG start-up {r.seconds_setup:.1f} s, one iteration {r.seconds_iters:.1f} s")
+    km = oracle.kmeans(r.X, k, kmeans_draws(1, k, 1), max_iter=1)
+    t_norm, t_seed, t_lloyd, n_lloyd = km.timing
+    log(f"k-means: normalisation {t_norm:.1f} s, seeding {t_seed:.1f} s, "
+        f"{n_lloyd} Lloyd update {t_lloyd:.1f} s")
+    rec = {
+        "workload": args.config, "n": n, "nnz": int(g.nnz), "k": k, "kind": "oracle",
+        "threads": threads, "host": host_info(),
+        "seconds": {"graph_build_laplacian": round(t_graph, 3), "spmm": round(t_spmm, 3),
+                    "lobpcg_setup": round(r.seconds_setup, 3),
+                    "lobpcg_iteration": round(r.seconds_iters, 3),
+                    "kmeans_normalise": round(t_norm, 3),
+                    "kmeans_seeding_per_restart": round(t_seed, 3),
+                    "kmeans_lloyd_update": round(t_lloyd / max(n_lloyd, 1), 3)},
+        "command": f"OMP_NUM_THREADS={threads} python bench.py --config {args.config} "
+                   "--record-cpu-baseline",
+    }
+    with open(cpu_record_path(args.config), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    return rec
+
+
+def cpu_baseline(g0, cfg, name, gpu_iters, restarts, lloyd_iters, combinatorial=False):
+    """The oracle on this host's cores for one partition of the workload.
+    Timed live on the full graph (a bounded sample, about 10 s of CPU work):
+    graph build + Laplacian, and one SpMM with the k-column block.  The
+    phases too long to repeat in every run come from the full-size record
+    profiles/cpu_baseline_<workload>.json (measured once on a GPU machine's host
+    by record_cpu_baseline): LOBPCG start-up and per-iteration time, k-means
+    normalisation, per-restart seeding and per-Lloyd-update time.  One
+    partition = graph + start-up + the GPU solve's iterations x iteration +
+    normalisation + restarts x seeding + restarts x the GPU's Lloyd updates
+    (of its slowest restart, so an upper estimate) x update."""
+    import oracle
+    from synth import gaussian_block
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    g = oracle.graph_build(g0.n, g0.src, g0.dst)
+    val, diag = oracle.laplacian_combinatorial(g) if combinatorial else (oracle.laplacian(g)[0], None)
+    t_graph = time.perf_counter() - t0
+    X0 = gaussian_block(g0.n, cfg["k"], 1)
+    t0 = time.perf_counter()
+    oracle.spmm(g, val, X0, diag)
+    t_spmm = time.perf_counter() - t0
+    del g, val, X0
+    try:
+        with open(cpu_record_path(name)) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        rec = None
+    if rec is None or rec.get("n") != g0.n or rec.get("k") != cfg["k"] or combinatorial:
+        return {"value": None, "unit": "s", "cores": threads, "kind": "oracle",
+                "sample": (f"live on the full graph: graph build + Laplacian {t_graph:.1f} s, "
+                           f"one SpMM with k={cfg['k']} columns {t_spmm:.1f} s; no full-size "
+                           f"record of the other phases for this workload")}
+    sec = rec["seconds"]
+    value = (t_graph + sec["lobpcg_setup"] + gpu_iters * sec["lobpcg_iteration"]
+             + sec["kmeans_normalise"] + restarts * sec["kmeans_seeding_per_restart"]
+             + restarts * lloyd_iters * sec["kmeans_lloyd_update"])
+    return {"value": round(value, 1), "unit": "s", "cores": threads, "kind": "oracle",
+            "host": host_info(),
+            "sample": (f"oracle on the full graph (n={g0.n}, k={cfg['k']}). Live in this run: "
+                       f"graph build + Laplacian {t_graph:.1f} s, one SpMM {t_spmm:.1f} s (the "
+                       f"record's: {sec['spmm']:.1f} s). From the full-size record "
+                       f"profiles/cpu_baseline_{name}.json ({rec['threads']} threads on "
+                       f"{rec['host'].get('Model name', '?')}): LOBPCG start-up "
+                       f"{sec['lobpcg_setup']:.1f} s + {gpu_iters} iterations x "
+                       f"{sec['lobpcg_iteration']:.1f} s; k-means normalisation "
+                       f"{sec['kmeans_normalise']:.1f} s + {restarts} restarts x seeding "
+                       f"{sec['kmeans_seeding_per_restart']:.1f} s + {restarts} x {lloyd_iters} "
+                       f"Lloyd updates x {sec['kmeans_lloyd_update']:.1f} s (the GPU's count for "
+                       f"its slowest restart: an upper estimate)")}
 
 
 def run_serve(args):
@@ -172,6 +244,7 @@ def run_serve(args):
         st["final_stage_PM"] = {z: round(float(np.mean(v)), 4) for z, v in pm.items()}
         passes[mode] = {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in st.items()}
         log(f"{mode}: {passes[mode]}")
+    be.close()
     w, c = passes["warm"], passes["cold"]
     out = {
         "metric": "LOBPCG time-to-partition at rel-residual 1e-2; SpMM HBM GB/s; p99 solve latency",
@@ -194,16 +267,18 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
-def compare_fp64(args, api, ctx, cfg, n, k, src, dst, X0h, draws, res, km, t_mixed, truth):
-    """The same graph and start block in FP64: timing and the differences."""
+def compare_fp64(args, api, ctx, cfg, n, k, src, dst, draws, res, km, t_mixed, truth):
+    """The same graph and start block (the same Philox stream, in FP64) in
+    FP64: timing and the differences."""
     import numpy as np
     import torch
     from paper_1708_07481_amd.metrics import partition_scores
-    X0 = torch.from_numpy(X0h).to(src.device)
+    X0 = torch.empty((n, k), dtype=torch.float64, device=src.device)
 
     def step():
         gd = api.graph_build(ctx, n, src, dst)
         v64, _, _ = api.laplacian_csr(ctx, gd, True, False)
+        api.randn(ctx, n, k, X0_SEED, X0_STREAM, "normal", torch.float64, out=X0)
         r = api.lobpcg_solve(ctx, gd, v64, X0, cfg["maxit"], cfg["tol"], "fp64")
         kk = api.kmeans_assign(ctx, r.X, k, draws, max_iter=100)
         return r, kk
@@ -275,6 +350,9 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also solve the same graph from the same start block in FP64 and report "
                          "speedup, eigenvalue error, subspace sine and accuracy of both")
+    ap.add_argument("--record-cpu-baseline", action="store_true",
+                    help="time the oracle once on the full graph (several minutes, host only) "
+                         "and write profiles/cpu_baseline_<config>.json")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, run a plain 512 MiB device copy three times "
                          "(reference kernel for the HBM byte counters)")
@@ -294,7 +372,7 @@ def main():
     import torch
     from paper_1708_07481_amd import api
     from paper_1708_07481_amd.metrics import partition_scores
-    from synth import gaussian_block, kmeans_draws
+    from synth import kmeans_draws
     from synth.configs import config, graph_for
 
     cfg = config(args.config)
@@ -310,14 +388,17 @@ def main():
     t = time.perf_counter()
     g0 = graph_for(args.config, seed=1)
     log(f"graph: m={g0.m} in {time.perf_counter() - t:.1f} s")
+    if args.record_cpu_baseline:
+        rec = record_cpu_baseline(args, cfg, g0)
+        print(json.dumps(rec), flush=True)
+        return
     kb = k + args.extra_cols
-    X0h = gaussian_block(n, kb, 1)
     draws_h = kmeans_draws(restarts, k, 1)
 
     dev = torch.device("cuda:0")
     src = torch.from_numpy(g0.src).to(dev)
     dst = torch.from_numpy(g0.dst).to(dev)
-    X0 = torch.from_numpy(X0h.astype(np.float64 if fp64 else np.float32)).to(dev)
+    X0 = torch.empty((n, kb), dtype=torch.float64 if fp64 else torch.float32, device=dev)
     draws = torch.from_numpy(draws_h.view(np.int64)).to(dev)
     ctx = api.Context(0)
 
@@ -332,6 +413,8 @@ def main():
         else:
             v64, v32, _ = api.laplacian_csr(ctx, gd, fp64, not fp64)
         val = v64 if fp64 else v32
+        # Gaussian start block from the device Philox stream (Section III)
+        api.randn(ctx, n, kb, X0_SEED, X0_STREAM, "normal", X0.dtype, out=X0)
         res = api.lobpcg_solve(ctx, gd, val, X0, cfg["maxit"], cfg["tol"], prec, diag=diag,
                                lock_tol=args.lock_tol, k_conv=k if kb > k else 0)
         kc = k
@@ -435,7 +518,7 @@ def main():
             "algorithmic_gflop": round(gflop, 1),
             "counters": gram_counters(args.config) if (prec == "fp32" and k == 160) else None}]
     if args.compare and not fp64:
-        out["precision_comparison"] = compare_fp64(args, api, ctx, cfg, n, k, src, dst, X0h, draws,
+        out["precision_comparison"] = compare_fp64(args, api, ctx, cfg, n, k, src, dst, draws,
                                                    res, km, total / args.steps, g0.truth)
     if args.calibrate_copy:
         x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
@@ -444,10 +527,13 @@ def main():
             torch.mul(x, 1.0, out=y)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+    out["hip_runtime"] = api.runtime_info()
+    ctx.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         try:
-            out["cpu_baseline"] = cpu_baseline(g0, cfg, res.iterations, combinatorial=comb)
+            out["cpu_baseline"] = cpu_baseline(g0, cfg, args.config, res.iterations, restarts,
+                                               km.lloyd_iterations or 0, combinatorial=comb)
         except Exception as e:  # the GPU result stands on its own
             out["cpu_baseline"] = {"value": None, "error": str(e)}
     print(json.dumps(out), flush=True)

@@ -64,13 +64,26 @@ typedef enum { SC_PREC_FP64 = 0, SC_PREC_FP32 = 1, SC_PREC_FP32_BF16GRAM = 2 } s
 typedef struct sc_ctx sc_ctx;
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  Host memory only. */
+ * (a hipStream_t; NULL = the default stream).  Host memory only.  Fails with
+ * SC_E_HIP when more than one HIP runtime is mapped into the process (see
+ * sc_runtime_info). */
 sc_status sc_ctx_create(int device, void* hip_stream, sc_ctx** out);
+/* Synchronises the context's stream, then frees its events and pinned host
+ * buffer.  Call it while the HIP runtime is alive, i.e. before the program
+ * starts its exit: not from process-exit handlers or finalisers. */
 sc_status sc_ctx_destroy(sc_ctx* ctx);
 /* Text of the last error on this context ("" if none).  Host string owned by ctx. */
 const char* sc_last_error(const sc_ctx* ctx);
 /* Library ABI version (major * 10000 + minor * 100 + patch). */
 int sc_version(void);
+/* The HIP runtime this process runs the library on (host outputs, any may be
+ * NULL): hipRuntimeGetVersion's value, the number of distinct libamdhip64
+ * objects mapped into the process (1 when the library shares the runtime of
+ * the program that loaded it; 2 means two runtimes, which must not happen),
+ * and the file path of the one that resolves the library's HIP calls,
+ * truncated to path_len - 1 bytes.  Needs no device and no context. */
+sc_status sc_runtime_info(int* hip_runtime_version, int* hip_libs_mapped, char* path,
+                          size_t path_len);
 
 /* ------------------------------------------------------------------------
  * Graph construction: W <- W + W' (Section II-A).
@@ -133,8 +146,9 @@ sc_status sc_laplacian_csr(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* r
  *   val32    float32 [nnz] (out) or NULL: val64 rounded to nearest
  *   diag32   float32 [n] (out) or NULL: the degrees rounded to nearest, the
  *            diagonal of FP32 products
- * Pass the diagonal to sc_spmm_diag / sc_lobpcg_opts.diag, with
- * sc_lobpcg_opts.op_norm = 2 max_i d_i (Gershgorin bound of ||D - W||).
+ * Pass the diagonal to sc_spmm_diag / sc_lobpcg_opts.diag; with
+ * sc_lobpcg_opts.op_norm = 0 the solver bounds ||D - W|| by 2 max_i d_i
+ * (Gershgorin), computed on the device.
  * No synchronisation.
  */
 sc_status sc_laplacian_combinatorial(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
@@ -182,7 +196,9 @@ typedef struct {
                               float32), device; NULL = unit diagonal, i.e. the
                               normalised Laplacian I - D^-1/2 W D^-1/2 */
     double op_norm;        /* upper bound of ||L|| in relres_j = ||r_j|| / (op_norm
-                              ||x_j||) (0 = default 2, the normalised Laplacian's) */
+                              ||x_j||); 0 = default: 2 (the normalised Laplacian's
+                              bound) without diag, 2 max_i |diag_i| (Gershgorin,
+                              computed on the device) with diag */
     int k_conv;            /* the stopping test (and info.max_relres) covers columns
                               0 .. k_conv-1 only (0 = all k): a block wider than the
                               wanted pairs, as Section IV runs l slightly above k */
@@ -250,9 +266,11 @@ sc_status sc_lobpcg_solve(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* ro
                           const void* X0, void* X_out, double* theta, double* relres_hist,
                           sc_lobpcg_info* info, void* ws, size_t ws_bytes);
 
-/* Step API: the same solver advanced one iteration per call, so that a
- * scheduler can interleave several solves (continuous batching).  The state
- * lives in the workspace; the same buffers must be passed to every call.
+/* Step API: the same solver (Section II-B) advanced one iteration per call,
+ * so that a scheduler can interleave several solves (continuous batching of
+ * the streaming stages of Section III, each warm-started from the previous
+ * stage's eigenvectors).  The iterates live in the workspace; the same
+ * buffers must be passed to every call.
  *   begin: validates, runs the initial CholQR2 / SpMM / Rayleigh-Ritz and the
  *          first residual; *done = 1 if already converged.  Synchronises.
  *   step:  one iteration; *done = 1 when converged or maxit reached.
@@ -276,6 +294,31 @@ sc_status sc_lobpcg_step_async(sc_ctx* ctx, sc_lobpcg_state* state);
 sc_status sc_lobpcg_step_poll(sc_ctx* ctx, sc_lobpcg_state* state, int* ready, int* done);
 sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* state, void* X_out, double* theta,
                         double* relres_hist, sc_lobpcg_info* info);
+
+/* ------------------------------------------------------------------------
+ * Random start block (Section III: LOBPCG starts from random vectors,
+ * Gaussian or uniform on [-1, 1], when no previous eigenvectors exist).
+ * ------------------------------------------------------------------------ */
+typedef enum { SC_RAND_NORMAL = 0, SC_RAND_UNIFORM = 1, SC_RAND_RAW = 2 } sc_rand_dist;
+/*
+ * Fills a rows x cols block (row stride ld >= cols elements, device memory
+ * owned by the caller) from the counter-based Philox4x64-10 generator
+ * (Salmon et al., SC'11) keyed by (seed, stream): word t of the stream is
+ * word t mod 4 of the generator at counter t / 4 + 1, and element
+ * e = row * cols + col uses
+ *   SC_RAND_RAW      word e itself (out is uint64; prec ignored);
+ *   SC_RAND_UNIFORM  (word e >> 11) * 2^-52 - 1, exact in [-1, 1);
+ *   SC_RAND_NORMAL   Box-Muller on words 2p, 2p+1 (p = e / 2):
+ *                    u1 = ((w >> 11) + 1) 2^-53, u2 = (w' >> 11) 2^-53,
+ *                    r = sqrt(-2 ln u1), r cos(2 pi u2) for even e,
+ *                    r sin(2 pi u2) for odd e (device log / sin / cos).
+ * out is float64 for SC_PREC_FP64, float32 (rounded to nearest) otherwise.
+ * Deterministic and independent of the launch shape.  Asynchronous on the
+ * context's stream.  Errors: SC_E_INVAL (sizes, unknown dist or precision,
+ * NULL out with rows > 0).
+ */
+sc_status sc_randn(sc_ctx* ctx, int64_t rows, int cols, int64_t ld, uint64_t seed,
+                   uint64_t stream, int dist, void* out, sc_precision prec);
 
 /* ------------------------------------------------------------------------
  * k-means on the row-normalised eigenvectors (Section II-A labels).
@@ -306,8 +349,9 @@ sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim, const sc_kmeans_o
  *     T = sum w, t = mulhi64(u_j, T), c_j = y[min i : prefix_i > t]
  *     (T = 0: y[mulhi64(u_j, n)]), D2_i <- min(D2_i, |y_i - c_j|^2);
  *   Lloyd: assign to the nearest centroid (squared distance accumulated with
- *     fma in dimension order, ties to the lowest index); centroids = member
- *     sums in ascending vertex order / count (empty clusters keep theirs);
+ *     fma in dimension order, ties to the lowest index); each centroid
+ *     coordinate is one FP64 sum from 0.0 over the members in ascending
+ *     vertex order, divided by the member count (empty clusters keep theirs);
  *     stop when no label changes or after max_iter updates;
  *   best restart: least sum_i floor(mind_i * 2^s), ties to the lowest.
  *   X        float64 (or float32 when opts->x_fp32) n x ldx (device)

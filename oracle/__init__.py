@@ -59,7 +59,8 @@ class LobpcgOpts(C.Structure):
 
 class LobpcgInfo(C.Structure):
     _fields_ = [("iterations", _int), ("converged", _int), ("p_drops", _int),
-                ("locked_cols", _int), ("max_relres", _dbl)]
+                ("locked_cols", _int), ("max_relres", _dbl), ("seconds_setup", _dbl),
+                ("seconds_iters", _dbl)]
 
 
 def _declare(L):
@@ -82,7 +83,7 @@ def _declare(L):
                              C.POINTER(LobpcgInfo)]
     L.orc_kmeans.restype = _int
     L.orc_kmeans.argtypes = [_i64, _int, _p, _i64, _int, _int, _int, _p, _p, _int, _p, _p,
-                             _p, _p, _p, _p]
+                             _p, _p, _p, _p, _p]
     L.orc_cpqr_labels.restype = _int
     L.orc_cpqr_labels.argtypes = [_i64, _int, _p, _i64, _p, _p, _p]
     L.orc_eigengap.restype = _int
@@ -223,6 +224,8 @@ class LobpcgResult:
     p_drops: int
     locked_cols: int
     max_relres: float
+    seconds_setup: float = 0.0     # wall time of the start-up (CholQR2, L X, first RR)
+    seconds_iters: float = 0.0     # wall time of the iterations after it
 
 
 def op_norm_bound(diag) -> float:
@@ -250,7 +253,8 @@ def lobpcg(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL
            "lobpcg")
     it = info.iterations
     return LobpcgResult(X, theta, rh[: it + 1].copy(), th[: it + 1].copy(), it,
-                        bool(info.converged), info.p_drops, info.locked_cols, info.max_relres)
+                        bool(info.converged), info.p_drops, info.locked_cols, info.max_relres,
+                        info.seconds_setup, info.seconds_iters)
 
 
 def lobpcg_status(g: CSR, val, X0, maxit, tol=0.0, lock_tol=LOCK_TOL, chol_tol=CHOL_TOL) -> int:
@@ -274,6 +278,9 @@ class KmeansResult:
     inertia_q: int
     best_restart: int
     lloyd_iters: int
+    # wall seconds of normalisation, seedings (+ first assignment), Lloyd updates,
+    # and the number of Lloyd updates, all restarts together
+    timing: tuple = (0.0, 0.0, 0.0, 0)
 
 
 def kmeans(X, n_clusters, draws=None, restarts=None, max_iter=100, normalize=True,
@@ -294,10 +301,12 @@ def kmeans(X, n_clusters, draws=None, restarts=None, max_iter=100, normalize=Tru
     iq = np.zeros(1, dtype=np.uint64)
     br = np.zeros(1, dtype=np.int32)
     li = np.zeros(1, dtype=np.int32)
+    tm = np.zeros(4)
     _check(lib().orc_kmeans(n, dim, _ptr(X), dim, n_clusters, restarts, max_iter, _ptr(dr),
                             _ptr(init), int(bool(normalize)), _ptr(labels), _ptr(cent),
-                            _ptr(inertia), _ptr(iq), _ptr(br), _ptr(li)), "kmeans")
-    return KmeansResult(labels, cent, float(inertia[0]), int(iq[0]), int(br[0]), int(li[0]))
+                            _ptr(inertia), _ptr(iq), _ptr(br), _ptr(li), _ptr(tm)), "kmeans")
+    return KmeansResult(labels, cent, float(inertia[0]), int(iq[0]), int(br[0]), int(li[0]),
+                        (float(tm[0]), float(tm[1]), float(tm[2]), int(tm[3])))
 
 
 @dataclass

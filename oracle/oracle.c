@@ -38,14 +38,30 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define ORC_OK 0
 #define ORC_E_INVAL (-1)
 #define ORC_E_NOMEM (-2)
 #define ORC_E_BREAKDOWN (-4)
 #define ORC_E_NUMERIC (-5)
+
+/* Wall-clock seconds (timing of the CPU baseline only; no arithmetic uses it). */
+static double orc_now(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* Progress lines on stderr when the environment sets ORC_TRACE (long runs). */
+static int orc_trace(void) {
+    static int v = -1;
+    if (v < 0) v = getenv("ORC_TRACE") != NULL;
+    return v;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Graph symmetrisation (Section II-A).                                      */
@@ -481,6 +497,9 @@ typedef struct {
     int p_drops;
     int locked_cols;   /* W columns left out in the last iteration */
     double max_relres; /* of the returned X */
+    double seconds_setup;  /* wall time of CholQR2(X0), L X, the first Rayleigh-Ritz step
+                              and residual */
+    double seconds_iters;  /* wall time of the iterations after it */
 } orc_lobpcg_info;
 
 /*
@@ -515,7 +534,9 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
     double *X = S, *W = S + blk, *P = S + 2 * blk;
     double *LX = LS, *LW = LS + blk, *LP = LS + 2 * blk;
     int status = ORC_OK, p_dropped = 0;
-    orc_lobpcg_info inf = {0, 0, 0, 0, 0.0};
+    orc_lobpcg_info inf = {0, 0, 0, 0, 0.0, 0.0, 0.0};
+    const double t_start = orc_now();
+    double t_mark = t_start;
 
     for (int64_t i = 0; i < n; ++i)
         for (int j = 0; j < k; ++j) X[(int64_t)j * n + i] = X0[i * k + j];
@@ -563,6 +584,8 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
         }
         gram_cm(n, K3, S, K3, LS, GA, 1);
         gram_cm(n, K3, S, K3, S, GB, 1);
+        if (orc_trace())
+            fprintf(stderr, "[oracle lobpcg] t=%d Gram products done (%.1f s)\n", t, orc_now() - t_mark);
         status = rayleigh_ritz(k, GA, GB, act3, C, theta, &p_dropped, o->chol_tol);
         if (status != ORC_OK) goto out;
         if (p_dropped) inf.p_drops++;
@@ -625,6 +648,15 @@ int orc_lobpcg(int64_t n, const int64_t* row_ptr, const int32_t* col, const doub
         }
         if (relres_hist) for (int j = 0; j < k; ++j) relres_hist[(int64_t)t * k + j] = relres[j];
         inf.max_relres = mx;
+        {
+            const double now = orc_now();
+            if (t == 0) inf.seconds_setup = now - t_start;
+            else inf.seconds_iters = now - t_start - inf.seconds_setup;
+            if (orc_trace())
+                fprintf(stderr, "[oracle lobpcg] n=%lld k=%d t=%d max relres %.3e (%.1f s)\n",
+                        (long long)n, k, t, mx, now - t_mark);
+            t_mark = now;
+        }
         if (mx <= o->tol || all_locked) { inf.converged = 1; break; }
         if (t == o->maxit) break;
     }
@@ -683,12 +715,15 @@ static uint64_t qweight(double d2, int shift) {
  *              cluster keeps its centroid), stop when no label changes;
  *   choice:    restart with the least integer inertia sum_i floor(mind_i 2^s),
  *              ties to the lowest restart.
+ * timing (optional, [4]): wall seconds of the row normalisation, of the
+ * seedings with their first assignments, of the Lloyd updates, and the number
+ * of Lloyd updates, all restarts together.
  * If init_centroids != NULL it replaces the seeding (restarts must be 1).
  */
 int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int restarts, int max_iter,
                const uint64_t* draws, const double* init_centroids, int normalize,
                int32_t* labels, double* centroids, double* inertia, uint64_t* inertia_q,
-               int* best_restart, int* lloyd_iters) {
+               int* best_restart, int* lloyd_iters, double* timing) {
     if (n <= 0 || dim <= 0 || K <= 0 || K > n || restarts <= 0 || max_iter < 0 || ldx < dim)
         return ORC_E_INVAL;
     if (init_centroids && restarts != 1) return ORC_E_INVAL;
@@ -700,6 +735,7 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     int32_t* nl = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)K);
     if (!Y || !Cc || !D2 || !pref || !lab || !nl || !cnt) return ORC_E_NOMEM;
+    double t_norm = orc_now(), t_seed = 0.0, t_lloyd = 0.0, n_lloyd = 0.0;
     double m2 = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         const double* x = X + i * ldx;
@@ -722,10 +758,12 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     (void)frexp(4.0 * m2, &e);
     if (m2 == 0.0) e = 0;
     int shift = 61 - ceil_log2_u64((uint64_t)n) - e;
+    t_norm = orc_now() - t_norm;
     uint64_t best_q = UINT64_MAX;
     int best_r = -1, best_iters = 0;
     for (int r = 0; r < restarts; ++r) {
         const uint64_t* u = draws ? draws + (int64_t)r * K : NULL;
+        const double t_r0 = orc_now();
         if (init_centroids) {
             memcpy(Cc, init_centroids, sizeof(double) * (size_t)K * dim);
         } else {
@@ -769,6 +807,8 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
             lab[i] = bj;
             D2[i] = best;
         }
+        const double t_r1 = orc_now();
+        t_seed += t_r1 - t_r0;
         for (int it = 1; it <= max_iter; ++it) {
             for (int j = 0; j < K; ++j) cnt[j] = 0;
             for (int64_t i = 0; i < n; ++i) cnt[lab[i]]++;
@@ -804,6 +844,11 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
             iters = it;
             if (changed == 0) break;
         }
+        t_lloyd += orc_now() - t_r1;
+        n_lloyd += iters;
+        if (orc_trace())
+            fprintf(stderr, "[oracle kmeans] restart %d: seeding %.1f s, %d Lloyd updates %.1f s\n",
+                    r, t_r1 - t_r0, iters, orc_now() - t_r1);
         uint64_t q = 0;
         for (int64_t i = 0; i < n; ++i) q += qweight(D2[i], shift);
         if (q < best_q || best_r < 0) {
@@ -820,6 +865,12 @@ int orc_kmeans(int64_t n, int dim, const double* X, int64_t ldx, int K, int rest
     if (inertia_q) *inertia_q = best_q;
     if (best_restart) *best_restart = best_r;
     if (lloyd_iters) *lloyd_iters = best_iters;
+    if (timing) {
+        timing[0] = t_norm;
+        timing[1] = t_seed;
+        timing[2] = t_lloyd;
+        timing[3] = n_lloyd;
+    }
     free(Y); free(Cc); free(D2); free(pref); free(lab); free(nl); free(cnt);
     return ORC_OK;
 }

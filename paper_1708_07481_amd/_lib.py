@@ -46,6 +46,7 @@ class sc_kmeans_opts(C.Structure):
 
 
 SC_KM_SCAN_AUTO, SC_KM_SCAN_PRUNED, SC_KM_SCAN_FULL = 0, 1, 2
+SC_RAND_NORMAL, SC_RAND_UNIFORM, SC_RAND_RAW = 0, 1, 2
 
 
 SC_KIND_SPMM, SC_KIND_GRAM, SC_KIND_RR, SC_KIND_UPDATE, SC_KIND_CHOLQR, SC_KIND_RESIDUAL, \
@@ -60,6 +61,7 @@ SIGNATURES = {
     "sc_ctx_destroy": (_int, [_p]),
     "sc_last_error": (C.c_char_p, [_p]),
     "sc_version": (_int, []),
+    "sc_runtime_info": (_int, [C.POINTER(_int), C.POINTER(_int), C.c_char_p, _size]),
     "sc_graph_build_workspace": (_int, [_p, _i64, _i64, C.POINTER(_size)]),
     "sc_graph_build": (_int, [_p, _i64, _i64, _p, _p, _p, _int, _p, _p, _p, _p,
                               C.POINTER(_i64), C.POINTER(_i64), _p, _size]),
@@ -89,6 +91,7 @@ SIGNATURES = {
     "sc_warm_fill": (_int, [_p, _i64, _i64, _p, _p, _int, _p, _i64, _int]),
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
+    "sc_randn": (_int, [_p, _i64, _int, _i64, C.c_uint64, C.c_uint64, _int, _p, _int]),
 }
 
 _lib = None

@@ -6,6 +6,7 @@ stream); every step of the computation runs in the HIP library.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 from dataclasses import dataclass
 
 import torch
@@ -65,15 +66,40 @@ class Context:
         self.check(lib().sc_ctx_profile_reset(self.handle), "sc_ctx_profile_reset")
 
     def close(self):
+        """Destroy the library context (synchronises its stream).  Programs
+        call this before they exit: a context still open when the
+        interpreter shuts down is left to the process exit, since the HIP
+        runtime may already be going away then."""
         if getattr(self, "handle", None):
             lib().sc_ctx_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # module globals (sys, lib) may already be gone at interpreter exit
+        if not getattr(self, "handle", None) or _finalizing():
+            return
         try:
             self.close()
         except Exception:
             pass
+
+
+def runtime_info() -> dict:
+    """HIP runtime version, number of libamdhip64 copies mapped into the
+    process and the path of the one the library calls."""
+    v, cnt = C.c_int(), C.c_int()
+    buf = C.create_string_buffer(4096)
+    st = lib().sc_runtime_info(C.byref(v), C.byref(cnt), buf, len(buf))
+    if st != 0:
+        raise SpectralError(st, "sc_runtime_info")
+    return {"hip_runtime_version": v.value, "hip_libs_mapped": cnt.value,
+            "libamdhip64": buf.value.decode()}
 
 
 @dataclass
@@ -185,14 +211,12 @@ def lobpcg_solve(ctx: Context, g: DeviceCSR, val: torch.Tensor, X0: torch.Tensor
                  X_out: torch.Tensor | None = None, diag: torch.Tensor | None = None,
                  op_norm: float = 0.0, k_conv: int = 0) -> LobpcgResult:
     """diag None: the normalised Laplacian (unit diagonal, op_norm 2).  With a
-    diagonal (L = D - W) op_norm defaults to 2 max(diag), the Gershgorin bound."""
+    diagonal (L = D - W) and op_norm 0 the library bounds ||L|| by 2 max(diag)
+    (Gershgorin)."""
     import numpy as np
     n, k = X0.shape
-    if diag is not None:
-        if diag.dtype != X0.dtype:
-            raise TypeError("diag must have X0's dtype")
-        if op_norm <= 0.0:
-            op_norm = 2.0 * float(diag.max()) if diag.numel() else 2.0
+    if diag is not None and diag.dtype != X0.dtype:
+        raise TypeError("diag must have X0's dtype")
     opts = lobpcg_opts(k, maxit, tol, precision, X0.stride(0), lock_tol, chol_tol, diag, op_norm,
                        k_conv)
     nb = lobpcg_workspace(ctx, n, g.nnz, opts)
@@ -319,6 +343,30 @@ def eigengap(ctx: Context, theta: torch.Tensor, sig: float = 10.0):
     ctx.check(lib().sc_eigengap(ctx.handle, k, _ptr(theta), sig, _ptr(cnt), _ptr(ratio)),
               "sc_eigengap")
     return int(cnt.item()), float(ratio.item())
+
+
+def randn(ctx: Context, rows: int, cols: int, seed: int, stream: int = 0,
+          dist: str = "normal", dtype=torch.float64, out: torch.Tensor | None = None,
+          device=None) -> torch.Tensor:
+    """rows x cols block from the device Philox4x64-10 stream keyed (seed,
+    stream): Gaussian (Box-Muller), uniform on [-1, 1), or the raw 64-bit
+    words (dtype int64 holding the uint64 bits)."""
+    code = {"normal": _lib.SC_RAND_NORMAL, "uniform": _lib.SC_RAND_UNIFORM,
+            "raw": _lib.SC_RAND_RAW}[dist]
+    if dist == "raw":
+        dtype = torch.int64
+    elif dtype not in (torch.float64, torch.float32):
+        raise TypeError("dtype must be float64 or float32")
+    if out is None:
+        out = torch.empty((rows, cols), dtype=dtype,
+                          device=device if device is not None else f"cuda:{ctx.device}")
+    if out.shape != (rows, cols) or out.dtype != dtype or out.stride(1) != 1:
+        raise TypeError("out must be a rows x cols block of dtype with unit column stride")
+    prec = SC_PREC_FP64 if dtype in (torch.float64, torch.int64) else SC_PREC_FP32
+    ctx.check(lib().sc_randn(ctx.handle, rows, cols, out.stride(0) if rows else cols,
+                             seed & 0xFFFFFFFFFFFFFFFF, stream & 0xFFFFFFFFFFFFFFFF, code,
+                             _ptr(out), prec), "sc_randn")
+    return out
 
 
 def symeig(ctx: Context, A: torch.Tensor, k: int, ws: torch.Tensor | None = None):

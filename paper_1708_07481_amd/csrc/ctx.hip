@@ -1,4 +1,8 @@
 // Context, error reporting and version of the spectral-clustering library.
+#include <dlfcn.h>
+#include <link.h>
+#include <string.h>
+
 #include "sc_internal.h"
 
 sc_status sc_fail(sc_ctx* ctx, sc_status st, const char* fmt, ...) {
@@ -13,13 +17,58 @@ sc_status sc_fail(sc_ctx* ctx, sc_status st, const char* fmt, ...) {
     return st;
 }
 
-extern "C" int sc_version(void) { return 10000; }
+extern "C" int sc_version(void) { return 10100; }
+
+namespace {
+struct HipLibScan {
+    int count = 0;
+    uintptr_t base[8] = {};
+};
+
+int count_hip_libs(struct dl_phdr_info* info, size_t, void* data) {
+    HipLibScan* s = static_cast<HipLibScan*>(data);
+    const char* name = info->dlpi_name;
+    if (!name || !strstr(name, "libamdhip64")) return 0;
+    // the same object can appear under two names (soname link and file):
+    // count distinct load addresses
+    for (int i = 0; i < s->count && i < 8; ++i)
+        if (s->base[i] == static_cast<uintptr_t>(info->dlpi_addr)) return 0;
+    if (s->count < 8) s->base[s->count] = static_cast<uintptr_t>(info->dlpi_addr);
+    ++s->count;
+    return 0;
+}
+}  // namespace
+
+extern "C" sc_status sc_runtime_info(int* hip_runtime_version, int* hip_libs_mapped, char* path,
+                                     size_t path_len) {
+    if (hip_runtime_version) {
+        int v = 0;
+        if (hipRuntimeGetVersion(&v) != hipSuccess) return SC_E_HIP;
+        *hip_runtime_version = v;
+    }
+    if (hip_libs_mapped) {
+        HipLibScan s;
+        dl_iterate_phdr(count_hip_libs, &s);
+        *hip_libs_mapped = s.count;
+    }
+    if (path && path_len) {
+        Dl_info di{};
+        path[0] = 0;
+        if (dladdr(reinterpret_cast<void*>(&hipGetDeviceCount), &di) && di.dli_fname) {
+            strncpy(path, di.dli_fname, path_len - 1);
+            path[path_len - 1] = 0;
+        }
+    }
+    return SC_OK;
+}
 
 extern "C" sc_status sc_ctx_create(int device, void* hip_stream, sc_ctx** out) {
     if (!out) return SC_E_INVAL;
     *out = nullptr;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return SC_E_INVAL;
+    int libs = 0;
+    if (sc_runtime_info(nullptr, &libs, nullptr, 0) != SC_OK || libs > 1) return SC_E_HIP;
     sc_ctx* c = new sc_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);

@@ -8,6 +8,7 @@
 // (kp = k rounded up to a multiple of 4; pad columns stay zero), the Gram
 // matrices, the small factors, and the per-iteration residual history.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -40,6 +41,23 @@ __global__ void k_load_block(int64_t n, int k, int kp, const Tin* __restrict__ X
         v = (T)x;
     }
     S[i * ld + j] = v;
+}
+
+// bound[0] = 2 max_i |d_i|, Gershgorin's bound on ||D - W|| when d_i is the
+// row sum of W (one workgroup; max is exact in any order)
+template <class T>
+__global__ void __launch_bounds__(1024) k_diag_bound(int64_t n, const T* __restrict__ d,
+                                                     double* __restrict__ bound) {
+    __shared__ double sm[1024];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, fabs((double)d[i]));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bound[0] = 2.0 * sm[0];
 }
 
 template <class T>
@@ -320,10 +338,26 @@ struct Solver {
                            s->n, s->k, s->kp, static_cast<const T*>(X0), s->ldx, S(s), ld, s->status);
         SC_CHECK_LAUNCH(ctx);
         {
-            int* h = static_cast<int*>(ctx->stage);
+            const bool bound = s->diag && s->op_norm <= 0.0;
+            if (bound) {
+                hipLaunchKernelGGL((k_diag_bound<T>), dim3(1), dim3(1024), 0, st, s->n, diag(s),
+                                   s->out_max);
+                SC_CHECK_LAUNCH(ctx);
+            }
+            char* h = static_cast<char*>(ctx->stage);
             SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, sizeof(int), hipMemcpyDeviceToHost, st));
+            if (bound)
+                SC_CHECK_HIP(ctx, hipMemcpyAsync(h + 8, s->out_max, sizeof(double),
+                                                 hipMemcpyDeviceToHost, st));
             SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
-            if (h[0] & DEV_NUMERIC) return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in X0");
+            int flags;
+            memcpy(&flags, h, sizeof flags);
+            if (flags & DEV_NUMERIC) return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: NaN or Inf in X0");
+            if (bound) {
+                memcpy(&s->op_norm, h + 8, sizeof(double));
+                if (!(s->op_norm > 0.0) || !std::isfinite(s->op_norm))
+                    return sc_fail(ctx, SC_E_NUMERIC, "lobpcg: the diagonal has no positive finite entry");
+            }
         }
         // X <- CholQR2(X0)
         for (int rep = 0; rep < 2; ++rep) {
@@ -485,7 +519,9 @@ extern "C" sc_status sc_lobpcg_begin(sc_ctx* ctx, int64_t n, int64_t nnz, const 
     s->col = col;
     s->val = val;
     s->diag = opts->diag;
-    s->op_norm = opts->op_norm > 0 ? opts->op_norm : 2.0;
+    // with a diagonal (L = D - W) and no bound given, begin() computes
+    // 2 max |d_i| on the device
+    s->op_norm = opts->op_norm > 0 ? opts->op_norm : (opts->diag ? 0.0 : 2.0);
     s->k_conv = (opts->k_conv > 0 && opts->k_conv < opts->k) ? opts->k_conv : opts->k;
     s->k = opts->k;
     s->maxit = opts->maxit;

@@ -339,18 +339,23 @@ class SimulatedBackend:
 
 
 def footprint_bytes(n: int, nnz: int, k: int, elem: int, restarts: int = 10,
-                    lobpcg_ws: int | None = None, kmeans_ws: int | None = None) -> int:
+                    lobpcg_ws: int | None = None, kmeans_ws: int | None = None,
+                    graph_ws: int | None = None) -> int:
     """Device bytes of one admitted solve: edges, CSR, Laplacian values, start
-    and result blocks, solver and k-means workspaces (closed-form estimates
-    when the library's exact workspace sizes are not given)."""
+    and result blocks, and the graph-build, solver and k-means workspaces
+    (the library's exact *_workspace sizes; closed-form estimates only where
+    they are not given, as in the CPU scheduling tests)."""
     m = nnz // 2
     kp = (k + 3) // 4 * 4
-    graph = 8 * m + 8 * (n + 1) + 4 * nnz + 8 * n + (8 + 4) * nnz + 8 * n
+    # edges (int32 src, dst), row_ptr, col, degree, values (FP64 and/or FP32), dinv_sqrt
+    graph = 8 * m + 8 * (n + 1) + 4 * nnz + 8 * n + elem * nnz + 8 * n
     if lobpcg_ws is None:
         lobpcg_ws = 2 * n * 3 * kp * elem + 8 * (3 * kp) ** 2 * 12 + 64 * n
     if kmeans_ws is None:
         kmeans_ws = 8 * n * k * 2 + restarts * n * (8 * 6 + 4 * 6)
-    graph_ws = 2 * m * (8 * 3 + 4 * 2) + 64 * m
+    if graph_ws is None:
+        graph_ws = 2 * m * (8 * 3 + 4 * 2) + 64 * m
+    # the graph-build workspace is released before the solve's and k-means's
     return graph + 2 * n * k * elem + lobpcg_ws + max(kmeans_ws, graph_ws)
 
 
@@ -393,7 +398,10 @@ class LibraryBackend:
         ko = sc_kmeans_opts(req.k, self.restarts, self.kmeans_iters, 1, int(elem == 4), 0)
         ctx.check(lib().sc_kmeans_workspace(ctx.handle, req.n, req.k, C.byref(ko), C.byref(kw)),
                   "sc_kmeans_workspace")
-        return footprint_bytes(req.n, nnz_cap, req.k, elem, self.restarts, lw, kw.value)
+        gw = C.c_size_t()
+        ctx.check(lib().sc_graph_build_workspace(ctx.handle, req.n, len(req.src), C.byref(gw)),
+                  "sc_graph_build_workspace")
+        return footprint_bytes(req.n, nnz_cap, req.k, elem, self.restarts, lw, kw.value, gw.value)
 
     def x0(self, req: Request, warm, stream=None, ctx=None, g=None):
         """Start block: the previous stage's eigenvectors or a seeded Gaussian
@@ -413,8 +421,12 @@ class LibraryBackend:
             if self.warm_fill == "neighbors" and g is not None:
                 self.api.warm_fill(ctx, g, x0, n_prev)
             return x0, True
-        from synth import gaussian_block
-        return torch.from_numpy(gaussian_block(req.n, req.k, req.seed)).to(dtype).to(self.dev), False
+        # cold start: a Gaussian block from the device Philox stream keyed by
+        # the request's seed (Section III), on the slot's context
+        X = torch.empty((req.n, req.k), dtype=dtype, device=self.dev)
+        self.api.randn(ctx if ctx is not None else self.ctxs[0], req.n, req.k, req.seed, 2,
+                       "normal", dtype, out=X)
+        return X, False
 
     def start(self, slot: int, req: Request, warm):
         import ctypes as C
@@ -486,6 +498,13 @@ class LibraryBackend:
 
     def release(self, block):
         pass                                  # torch frees the tensor when unreferenced
+
+    def close(self):
+        """Synchronise the slots' streams and destroy their library contexts."""
+        for s in self.streams:
+            s.synchronize()
+        for c in self.ctxs:
+            c.close()
 
     def idle(self, next_arrival, wait):
         if next_arrival is not None:

@@ -23,14 +23,32 @@ def test_header_declares_the_four_calls():
         assert call in names
 
 
-def test_library_exports_every_declared_symbol():
+def _load():
     if not os.path.exists(LIB):
         pytest.fail("libspectral.so is not built (python -m paper_1708_07481_amd.build)")
-    lib = ctypes.CDLL(LIB)
+    # through the binding, which loads torch (and its HIP runtime) first
+    from paper_1708_07481_amd import _lib
+    return _lib.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _load()
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
-    lib.sc_version.restype = ctypes.c_int
-    assert lib.sc_version() == 10000
+    assert lib.sc_version() == 10100
+
+
+def test_one_hip_runtime_is_mapped():
+    """The library resolves its HIP calls to the runtime torch loaded: one
+    libamdhip64 in the process (no device call needed)."""
+    lib = _load()
+    cnt = ctypes.c_int()
+    buf = ctypes.create_string_buffer(4096)
+    assert lib.sc_runtime_info(None, ctypes.byref(cnt), buf, len(buf)) == 0
+    assert cnt.value == 1
+    import torch
+    assert os.path.dirname(os.path.realpath(buf.value.decode())) == \
+        os.path.realpath(os.path.join(os.path.dirname(torch.__file__), "lib"))
 
 
 def test_binding_declares_every_symbol():
