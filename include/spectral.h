@@ -370,6 +370,26 @@ sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X, int64
                            double* inertia, uint64_t* inertia_q, int* best_restart,
                            int* lloyd_iterations, void* ws, size_t ws_bytes);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * k-means as sc_kmeans_assign, same arguments and results bit for bit, with
+ * its scratch in a fixed 64 MiB device array of the library instead of a
+ * caller workspace.  It calls no hipMalloc / hipFree and allocates no host
+ * memory (at most 64 restarts; kernel timing must be off).  Each GPU holds
+ * one copy of the array until the process ends, and every call on that GPU
+ * uses it: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialised by the caller.  Nothing in it needs to start at zero.
+ * Errors: as sc_kmeans_assign, plus SC_E_UNSUPPORTED when the problem needs
+ * more than the fixed scratch (sc_kmeans_workspace > 64 MiB) or more than 64
+ * restarts.
+ */
+sc_status sc_kmeans_assign_static(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx,
+                                  const sc_kmeans_opts* opts, const uint64_t* draws,
+                                  const double* init_centroids, int32_t* labels,
+                                  double* centroids, double* inertia, uint64_t* inertia_q,
+                                  int* best_restart, int* lloyd_iterations);
+
 /* ------------------------------------------------------------------------
  * Kernel timing on the context's stream (HIP events around every launch of
  * the selected kinds).  Used to report per-kernel durations and roofline

@@ -82,6 +82,9 @@ SIGNATURES = {
     "sc_kmeans_assign": (_int, [_p, _i64, _int, _p, _i64, C.POINTER(sc_kmeans_opts), _p, _p, _p,
                                 _p, C.POINTER(_dbl), C.POINTER(C.c_uint64), C.POINTER(_int),
                                 C.POINTER(_int), _p, _size]),
+    "sc_kmeans_assign_static": (_int, [_p, _i64, _int, _p, _i64, C.POINTER(sc_kmeans_opts), _p,
+                                       _p, _p, _p, C.POINTER(_dbl), C.POINTER(C.c_uint64),
+                                       C.POINTER(_int), C.POINTER(_int)]),
     "sc_ctx_set_profiling": (_int, [_p, C.c_uint]),
     "sc_ctx_profile": (_int, [_p, _int, C.POINTER(_i64), C.POINTER(_dbl)]),
     "sc_ctx_profile_reset": (_int, [_p]),

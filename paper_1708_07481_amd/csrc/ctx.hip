@@ -106,7 +106,7 @@ static hipEvent_t ev_get(sc_ctx* ctx) {
 }
 
 ProfScope::ProfScope(sc_ctx* c, int k) : ctx(c), kind(k) {
-    if (!(ctx->prof_mask & (1u << kind))) return;
+    if (kind < 0 || !(ctx->prof_mask & (1u << kind))) return;
     a = ev_get(ctx);
     b = ev_get(ctx);
     if (a && b) (void)hipEventRecord(a, ctx->stream);

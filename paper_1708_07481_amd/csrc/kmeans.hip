@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "sc_internal.h"
@@ -1410,13 +1411,41 @@ extern "C" sc_status sc_kmeans_workspace(sc_ctx* ctx, int64_t n, int dim,
     return SC_OK;
 }
 
-extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X,
-                                      int64_t ldx, const sc_kmeans_opts* opts,
-                                      const uint64_t* draws, const double* init_centroids,
-                                      int32_t* labels, double* centroids, double* inertia,
-                                      uint64_t* inertia_q, int* best_restart,
-                                      int* lloyd_iterations, void* ws, size_t ws_bytes) {
-    if (!ctx) return SC_E_INVAL;
+// Fixed device scratch of the entry point for callers that cannot allocate:
+// one copy per GPU, held until the process ends.  Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t KM_STATIC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[KM_STATIC_BYTES];
+
+namespace {
+
+// Host arrays of one entry per restart: inline storage up to KM_HOST_INLINE
+// restarts, heap beyond (only the entry point with a caller workspace admits
+// more restarts).
+constexpr int KM_HOST_INLINE = 64;
+template <class T>
+struct PerRestart {
+    T inl[KM_HOST_INLINE];
+    std::vector<T> heap;
+    T* p;
+    PerRestart(int R, T v) {
+        if (R <= KM_HOST_INLINE) {
+            p = inl;
+        } else {
+            heap.resize(R);
+            p = heap.data();
+        }
+        for (int r = 0; r < R; ++r) p[r] = v;
+    }
+    T& operator[](int r) { return p[r]; }
+    T* data() { return p; }
+};
+
+sc_status kmeans_run(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx,
+                     const sc_kmeans_opts* opts, const uint64_t* draws,
+                     const double* init_centroids, int32_t* labels, double* centroids,
+                     double* inertia, uint64_t* inertia_q, int* best_restart,
+                     int* lloyd_iterations, void* ws, size_t ws_bytes, bool timed) {
     SC_TRY(km_validate(ctx, n, dim, opts));
     if (ldx < dim) return sc_fail(ctx, SC_E_INVAL, "kmeans: need ldx >= dim");
     if (!X || !labels || !centroids || !ws || (!init_centroids && !draws))
@@ -1433,7 +1462,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     const int64_t nr = n * R;
     const dim3 gnr((unsigned)ceil_div(nr, TH));
     const size_t cent_bytes = (size_t)R * K * dim * sizeof(double);
-    ProfScope ps(ctx, SC_KIND_KMEANS);
+    ProfScope ps(ctx, timed ? SC_KIND_KMEANS : -1);
 
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.m2, 0, sizeof(unsigned long long), st));
     SC_CHECK_HIP(ctx, hipMemsetAsync(w.status, 0, sizeof(int), st));
@@ -1463,7 +1492,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (m2 == 0.0) e = 0;
     const int shift = 61 - ceil_log2_u64((uint64_t)n) - e;
 
-    std::vector<int> act_h(R, 1);
+    PerRestart<int> act_h(R, 1);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(w.active, act_h.data(), R * sizeof(int), hipMemcpyHostToDevice, st));
     // seeding
     if (init_centroids) {
@@ -1507,7 +1536,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     const int bits = ceil_log2_u64((uint64_t)K);
     int n_active = R;
     int iterations = 0;
-    std::vector<int> ch(R), cnt_h(R);
+    PerRestart<int> ch(R, 0), cnt_h(R, 0);
     for (int it = 1; it <= opts->max_iter && n_active > 0; ++it) {
         iterations = it;
         // centroid update from the stable member lists
@@ -1604,7 +1633,7 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
                        st, n,
                        w.D2, shift, w.q);
     SC_CHECK_LAUNCH(ctx);
-    std::vector<unsigned long long> qh(R);
+    PerRestart<unsigned long long> qh(R, 0ull);
     SC_CHECK_HIP(ctx, hipMemcpyAsync(qh.data(), w.q, R * sizeof(unsigned long long),
                                      hipMemcpyDeviceToHost, st));
     SC_CHECK_HIP(ctx, hipStreamSynchronize(st));
@@ -1628,4 +1657,65 @@ extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const voi
     if (best_restart) *best_restart = best;
     if (lloyd_iterations) *lloyd_iterations = iterations;
     return SC_OK;
+}
+
+constexpr int KM_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[KM_MAX_DEVICES] = {};
+
+// Address of this device's scratch (the device must be current), looked up
+// once per device.
+sc_status static_scratch(sc_ctx* ctx, void** out) {
+    if (ctx->device < 0 || ctx->device >= KM_MAX_DEVICES)
+        return sc_fail(ctx, SC_E_UNSUPPORTED, "kmeans_static: device %d", ctx->device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[ctx->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return sc_fail(ctx, SC_E_HIP, "kmeans_static: hipGetSymbolAddress failed: %s",
+                           hipGetErrorString(e));
+        g_scratch_ptr[ctx->device] = p;
+    }
+    *out = g_scratch_ptr[ctx->device];
+    return SC_OK;
+}
+
+}  // namespace
+
+extern "C" sc_status sc_kmeans_assign(sc_ctx* ctx, int64_t n, int dim, const void* X,
+                                      int64_t ldx, const sc_kmeans_opts* opts,
+                                      const uint64_t* draws, const double* init_centroids,
+                                      int32_t* labels, double* centroids, double* inertia,
+                                      uint64_t* inertia_q, int* best_restart,
+                                      int* lloyd_iterations, void* ws, size_t ws_bytes) {
+    return kmeans_run(ctx, n, dim, X, ldx, opts, draws, init_centroids, labels, centroids,
+                      inertia, inertia_q, best_restart, lloyd_iterations, ws, ws_bytes, true);
+}
+
+extern "C" sc_status sc_kmeans_assign_static(sc_ctx* ctx, int64_t n, int dim, const void* X,
+                                             int64_t ldx, const sc_kmeans_opts* opts,
+                                             const uint64_t* draws,
+                                             const double* init_centroids, int32_t* labels,
+                                             double* centroids, double* inertia,
+                                             uint64_t* inertia_q, int* best_restart,
+                                             int* lloyd_iterations) {
+    if (!ctx) return SC_E_INVAL;
+    SC_TRY(km_validate(ctx, n, dim, opts));
+    if (opts->restarts > KM_HOST_INLINE)
+        return sc_fail(ctx, SC_E_UNSUPPORTED, "kmeans_static: restarts %d > %d",
+                       opts->restarts, KM_HOST_INLINE);
+    Carver c(nullptr);
+    KmWs w;
+    const size_t need = carve_km(c, n, dim, opts->n_clusters, opts->restarts, w);
+    if (need > KM_STATIC_BYTES)
+        return sc_fail(ctx, SC_E_UNSUPPORTED,
+                       "kmeans_static: needs %zu bytes of scratch, the fixed scratch holds %zu",
+                       need, KM_STATIC_BYTES);
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    void* ws = nullptr;
+    SC_TRY(static_scratch(ctx, &ws));
+    return kmeans_run(ctx, n, dim, X, ldx, opts, draws, init_centroids, labels, centroids,
+                      inertia, inertia_q, best_restart, lloyd_iterations, ws, KM_STATIC_BYTES,
+                      false);
 }
