@@ -295,6 +295,34 @@ sc_status sc_lobpcg_step_poll(sc_ctx* ctx, sc_lobpcg_state* state, int* ready, i
 sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* state, void* X_out, double* theta,
                         double* relres_hist, sc_lobpcg_info* info);
 
+/*
+ * FP32 product Y = L X (as sc_spmm_diag, FP32) with two options for the
+ * measurements of the product's memory traffic:
+ *   gather  SC_GATHER_FP32: neighbour rows from X itself (the result is then
+ *           bit-identical to sc_spmm_diag); SC_GATHER_FP16 / SC_GATHER_BF16:
+ *           neighbour rows from Xg, a 16-bit copy of X (row stride ldg >= k,
+ *           _Float16 or bfloat16), widened to FP32 on load; a row's own x_ij
+ *           always comes from X.  Half the gathered bytes, at the copy's
+ *           precision.
+ *   order   NULL, or an int32 permutation of the n rows: the row groups of the
+ *           launch take the rows in that order (sc_row_order gives the rows
+ *           longest first, so long rows do not trail the launch).  The
+ *           arithmetic of every row is unchanged.
+ * No synchronisation.
+ */
+typedef enum { SC_GATHER_FP32 = 0, SC_GATHER_FP16 = 1, SC_GATHER_BF16 = 2 } sc_gather;
+sc_status sc_spmm_ex(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                     const int32_t* col, const float* val, const float* diag, int k,
+                     const float* X, int64_t ldx, const void* Xg, int64_t ldg, int gather,
+                     const int32_t* order, float* Y, int64_t ldy);
+/* order[0 .. n) = the rows by descending stored-entry count (row_ptr[i+1] -
+ * row_ptr[i]), stable (equal lengths in ascending row order); a stable LSD
+ * radix sort in the caller's workspace (sc_row_order_workspace bytes).
+ * Requires n < 2^31.  No synchronisation. */
+sc_status sc_row_order_workspace(sc_ctx* ctx, int64_t n, size_t* bytes);
+sc_status sc_row_order(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, int32_t* order, void* ws,
+                       size_t ws_bytes);
+
 /* ------------------------------------------------------------------------
  * Random start block (Section III: LOBPCG starts from random vectors,
  * Gaussian or uniform on [-1, 1], when no previous eigenvectors exist).
@@ -398,7 +426,10 @@ sc_status sc_kmeans_assign_static(sc_ctx* ctx, int64_t n, int dim, const void* X
 typedef enum {
     SC_KIND_SPMM = 0, SC_KIND_GRAM = 1, SC_KIND_RR = 2, SC_KIND_UPDATE = 3,
     SC_KIND_CHOLQR = 4, SC_KIND_RESIDUAL = 5, SC_KIND_GRAPH = 6, SC_KIND_KMEANS = 7,
-    SC_KIND_COUNT = 8
+    SC_KIND_GRAM_FP64ACC = 8,   /* the reduced-precision modes' FP64-accumulated Gram
+                                   recomputation (a predicated launch: about 10 us when
+                                   not needed) */
+    SC_KIND_COUNT = 9
 } sc_kernel_kind;
 /* mask: bit (1 << kind) enables timing of that kind; 0 disables all. */
 sc_status sc_ctx_set_profiling(sc_ctx* ctx, unsigned mask);

@@ -47,12 +47,13 @@ class sc_kmeans_opts(C.Structure):
 
 SC_KM_SCAN_AUTO, SC_KM_SCAN_PRUNED, SC_KM_SCAN_FULL = 0, 1, 2
 SC_RAND_NORMAL, SC_RAND_UNIFORM, SC_RAND_RAW = 0, 1, 2
+SC_GATHER_FP32, SC_GATHER_FP16, SC_GATHER_BF16 = 0, 1, 2
 
 
 SC_KIND_SPMM, SC_KIND_GRAM, SC_KIND_RR, SC_KIND_UPDATE, SC_KIND_CHOLQR, SC_KIND_RESIDUAL, \
-    SC_KIND_GRAPH, SC_KIND_KMEANS = range(8)
+    SC_KIND_GRAPH, SC_KIND_KMEANS, SC_KIND_GRAM_FP64ACC = range(9)
 KIND_NAMES = ["spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual",
-              "graph_build", "kmeans"]
+              "graph_build", "kmeans", "gram_fp64acc"]
 
 
 # name -> (restype, argtypes); every function declared in include/spectral.h
@@ -95,6 +96,10 @@ SIGNATURES = {
     "sc_symeig_workspace": (_int, [_p, _int, _int, C.POINTER(_size)]),
     "sc_symeig": (_int, [_p, _int, _int, _p, _p, _p, _p, _size]),
     "sc_randn": (_int, [_p, _i64, _int, _i64, C.c_uint64, C.c_uint64, _int, _p, _int]),
+    "sc_spmm_ex": (_int, [_p, _i64, _i64, _p, _p, _p, _p, _int, _p, _i64, _p, _i64, _int, _p, _p,
+                          _i64]),
+    "sc_row_order_workspace": (_int, [_p, _i64, C.POINTER(_size)]),
+    "sc_row_order": (_int, [_p, _i64, _p, _p, _p, _size]),
 }
 
 _lib = None

@@ -177,6 +177,37 @@ def spmm(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
     return Y
 
 
+def spmm_ex(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
+            Y: torch.Tensor | None = None, Xg: torch.Tensor | None = None,
+            order: torch.Tensor | None = None, diag: torch.Tensor | None = None) -> torch.Tensor:
+    """FP32 Y = L X with an optional 16-bit gather copy Xg (float16 or
+    bfloat16) and an optional row order (int32 permutation)."""
+    n, k = X.shape
+    if X.dtype != torch.float32 or val.dtype != torch.float32:
+        raise TypeError("spmm_ex takes FP32 X and values")
+    if Y is None:
+        Y = torch.empty_like(X)
+    gather = _lib.SC_GATHER_FP32
+    if Xg is not None:
+        gather = {torch.float16: _lib.SC_GATHER_FP16, torch.bfloat16: _lib.SC_GATHER_BF16}[Xg.dtype]
+    ctx.check(lib().sc_spmm_ex(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),
+                               _ptr(diag), k, _ptr(X), X.stride(0), _ptr(Xg),
+                               Xg.stride(0) if Xg is not None else 0, gather, _ptr(order),
+                               _ptr(Y), Y.stride(0)), "sc_spmm_ex")
+    return Y
+
+
+def row_order(ctx: Context, g: DeviceCSR) -> torch.Tensor:
+    """The rows by descending length (stable), int32."""
+    nb = C.c_size_t()
+    ctx.check(lib().sc_row_order_workspace(ctx.handle, g.n, C.byref(nb)), "sc_row_order_workspace")
+    ws = ctx.workspace(nb.value)
+    order = torch.empty(g.n, dtype=torch.int32, device=g.row_ptr.device)
+    ctx.check(lib().sc_row_order(ctx.handle, g.n, _ptr(g.row_ptr), _ptr(order), _ptr(ws), nb.value),
+              "sc_row_order")
+    return order
+
+
 @dataclass
 class LobpcgResult:
     X: torch.Tensor

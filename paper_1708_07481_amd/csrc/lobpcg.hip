@@ -96,6 +96,8 @@ struct sc_lobpcg_state {
     // accumulation, [5] Gram-precision probe flag of the current iteration,
     // [6] inconsistent-iterate flag of the last residual
     int *act, *status, *pdrops, *all_locked, *wdrops, *gram_fallbacks, *gflag, *restart_flag;
+    int32_t* row_order;             // rows longest first, for the SpMM's row groups
+    void* order_scr;                // scratch of the sort that makes it
     GramPlan plan3{}, plan3x{}, plank{};
     int res_blocks = 0;
     // progress
@@ -154,6 +156,8 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.gram_fallbacks = s.status + 4;
     s.gflag = s.status + 5;
     s.restart_flag = s.status + 6;
+    s.row_order = c.take<int32_t>((size_t)n);
+    s.order_scr = c.take<char>(row_order_scratch_bytes(n));
     return c.size();
 }
 
@@ -248,7 +252,7 @@ struct Solver {
                                        s->pdrops, nullptr, s->gflag, s->gram_fallbacks, nullptr));
             }
             {
-                ProfScope ps(ctx, SC_KIND_GRAM);
+                ProfScope ps(ctx, SC_KIND_GRAM_FP64ACC);
                 SC_TRY(launch_gram<T>(ctx, s->plan3x, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
                                       s->GB, GRAM_F32_EXACT, s->gflag));
             }
@@ -334,6 +338,9 @@ struct Solver {
         hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->LS, words);
         hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->status, (int64_t)8);
         SC_CHECK_LAUNCH(ctx);
+        // the SpMM's row groups take the rows longest first, so that the long
+        // rows of high-degree vertices do not trail each launch
+        SC_TRY(row_order_by_length(ctx, s->n, s->row_ptr, s->row_order, s->order_scr));
         hipLaunchKernelGGL((k_load_block<T, T>), dim3(ceil_div(s->n * s->kp, 256)), dim3(256), 0, st,
                            s->n, s->k, s->kp, static_cast<const T*>(X0), s->ldx, S(s), ld, s->status);
         SC_CHECK_LAUNCH(ctx);
@@ -366,7 +373,8 @@ struct Solver {
         }
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld));
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld,
+                                  s->row_order));
         }
         // Rayleigh-Ritz on span(X) alone
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
@@ -397,7 +405,8 @@ struct Solver {
         }
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld));
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s), ld, LS(s), ld,
+                                  s->row_order));
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
         SC_CHECK_LAUNCH(ctx);
@@ -425,7 +434,7 @@ struct Solver {
         {
             ProfScope ps(ctx, SC_KIND_SPMM);
             SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s) + kp, ld,
-                                  LS(s) + kp, ld));
+                                  LS(s) + kp, ld, s->row_order));
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
                            s->has_p ? s->k : 0);

@@ -150,10 +150,17 @@ sc_status radix_sort_pairs(sc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t
 // ---------------------------------------------------------------------------
 // Kernels used by the LOBPCG driver (spmm.hip, dense.hip, rr.hip)
 // ---------------------------------------------------------------------------
+// order: optional row permutation for the row groups (rows longest first:
+// row_order_by_length); the arithmetic of every row is unchanged.
 template <class T>
 sc_status launch_spmm(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col,
                       const T* val, const T* diag, int k, const T* X, int64_t ldx, T* Y,
-                      int64_t ldy);
+                      int64_t ldy, const int32_t* order = nullptr);
+// order[0 .. n) = the rows by descending length, stable; `scratch` needs
+// row_order_scratch_bytes(n) bytes (256-byte aligned)
+size_t row_order_scratch_bytes(int64_t n);
+sc_status row_order_by_length(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, int32_t* order,
+                              void* scratch);
 
 // Gram products G1 = A^T B1 (and G2 = A^T B2 when B2 != nullptr), ca x cb,
 // upper triangle computed, mirrored; FP64 results.  A/B1/B2 are n x c blocks

@@ -10,22 +10,38 @@
 // with y = fma(v_p, x_{col_p, j}, y), so each output element is the exact
 // sequential chain of the definition; the lanes of a group gather one
 // contiguous row of X per stored entry.
+#include <hip/hip_bf16.h>
+
 #include "sc_internal.h"
 
 namespace {
 
 constexpr int TH = 256;
 
-template <class T, int LPR, int NC>
+template <class T>
+__device__ __forceinline__ T widen(T v) { return v; }
+template <class T>
+__device__ __forceinline__ T widen(_Float16 v) { return (T)(float)v; }
+template <class T>
+__device__ __forceinline__ T widen(__hip_bfloat16 v) { return (T)__bfloat162float(v); }
+
+// TG: type of the gathered neighbour rows (T itself, or a 16-bit copy Xg of X
+// widened to T on load); the row's own x_ij always comes from X.  order:
+// optional row permutation (group g computes row order[g]), e.g. the rows in
+// descending length so that the longest rows start first.
+template <class T, class TG, int LPR, int NC>
 __global__ void __launch_bounds__(TH) k_spmm(int64_t n, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col,
                                               const T* __restrict__ val,
                                               const T* __restrict__ diag, int k,
                                               const T* __restrict__ X, int64_t ldx,
+                                              const TG* __restrict__ Xg, int64_t ldg,
+                                              const int32_t* __restrict__ order,
                                               T* __restrict__ Y, int64_t ldy) {
-    const int64_t row = ((int64_t)blockIdx.x * TH + threadIdx.x) / LPR;
+    const int64_t grp = ((int64_t)blockIdx.x * TH + threadIdx.x) / LPR;
     const int lane = threadIdx.x % LPR;
-    if (row >= n) return;
+    if (grp >= n) return;
+    const int64_t row = order ? (int64_t)order[grp] : grp;
     const int64_t lo = row_ptr[row], hi = row_ptr[row + 1];
     const T a = diag ? diag[row] : T(1);
     T acc[NC];
@@ -51,7 +67,7 @@ __global__ void __launch_bounds__(TH) k_spmm(int64_t n, const int64_t* __restric
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                g[u][c] = ok[c] ? X[(int64_t)cp[u] * ldx + lane + LPR * c] : T(0);
+                g[u][c] = ok[c] ? widen<T>(Xg[(int64_t)cp[u] * ldg + lane + LPR * c]) : T(0);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -62,45 +78,56 @@ __global__ void __launch_bounds__(TH) k_spmm(int64_t n, const int64_t* __restric
         const T vp = val[p];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (ok[c]) acc[c] = fma(vp, X[(int64_t)cp * ldx + lane + LPR * c], acc[c]);
+            if (ok[c]) acc[c] = fma(vp, widen<T>(Xg[(int64_t)cp * ldg + lane + LPR * c]), acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         if (ok[c]) Y[row * ldy + lane + LPR * c] = acc[c];
 }
 
-template <class T, int LPR, int NC>
+template <class T, class TG, int LPR, int NC>
 sc_status go(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
-             const T* diag, int k, const T* X, int64_t ldx, T* Y, int64_t ldy) {
+             const T* diag, int k, const T* X, int64_t ldx, const TG* Xg, int64_t ldg,
+             const int32_t* order, T* Y, int64_t ldy) {
     const int64_t rows_per_block = TH / LPR;
-    hipLaunchKernelGGL((k_spmm<T, LPR, NC>), dim3(ceil_div(n, rows_per_block)), dim3(TH), 0,
-                       ctx->stream, n, rp, col, val, diag, k, X, ldx, Y, ldy);
+    hipLaunchKernelGGL((k_spmm<T, TG, LPR, NC>), dim3(ceil_div(n, rows_per_block)), dim3(TH), 0,
+                       ctx->stream, n, rp, col, val, diag, k, X, ldx, Xg, ldg, order, Y, ldy);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
+}
+
+template <class T, class TG>
+sc_status dispatch(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
+                   const T* diag, int k, const T* X, int64_t ldx, const TG* Xg, int64_t ldg,
+                   const int32_t* order, T* Y, int64_t ldy) {
+    if (n <= 0 || k <= 0) return SC_OK;
+#define SC_SPMM_GO(L, C) go<T, TG, L, C>(ctx, n, rp, col, val, diag, k, X, ldx, Xg, ldg, order, Y, ldy)
+    if (k <= 8) return SC_SPMM_GO(8, 1);
+    if (k <= 16) return SC_SPMM_GO(16, 1);
+    if (k <= 32) return SC_SPMM_GO(32, 1);
+    if (k <= 64) return SC_SPMM_GO(64, 1);
+    if (k <= 128) return SC_SPMM_GO(64, 2);
+    if (k <= 192) return SC_SPMM_GO(64, 3);
+    if (k <= 256) return SC_SPMM_GO(64, 4);
+#undef SC_SPMM_GO
+    return sc_fail(ctx, SC_E_UNSUPPORTED, "spmm: k = %d > 256", k);
 }
 
 }  // namespace
 
 template <class T>
 sc_status launch_spmm(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
-                      const T* diag, int k, const T* X, int64_t ldx, T* Y, int64_t ldy) {
-    if (n <= 0 || k <= 0) return SC_OK;
-    if (k <= 8) return go<T, 8, 1>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 16) return go<T, 16, 1>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 32) return go<T, 32, 1>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 64) return go<T, 64, 1>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 128) return go<T, 64, 2>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 192) return go<T, 64, 3>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    if (k <= 256) return go<T, 64, 4>(ctx, n, rp, col, val, diag, k, X, ldx, Y, ldy);
-    return sc_fail(ctx, SC_E_UNSUPPORTED, "spmm: k = %d > 256", k);
+                      const T* diag, int k, const T* X, int64_t ldx, T* Y, int64_t ldy,
+                      const int32_t* order) {
+    return dispatch<T, T>(ctx, n, rp, col, val, diag, k, X, ldx, X, ldx, order, Y, ldy);
 }
 
 template sc_status launch_spmm<double>(sc_ctx*, int64_t, const int64_t*, const int32_t*,
                                        const double*, const double*, int, const double*, int64_t,
-                                       double*, int64_t);
+                                       double*, int64_t, const int32_t*);
 template sc_status launch_spmm<float>(sc_ctx*, int64_t, const int64_t*, const int32_t*,
                                       const float*, const float*, int, const float*, int64_t,
-                                      float*, int64_t);
+                                      float*, int64_t, const int32_t*);
 
 extern "C" sc_status sc_spmm_diag(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                                   const int32_t* col, const void* val, const void* diag, int fp64,
@@ -127,4 +154,100 @@ extern "C" sc_status sc_spmm(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t*
                              const int32_t* col, const void* val, int fp64, int k, const void* X,
                              int64_t ldx, void* Y, int64_t ldy) {
     return sc_spmm_diag(ctx, n, nnz, row_ptr, col, val, nullptr, fp64, k, X, ldx, Y, ldy);
+}
+
+extern "C" sc_status sc_spmm_ex(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col, const float* val, const float* diag, int k,
+                                const float* X, int64_t ldx, const void* Xg, int64_t ldg,
+                                int gather, const int32_t* order, float* Y, int64_t ldy) {
+    if (!ctx) return SC_E_INVAL;
+    if (n <= 0 || nnz < 0 || k <= 0 || ldx < k || ldy < k)
+        return sc_fail(ctx, SC_E_INVAL, "spmm_ex: need n > 0, k > 0, ldx >= k, ldy >= k");
+    if (!row_ptr || !X || !Y || (nnz > 0 && (!col || !val)))
+        return sc_fail(ctx, SC_E_INVAL, "spmm_ex: null pointer argument");
+    if (X == Y) return sc_fail(ctx, SC_E_INVAL, "spmm_ex: X and Y must not alias");
+    if (gather != SC_GATHER_FP32 && (!Xg || ldg < k))
+        return sc_fail(ctx, SC_E_INVAL, "spmm_ex: a 16-bit gather copy needs Xg and ldg >= k");
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    ProfScope ps(ctx, SC_KIND_SPMM);
+    switch (gather) {
+    case SC_GATHER_FP32:
+        return dispatch<float, float>(ctx, n, row_ptr, col, val, diag, k, X, ldx, X, ldx, order, Y,
+                                      ldy);
+    case SC_GATHER_FP16:
+        return dispatch<float, _Float16>(ctx, n, row_ptr, col, val, diag, k, X, ldx,
+                                         static_cast<const _Float16*>(Xg), ldg, order, Y, ldy);
+    case SC_GATHER_BF16:
+        return dispatch<float, __hip_bfloat16>(ctx, n, row_ptr, col, val, diag, k, X, ldx,
+                                               static_cast<const __hip_bfloat16*>(Xg), ldg, order,
+                                               Y, ldy);
+    default:
+        return sc_fail(ctx, SC_E_INVAL, "spmm_ex: unknown gather type %d", gather);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row order by length: the rows sorted by descending stored-entry count (stable,
+// so equal lengths keep ascending row order), for sc_spmm_ex's `order`.
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void k_len_keys(int64_t n, const int64_t* __restrict__ row_ptr,
+                           uint64_t* __restrict__ keys, uint32_t* __restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * TH + threadIdx.x;
+    if (i >= n) return;
+    const int64_t len = row_ptr[i + 1] - row_ptr[i];
+    keys[i] = 0xFFFFFFFFull - (uint64_t)min<int64_t>(len, 0xFFFFFFFFll);
+    rows[i] = (uint32_t)i;
+}
+
+struct OrderWs {
+    uint64_t *keys, *keys_alt, *tmp;
+    uint32_t* rows_alt;
+};
+
+size_t carve_order(Carver& c, int64_t n, OrderWs& w) {
+    w.keys = c.take<uint64_t>((size_t)n);
+    w.keys_alt = c.take<uint64_t>((size_t)n);
+    w.rows_alt = c.take<uint32_t>((size_t)n);
+    w.tmp = c.take<uint64_t>(radix_tmp_elems(n));
+    return c.size();
+}
+
+}  // namespace
+
+size_t row_order_scratch_bytes(int64_t n) {
+    Carver c(nullptr);
+    OrderWs w;
+    return carve_order(c, n, w);
+}
+
+sc_status row_order_by_length(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, int32_t* order,
+                              void* scratch) {
+    Carver c(scratch);
+    OrderWs w;
+    carve_order(c, n, w);
+    uint32_t* rows = reinterpret_cast<uint32_t*>(order);
+    hipLaunchKernelGGL(k_len_keys, dim3((unsigned)ceil_div(n, TH)), dim3(TH), 0, ctx->stream, n,
+                       row_ptr, w.keys, rows);
+    SC_CHECK_LAUNCH(ctx);
+    return radix_sort_pairs(ctx, w.keys, rows, w.keys_alt, w.rows_alt, n, 32, w.tmp);
+}
+
+extern "C" sc_status sc_row_order_workspace(sc_ctx* ctx, int64_t n, size_t* bytes) {
+    if (!ctx || !bytes) return SC_E_INVAL;
+    if (n <= 0 || n >= (int64_t(1) << 31)) return sc_fail(ctx, SC_E_INVAL, "row_order: need 0 < n < 2^31");
+    *bytes = row_order_scratch_bytes(n);
+    return SC_OK;
+}
+
+extern "C" sc_status sc_row_order(sc_ctx* ctx, int64_t n, const int64_t* row_ptr, int32_t* order,
+                                  void* ws, size_t ws_bytes) {
+    if (!ctx) return SC_E_INVAL;
+    if (n <= 0 || n >= (int64_t(1) << 31)) return sc_fail(ctx, SC_E_INVAL, "row_order: need 0 < n < 2^31");
+    if (!row_ptr || !order || !ws) return sc_fail(ctx, SC_E_INVAL, "row_order: null pointer argument");
+    const size_t need = row_order_scratch_bytes(n);
+    if (ws_bytes < need) return sc_fail(ctx, SC_E_NOMEM, "row_order: workspace %zu < %zu", ws_bytes, need);
+    SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
+    return row_order_by_length(ctx, n, row_ptr, order, ws);
 }
