@@ -145,17 +145,18 @@ def record_cpu_baseline(args, cfg, g0):
 
 def cpu_baseline(g0, cfg, name, gpu_iters, restarts, lloyd_iters, combinatorial=False):
     """The oracle on this host's cores for one partition of the workload.
-    Timed live on the full graph (a bounded sample, about 10 s of CPU work):
-    graph build + Laplacian, and one SpMM with the k-column block.  The
-    phases too long to repeat in every run come from the full-size record
+    Timed live on the full graph (a bounded sample, about 15 s of CPU work):
+    graph build + Laplacian, one SpMM with the k-column block, and k-means
+    normalisation plus one restart's seeding.  The phases too long to repeat
+    in every run come from the full-size record
     profiles/cpu_baseline_<workload>.json (measured once on a GPU machine's host
     by record_cpu_baseline): LOBPCG start-up and per-iteration time, k-means
-    normalisation, per-restart seeding and per-Lloyd-update time.  One
-    partition = graph + start-up + the GPU solve's iterations x iteration +
-    normalisation + restarts x seeding + restarts x the GPU's Lloyd updates
-    (of its slowest restart, so an upper estimate) x update."""
+    per-Lloyd-update time.  One partition = graph + start-up + the GPU
+    solve's iterations x iteration + normalisation + restarts x seeding +
+    restarts x the GPU's Lloyd updates (of its slowest restart, so an upper
+    estimate) x update."""
     import oracle
-    from synth import gaussian_block
+    from synth import gaussian_block, kmeans_draws
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     g = oracle.graph_build(g0.n, g0.src, g0.dst)
@@ -165,7 +166,11 @@ def cpu_baseline(g0, cfg, name, gpu_iters, restarts, lloyd_iters, combinatorial=
     t0 = time.perf_counter()
     oracle.spmm(g, val, X0, diag)
     t_spmm = time.perf_counter() - t0
-    del g, val, X0
+    del g, val
+    # one k-means++ seeding (with its first assignment) on the n x k block
+    km = oracle.kmeans(X0, cfg["k"], kmeans_draws(1, cfg["k"], 1), max_iter=0)
+    t_norm, t_seed = km.timing[0], km.timing[1]
+    del X0
     try:
         with open(cpu_record_path(name)) as fh:
             rec = json.load(fh)
@@ -178,82 +183,162 @@ def cpu_baseline(g0, cfg, name, gpu_iters, restarts, lloyd_iters, combinatorial=
                            f"record of the other phases for this workload")}
     sec = rec["seconds"]
     value = (t_graph + sec["lobpcg_setup"] + gpu_iters * sec["lobpcg_iteration"]
-             + sec["kmeans_normalise"] + restarts * sec["kmeans_seeding_per_restart"]
+             + t_norm + restarts * t_seed
              + restarts * lloyd_iters * sec["kmeans_lloyd_update"])
     return {"value": round(value, 1), "unit": "s", "cores": threads, "kind": "oracle",
             "host": host_info(),
-            "sample": (f"oracle on the full graph (n={g0.n}, k={cfg['k']}). Live in this run: "
-                       f"graph build + Laplacian {t_graph:.1f} s, one SpMM {t_spmm:.1f} s (the "
-                       f"record's: {sec['spmm']:.1f} s). From the full-size record "
-                       f"profiles/cpu_baseline_{name}.json ({rec['threads']} threads on "
-                       f"{rec['host'].get('Model name', '?')}): LOBPCG start-up "
-                       f"{sec['lobpcg_setup']:.1f} s + {gpu_iters} iterations x "
-                       f"{sec['lobpcg_iteration']:.1f} s; k-means normalisation "
-                       f"{sec['kmeans_normalise']:.1f} s + {restarts} restarts x seeding "
-                       f"{sec['kmeans_seeding_per_restart']:.1f} s + {restarts} x {lloyd_iters} "
-                       f"Lloyd updates x {sec['kmeans_lloyd_update']:.1f} s (the GPU's count for "
-                       f"its slowest restart: an upper estimate)")}
+            "sample": (f"oracle on the full graph (n={g0.n}, k={cfg['k']}). Live in this run "
+                       f"(about {t_graph + t_spmm + t_norm + t_seed:.0f} s of CPU): graph build "
+                       f"+ Laplacian {t_graph:.1f} s, one SpMM {t_spmm:.1f} s (the record's: "
+                       f"{sec['spmm']:.1f} s), k-means normalisation {t_norm:.1f} s and one "
+                       f"restart's seeding with its first assignment {t_seed:.1f} s (the "
+                       f"record's: {sec['kmeans_seeding_per_restart']:.1f} s). From the "
+                       f"full-size record profiles/cpu_baseline_{name}.json "
+                       f"({rec['threads']} threads on {rec['host'].get('Model name', '?')}): "
+                       f"LOBPCG start-up {sec['lobpcg_setup']:.1f} s and {gpu_iters} iterations "
+                       f"x {sec['lobpcg_iteration']:.1f} s, {restarts} restarts x {lloyd_iters} "
+                       f"Lloyd updates x {sec['kmeans_lloyd_update']:.1f} s (the GPU's Lloyd "
+                       f"count of its slowest restart: an upper estimate). One partition = "
+                       f"graph + start-up + iterations + normalisation + {restarts} seedings + "
+                       f"Lloyd updates")}
+
+
+def serve_specs(S, seed=11):
+    """The serving mix: 60/30/10 % of S streams are 5K / 50K / 500K graphs,
+    alternately emerging-edge and snowball."""
+    import numpy as np
+    n5 = round(0.6 * S)
+    n50 = round(0.3 * S)
+    sizes = ["sbm5k"] * n5 + ["sbm50k"] * n50 + ["sbm500k"] * (S - n5 - n50)
+    order = np.random.default_rng(seed).permutation(S)
+    return [(f"{sizes[i]}-{j}", sizes[i], "emerging" if j % 2 == 0 else "snowball")
+            for j, i in enumerate(order)], (n5, n50, S - n5 - n50)
+
+
+def serve_pass(be, reqs, slots, budget, warm=True, discard_before=0.0, stages=10):
+    """Serve the requests (warm or cold starts) on the library backend; stats
+    over the requests that arrive at or after `discard_before` seconds."""
+    import numpy as np
+    import torch
+    from paper_1708_07481_amd.metrics import partition_scores
+    from paper_1708_07481_amd.serve import Server, percentile
+    batch = [_clone(r, warm=warm) for r in reqs]
+    srv = Server(be, slots=slots, hbm_budget=budget)
+    t0 = time.perf_counter()
+    out = srv.run(batch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kept = [r for r in out if r.request.arrival >= discard_before]
+    lat = [r.latency for r in kept]
+    t_first = min(r.arrived for r in kept)
+    t_last = max(r.finished for r in kept)
+    st = {"requests": len(out), "measured": len(kept), "wall_s": wall,
+          "solves_per_s": len(kept) / max(t_last - t_first, 1e-12),
+          "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
+          "mean_latency_s": float(np.mean(lat)),
+          "mean_queue_s": float(np.mean([r.queued for r in kept])),
+          "later_stage_iterations": int(sum(r.iterations for r in kept if r.request.stage > 0)),
+          "converged": int(sum(r.converged for r in kept)),
+          "peak_active": srv.peak_active, "evictions": srv.evictions}
+    pm = {}
+    for r in out:
+        if r.request.stage == stages - 1 and r.request.truth is not None:
+            pm.setdefault(r.request.stream.split("-")[0], []).append(
+                partition_scores(r.request.truth, r.labels)["PM"])
+    st["final_stage_PM"] = {z: round(float(np.mean(v)), 4) for z, v in pm.items()}
+    return {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in st.items()}
+
+
+def serve_warm_cold(S, stages, rate, stage_rate, slots, budget_gb, warm_fill):
+    """The serving mix served warm, then cold: solves/s, p50/p99 latency and
+    later-stage LOBPCG iterations of each pass."""
+    import torch
+    from paper_1708_07481_amd.serve import LibraryBackend, Server, make_streams
+    specs, counts = serve_specs(S)
+    log(f"serving: generating {S} streams x {stages} stages {counts}")
+    t = time.perf_counter()
+    reqs = make_streams(specs, rate=rate, seed=5, stages=stages, stage_rate=stage_rate)
+    log(f"serving: {len(reqs)} requests ready in {time.perf_counter() - t:.1f} s")
+    budget = int(budget_gb * (1 << 30))
+    be = LibraryBackend(slots, precision="fp64", maxit=30, tol=1e-2, restarts=10,
+                        warm_fill=warm_fill)
+    small = min(reqs, key=lambda r: r.n)      # warm-up: one small solve loads the kernels
+    Server(be, slots=1, hbm_budget=budget).run([_clone(small, arrival=0.0, stage=0, warm=False)])
+    torch.cuda.synchronize()
+    passes = {}
+    for mode in ("warm", "cold"):
+        passes[mode] = serve_pass(be, reqs, slots, budget, warm=(mode == "warm"), stages=stages)
+        log(f"serving {mode}: {passes[mode]}")
+    be.close()
+    return passes, counts, len(reqs)
+
+
+def serve_protocol(args):
+    """Load sweep of the serving mix: the capacity (solves/s with every stream
+    started at once, each stage held until its predecessor finishes), then
+    Poisson arrivals at 0.5, 0.8 and 0.95 of it with at least 1,000 requests
+    per load; the requests arriving in the first 10 % of each pass's arrival
+    span are discarded as warm-up.  Written to profiles/serve_mix_loads.json."""
+    import torch
+    from paper_1708_07481_amd.serve import LibraryBackend, Server, make_streams
+    budget = int(args.budget_gb * (1 << 30))
+    stages = args.stages
+    be = LibraryBackend(args.slots, precision="fp64", maxit=30, tol=1e-2, restarts=10,
+                        warm_fill=args.warm_fill)
+    specs, counts = serve_specs(20, seed=21)
+    reqs = make_streams(specs, rate=1e6, seed=7, stages=stages, stage_rate=None)
+    small = min(reqs, key=lambda r: r.n)
+    Server(be, slots=1, hbm_budget=budget).run([_clone(small, arrival=0.0, stage=0, warm=False)])
+    sat = serve_pass(be, reqs, args.slots, budget, stages=stages)
+    cap = sat["solves_per_s"]
+    log(f"capacity (20 streams started at once): {cap:.2f} solves/s; {sat}")
+    S = max(100, -(-args.protocol_requests // stages))
+    loads = {}
+    for rho in (0.5, 0.8, 0.95):
+        rate = rho * cap / stages                   # stream starts per second
+        specs, counts = serve_specs(S, seed=int(100 * rho))
+        t = time.perf_counter()
+        reqs = make_streams(specs, rate=rate, seed=int(1000 * rho), stages=stages,
+                            stage_rate=args.stage_rate)
+        span = max(r.arrival for r in reqs)
+        log(f"load {rho}: {len(reqs)} requests over {span:.0f} s of arrivals "
+            f"(generated in {time.perf_counter() - t:.0f} s)")
+        loads[str(rho)] = serve_pass(be, reqs, args.slots, budget, discard_before=0.1 * span,
+                                     stages=stages)
+        loads[str(rho)]["offered_solves_per_s"] = round(rho * cap, 3)
+        log(f"load {rho}: {loads[str(rho)]}")
+    be.close()
+    rec = {"workload": (f"serving mix (60/30/10 % of streams 5K/19, 50K/44, 500K/98 DC-SBM; half "
+                        f"emerging-edge, half snowball; {stages} stages), warm starts, "
+                        f"{args.slots} slots, {args.budget_gb} GB admission budget, maxit 30, "
+                        f"tol 1e-2, FP64 (5K, 50K) / FP32 + BF16 Gram (500K)"),
+           "capacity_solves_per_s": round(cap, 3), "capacity_run": sat,
+           "streams_per_load": S, "requests_per_load": S * stages,
+           "warmup_discarded": "requests arriving in the first 10 % of the arrival span",
+           "loads": loads,
+           "command": f"python bench.py --config serve --protocol --slots {args.slots}"}
+    with open(os.path.join(HERE, "profiles", "serve_mix_loads.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec), flush=True)
 
 
 def run_serve(args):
     """Continuous-batching mix, served warm then cold; one JSON line."""
-    import numpy as np
-    import torch
-    from paper_1708_07481_amd.metrics import partition_scores
-    from paper_1708_07481_amd.serve import LibraryBackend, Server, make_streams
-
+    if args.protocol:
+        return serve_protocol(args)
     S = args.streams
-    n5 = round(0.6 * S)
-    n50 = round(0.3 * S)
-    sizes = ["sbm5k"] * n5 + ["sbm50k"] * n50 + ["sbm500k"] * (S - n5 - n50)
-    order = np.random.default_rng(11).permutation(S)
-    specs = [(f"{sizes[i]}-{j}", sizes[i], "emerging" if j % 2 == 0 else "snowball")
-             for j, i in enumerate(order)]
-    log(f"generating {S} streams x {args.stages} stages: {dict((z, sizes.count(z)) for z in set(sizes))}")
-    t = time.perf_counter()
-    reqs = make_streams(specs, rate=args.rate, seed=5, stages=args.stages,
-                        stage_rate=args.stage_rate)
-    log(f"streams ready in {time.perf_counter() - t:.1f} s; {len(reqs)} requests")
-    budget = int(args.budget_gb * (1 << 30))
-
-    # warm-up: one small solve loads every kernel
-    be = LibraryBackend(args.slots, precision="fp64", maxit=30, tol=1e-2, restarts=10,
-                        warm_fill=args.warm_fill)
-    small = min(reqs, key=lambda r: r.n)
-    Server(be, slots=1, hbm_budget=budget).run([_clone(small, arrival=0.0, stage=0, warm=False)])
-    torch.cuda.synchronize()
-
-    passes = {}
-    for mode in ("warm", "cold"):
-        batch = [_clone(r, warm=(mode == "warm")) for r in reqs]
-        srv = Server(be, slots=args.slots, hbm_budget=budget)
-        t0 = time.perf_counter()
-        out = srv.run(batch)
-        torch.cuda.synchronize()
-        st = srv.stats()
-        st["wall_s"] = time.perf_counter() - t0
-        later = [r for r in out if r.request.stage > 0]
-        st["later_stage_iterations"] = int(sum(r.iterations for r in later))
-        st["converged"] = int(sum(r.converged for r in out))
-        pm = {}
-        for r in out:
-            if r.request.stage == args.stages - 1:
-                cfg_name = r.request.stream.split("-")[0]
-                pm.setdefault(cfg_name, []).append(
-                    partition_scores(r.request.truth, r.labels)["PM"])
-        st["final_stage_PM"] = {z: round(float(np.mean(v)), 4) for z, v in pm.items()}
-        passes[mode] = {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in st.items()}
-        log(f"{mode}: {passes[mode]}")
-    be.close()
+    passes, (n5, n50, n500), nreq = serve_warm_cold(S, args.stages, args.rate, args.stage_rate,
+                                                     args.slots, args.budget_gb, args.warm_fill)
     w, c = passes["warm"], passes["cold"]
     out = {
         "metric": "LOBPCG time-to-partition at rel-residual 1e-2; SpMM HBM GB/s; p99 solve latency",
-        "value": w["p99_latency_s"], "unit": "s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
-        "ms_per_step": round(1000.0 * w["makespan_s"] / max(len(reqs), 1), 3),
+        "value": w["p99_latency_s"], "unit": "s", "n_gpus": 1, "steps": nreq, "warmup": 1,
+        "ms_per_step": round(1000.0 / max(w["solves_per_s"], 1e-12), 3),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (5K, 50K) / f32+bf16gram (500K)", "data": "synthetic",
         "config": {"workload": (f"serving mix: {S} streams ({n5} x 5K/19, {n50} x 50K/44, "
-                                f"{S - n5 - n50} x 500K/98 degree-corrected SBM), half emerging-edge, "
+                                f"{n500} x 500K/98 degree-corrected SBM), half emerging-edge, "
                                 f"half snowball, {args.stages} stages each; stream starts Poisson "
                                 f"{args.rate}/s, stage arrivals Poisson {args.stage_rate}/s held "
                                 f"until the previous stage finishes; {args.slots} slots, "
@@ -265,6 +350,99 @@ def run_serve(args):
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
+
+
+def spmm_variants(args, cfg, g0):
+    """Time the FP32 product Y = L X (k = the workload's block width) in the
+    layouts that change its memory traffic: natural row order; rows longest
+    first (bit-identical); 16-bit gather copies of X (FP16, BF16: accuracy
+    against the FP32 product reported); the vertices renumbered by reverse
+    Cuthill-McKee (SciPy on the host, its time included) and, as the best any
+    community-finding order could do, by the generator's blocks.  Each variant:
+    2 untimed then 10 timed launches on the library's stream (HIP events).
+    Dispatch order: natural, longest first, FP16, BF16, RCM, blocks."""
+    import numpy as np
+    import torch
+    from paper_1708_07481_amd import api
+    n, k = g0.n, cfg["k"]
+    dev = torch.device("cuda:0")
+    ctx = api.Context(0)
+    out = {"workload": f"n={n} nnz~{2 * g0.m} k={k} FP32", "launches_timed": 10}
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    def build(src, dst):
+        g = api.graph_build(ctx, n, torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev))
+        _, v32, _ = api.laplacian_csr(ctx, g, False, True)
+        return g, v32
+
+    g, v32 = build(g0.src, g0.dst)
+    X = api.randn(ctx, n, k, 1, 2, "normal", torch.float32)
+    Y0 = torch.empty_like(X)
+    Y = torch.empty_like(X)
+    nb = spmm_algorithmic_bytes(n, g.nnz, k, 4)
+    rate = lambda ms: round(nb / (ms * 1e-3) / 1e9, 1)
+    ms = timed(lambda: api.spmm(ctx, g, v32, X, Y0))
+    out["natural"] = {"ms": round(ms, 4), "algorithmic_GBs": rate(ms)}
+    log(f"natural order: {ms:.3f} ms")
+    t0 = time.perf_counter()
+    order = api.row_order(ctx, g)
+    torch.cuda.synchronize()
+    t_order = time.perf_counter() - t0
+    ms = timed(lambda: api.spmm_ex(ctx, g, v32, X, Y, order=order))
+    out["longest_rows_first"] = {"ms": round(ms, 4), "algorithmic_GBs": rate(ms),
+                                 "order_ms": round(1e3 * t_order, 2),
+                                 "bit_identical": bool(torch.equal(Y, Y0))}
+    log(f"longest rows first: {ms:.3f} ms (order {1e3 * t_order:.1f} ms)")
+    ref = Y0.double()
+    scale = float(ref.abs().max())
+    for name, dt in (("fp16_gather", torch.float16), ("bf16_gather", torch.bfloat16)):
+        Xg = X.to(dt)
+        ms = timed(lambda: api.spmm_ex(ctx, g, v32, X, Y, Xg=Xg))
+        err = float((Y.double() - ref).abs().max()) / scale
+        out[name] = {"ms": round(ms, 4), "algorithmic_GBs": rate(ms),
+                     "max_abs_err_rel_to_max": err}
+        log(f"{name}: {ms:.3f} ms, max error / max |y| {err:.2e}")
+        del Xg
+    # renumberings: new id of vertex v is inv[v]
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    t0 = time.perf_counter()
+    A = sp.csr_matrix((np.ones(g0.m, np.int8), (g0.src, g0.dst)), shape=(n, n))
+    A = (A + A.T).tocsr()
+    perm_rcm = reverse_cuthill_mckee(A, symmetric_mode=True)
+    t_rcm = time.perf_counter() - t0
+    del A
+    perms = {"rcm": (perm_rcm, t_rcm), "generator_blocks": (np.argsort(g0.truth, kind="stable"), 0.0)}
+    for name, (perm, t_host) in perms.items():
+        inv = np.empty(n, np.int32)
+        inv[perm] = np.arange(n, dtype=np.int32)
+        gp, vp = build(inv[g0.src], inv[g0.dst])
+        Xp = X[torch.from_numpy(perm.astype(np.int64)).to(dev)].contiguous()
+        Yp = torch.empty_like(Xp)
+        ms = timed(lambda: api.spmm(ctx, gp, vp, Xp, Yp))
+        out[name] = {"ms": round(ms, 4), "algorithmic_GBs": rate(ms),
+                     "host_order_s": round(t_host, 2)}
+        log(f"{name}: {ms:.3f} ms (host order {t_host:.1f} s)")
+        del gp, vp, Xp, Yp
+    # reference kernel for the byte counters: a plain 512 MiB device copy, 3 times
+    x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+    ctx.close()
+    return out
 
 
 def compare_fp64(args, api, ctx, cfg, n, k, src, dst, draws, res, km, t_mixed, truth):
@@ -331,6 +509,12 @@ def main():
     ap.add_argument("--warm-fill", default="neighbors", choices=["neighbors", "zero"],
                     help="serve: start rows of the vertices a snowball stage adds")
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving pass after the timed steps")
+    ap.add_argument("--protocol", action="store_true",
+                    help="serve: load sweep (capacity, then 0.5 / 0.8 / 0.95 of it, >= 1,000 "
+                         "requests per load) written to profiles/serve_mix_loads.json")
+    ap.add_argument("--protocol-requests", type=int, default=1000)
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "fp32_bf16gram"],
                     help="override the workload's precision")
     ap.add_argument("--cluster", default="kmeans", choices=["kmeans", "cpqr"],
@@ -350,6 +534,9 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also solve the same graph from the same start block in FP64 and report "
                          "speedup, eigenvalue error, subspace sine and accuracy of both")
+    ap.add_argument("--spmm-variants", action="store_true",
+                    help="time the SpMM in the layouts that change its traffic (row order, "
+                         "16-bit gathers, RCM and block renumbering) on the workload's graph")
     ap.add_argument("--record-cpu-baseline", action="store_true",
                     help="time the oracle once on the full graph (several minutes, host only) "
                          "and write profiles/cpu_baseline_<config>.json")
@@ -388,6 +575,10 @@ def main():
     t = time.perf_counter()
     g0 = graph_for(args.config, seed=1)
     log(f"graph: m={g0.m} in {time.perf_counter() - t:.1f} s")
+    if args.spmm_variants:
+        rec = spmm_variants(args, cfg, g0)
+        print(json.dumps(rec), flush=True)
+        return
     if args.record_cpu_baseline:
         rec = record_cpu_baseline(args, cfg, g0)
         print(json.dumps(rec), flush=True)
@@ -435,7 +626,7 @@ def main():
             f"relres={res.max_relres:.3e}")
     torch.cuda.synchronize()
     ctx.set_profiling(["spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual",
-                       "graph_build", "kmeans"])
+                       "graph_build", "kmeans", "gram_fp64acc"])
     ctx.profile_reset()
     times = []
     torch.cuda.synchronize()
@@ -460,7 +651,8 @@ def main():
     alg_bytes = spmm_algorithmic_bytes(n, gd.nnz, k, es, comb)
     achieved = alg_bytes / (spmm["avg_ms"] * 1e-3) / 1e9
     lob_ms = sum(prof.get(x, {}).get("total_ms", 0.0) for x in
-                 ("spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual"))
+                 ("spmm", "gram", "rayleigh_ritz", "block_update", "cholqr", "residual",
+                  "gram_fp64acc"))
     iters_total = res.iterations * args.steps
     out = {
         "metric": "LOBPCG time-to-partition at rel-residual 1e-2; SpMM HBM GB/s; p99 solve latency",
@@ -497,26 +689,33 @@ def main():
         "phase_ms_per_step": {kk: round(v["total_ms"] / args.steps, 3) for kk, v in prof.items()},
         "kernel_avg_ms": {kk: round(v["avg_ms"], 4) for kk, v in prof.items()},
         "accuracy_vs_truth": {kk: round(v, 5) for kk, v in scores.items()},
-        "roofline": {"bound": "hbm", "kernel": "spmm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "traffic": spmm_traffic(args.config, alg_bytes)},
     }
-    # Gram products of the Rayleigh-Ritz step (S'LS and S'S, one pair per RR)
+    spmm_line = {"kernel": "spmm (L W, the product of the metric)", "bound": "hbm",
+                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_ms": round(spmm["avg_ms"], 4),
+                 "algorithmic_bytes_per_launch": alg_bytes,
+                 "traffic": spmm_traffic(args.config, alg_bytes)}
+    # The dominant kernel: the Gram products of the Rayleigh-Ritz step, S'LS and
+    # S'S in one launch (split over row chunks, then an ordered reduction), one
+    # launch per Rayleigh-Ritz step; its algorithmic work is the two
+    # symmetric K3 x K3 outputs over n rows.
     gram = prof.get("gram")
     if gram:
-        n_rr = (res.iterations + 1 + res.restarts) * args.steps
-        gram_ms = gram["total_ms"] / n_rr
-        K3 = 3 * ((k + 3) // 4 * 4)
-        gflop = 2.0 * n * K3 * (K3 + 1) / 1e9      # two symmetric K3 x K3 outputs
+        K3 = 3 * ((kb + 3) // 4 * 4)
+        gflop = 2.0 * n * K3 * (K3 + 1) / 1e9
         peak = 78.6 if fp64 else (2500.0 if prec == "fp32_bf16gram" else 157.3)
-        out["rooflines_other"] = [{
-            "kernel": "gram (S'LS and S'S)", "bound": "mfma", "unit": "TFLOP/s",
-            "achieved": round(gflop / gram_ms, 2), "peak": peak,
-            "frac": round(gflop / gram_ms / peak, 4), "ms_per_rr": round(gram_ms, 3),
-            "algorithmic_gflop": round(gflop, 1),
-            "counters": gram_counters(args.config) if (prec == "fp32" and k == 160) else None}]
+        tflops = gflop / gram["avg_ms"]
+        counters = gram_counters(args.config) if (prec == "fp32" and kb == 160) else None
+        out["roofline"] = {"bound": "mfma", "kernel": "gram (S'LS and S'S)",
+                           "achieved": round(tflops, 2), "peak": peak, "unit": "TFLOP/s",
+                           "frac": round(tflops / peak, 4), "avg_ms": round(gram["avg_ms"], 4),
+                           "launches": gram["launches"],
+                           "algorithmic_gflop_per_launch": round(gflop, 1),
+                           "traffic": counters["traffic"] if counters else None,
+                           "counters": counters}
+        out["rooflines_other"] = [spmm_line]
+    else:
+        out["roofline"] = dict(spmm_line, kernel="spmm")
     if args.compare and not fp64:
         out["precision_comparison"] = compare_fp64(args, api, ctx, cfg, n, k, src, dst, draws,
                                                    res, km, total / args.steps, g0.truth)
@@ -529,6 +728,25 @@ def main():
         out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
     out["hip_runtime"] = api.runtime_info()
     ctx.close()
+    if not args.no_serve:
+        # the serving mix after the timed steps (not part of `value`)
+        passes, counts, nreq = serve_warm_cold(args.streams, args.stages, args.rate,
+                                               args.stage_rate, args.slots, args.budget_gb,
+                                               args.warm_fill)
+        w, c = passes["warm"], passes["cold"]
+        out["serving"] = {
+            "workload": (f"{args.streams} streams ({counts[0]} x 5K/19, {counts[1]} x 50K/44, "
+                         f"{counts[2]} x 500K/98 DC-SBM), half emerging-edge, half snowball, "
+                         f"{args.stages} stages, Poisson stream starts {args.rate}/s and stage "
+                         f"arrivals {args.stage_rate}/s, {args.slots} slots"),
+            "requests": nreq, "p50_s": w["p50_latency_s"], "p99_s": w["p99_latency_s"],
+            "solves_per_s": w["solves_per_s"],
+            "iterations_saved": c["later_stage_iterations"] - w["later_stage_iterations"],
+            "cold": {"p50_s": c["p50_latency_s"], "p99_s": c["p99_latency_s"],
+                     "solves_per_s": c["solves_per_s"]},
+            "warm_later_stage_iterations": w["later_stage_iterations"],
+            "cold_later_stage_iterations": c["later_stage_iterations"],
+            "final_stage_PM": w["final_stage_PM"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         try:
