@@ -1060,76 +1060,144 @@ __device__ inline bool km_needs_update(int64_t rj, int K, const int* active, con
     return active[rj / K] && dirty[rj] && seg[2 * rj + 1] > seg[2 * rj];
 }
 
-// One wave per (cluster, 64-dimension slab).  The rows are the FP64 copy of
-// y (row stride dim), so the chain itself is one addition per member.  The
-// members come in batches of CS_B (one id per lane): the rows of batch b + 1
-// and the ids of batch b + 2 are requested before batch b is added, so the
-// chain rarely waits; every load is clamped to the last member.
-constexpr int CS_B = 32;
-__global__ void __launch_bounds__(64)
+// One workgroup per (cluster, 64-coordinate slab): wave 0 runs the chains
+// (lane = coordinate) and waves 1 .. CP_PW gather member rows for it.  A
+// single wave doing both issues about ten instructions per member (id
+// read-out, address, load, addition), and a wave issues at most one
+// instruction every four cycles; split this way the chain costs a shared-
+// memory read and an addition per member, while the gathers of the next
+// batches run on the other waves.  The rows are the FP64 copy of y (row
+// stride dim).  Batches of CP_B members pass through a two-slot ring in
+// shared memory; step u stores batch u into the ring, requests the rows of
+// batch u + CP_S (each gathering wave keeps CP_S batches in flight in
+// registers) and adds batch u - 1; a barrier closes every step.
+//
+// Member ids reach the gathering waves through shared memory too, in chunks
+// of CP_CH batches: wave 0 stores chunk c one step before its first batch is
+// requested and then loads chunk c + 1 into registers, where it has CP_CH
+// steps to arrive.  A wave's vector loads complete in issue order, so an id
+// load among a gathering wave's row loads would make every row load issued
+// before it complete first and cap the rows in flight; this way the
+// gathering waves load rows only.  Positions past the last member are
+// clamped to it and never stored.
+// s_waitcnt immediate (gfx9 layout) for vmcnt(0) with expcnt and lgkmcnt left free
+constexpr int KM_WAIT_VM0 = (0x7 << 4) | (0xF << 8);
+constexpr int CP_PW = 3;                   // gathering waves
+constexpr int CP_M = 15;                   // members per gathering wave and batch
+constexpr int CP_B = CP_PW * CP_M;         // members per batch
+constexpr int CP_S = 4;                    // batches in flight per gathering wave
+constexpr int CP_CH = 16;                  // batches per id chunk
+constexpr int CP_CI = CP_CH * CP_B;        // ids per chunk
+constexpr int CP_NL = (CP_CI + 63) / 64;   // id loads per lane and chunk
+constexpr int CP_NT = 64 * (CP_PW + 1);
+static_assert(CP_S * CP_M <= 63, "rows in flight beyond the vector load counter");
+static_assert(CP_CH > CP_S, "chunk 0 holds the ids the gathering waves start with");
+__global__ void __launch_bounds__(CP_NT)
 k_centroid_sum(int dim, int K, int R, const double* __restrict__ Y,
                const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
                const int* __restrict__ active, const int* __restrict__ dirty,
                double* __restrict__ C) {
+    __shared__ double ring[2][CP_B][64];
+    __shared__ int idbuf[2][CP_CI];
     const int wps = (dim + 63) / 64;
     const int64_t rj = blockIdx.x / wps;
     if (rj >= (int64_t)R * K) return;
     if (!km_needs_update(rj, K, active, dirty, seg)) return;
-    const int lane = (int)threadIdx.x;
+    const int wave = uniform((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
     const int d = (int)(blockIdx.x - rj * wps) * 64 + lane;
-    const bool dl = d < dim;
-    const int dd = dl ? d : dim - 1;
+    const int dd = d < dim ? d : dim - 1;
     const int64_t lo = seg[2 * rj];
     const int64_t cnt = seg[2 * rj + 1] - lo;       // >= 1
     const uint32_t* mem = members + lo;
     const double* Yd = Y + dd;
-    const int64_t nb = (cnt + CS_B - 1) / CS_B;
-    auto ids_of = [&](int64_t b) -> int {
-        return (int)mem[min<int64_t>(b * CS_B + (lane & (CS_B - 1)), cnt - 1)];
+    const int64_t nb = (cnt + CP_B - 1) / CP_B;
+    const int pw = wave - 1;                         // gathering wave index
+    // the ids of gathering wave pw's share of batch b, from the chunk buffer
+    auto ids = [&](int64_t b, int* out) {
+        const int* ir = &idbuf[(b / CP_CH) & 1][(int)(b % CP_CH) * CP_B + pw * CP_M];
+#pragma unroll
+        for (int q = 0; q < CP_M; ++q) out[q] = uniform(ir[q]);
     };
-    // two register sets: while one batch is added, the next one's rows are
-    // in flight (scheduling barriers keep the compiler from sinking the loads
-    // below the additions)
-    double va[CS_B], vb[CS_B];
-    auto rows = [&](double* v, int iv) {
+    auto rows = [&](const int* id, double* v) {
 #pragma unroll
-        for (int q = 0; q < CS_B; ++q)
-            v[q] = Yd[(int64_t)(uint32_t)__builtin_amdgcn_readlane(iv, q) * dim];
+        for (int q = 0; q < CP_M; ++q) v[q] = Yd[(int64_t)(uint32_t)id[q] * dim];
     };
-    // the ids of a batch are requested before the rows of the batch before
-    // it, so waiting for them never waits for rows still in flight
-    int i1 = ids_of(1);
-    rows(va, ids_of(0));                            // batch 0
-    double s = 0.0;
-    int64_t b = 0;
-    for (; b + 2 < nb; b += 2) {                    // batches b, b + 1 full; b + 2 exists
-        const int i2 = ids_of(b + 2);
-        rows(vb, i1);                               // batch b + 1
-        __builtin_amdgcn_sched_barrier(0);
+    auto chunk_load = [&](int64_t c, int* r) {
 #pragma unroll
-        for (int q = 0; q < CS_B; ++q) s += va[q];  // batch b
-        __builtin_amdgcn_sched_barrier(0);
-        i1 = ids_of(b + 3);
-        rows(va, i2);                               // batch b + 2
-        __builtin_amdgcn_sched_barrier(0);
+        for (int l = 0; l < CP_NL; ++l)
+            r[l] = (int)mem[min<int64_t>(c * CP_CI + l * 64 + lane, cnt - 1)];
+    };
+    auto chunk_store = [&](int64_t c, const int* r) {
 #pragma unroll
-        for (int q = 0; q < CS_B; ++q) s += vb[q];  // batch b + 1
-        __builtin_amdgcn_sched_barrier(0);
+        for (int l = 0; l < CP_NL; ++l)
+            if (l * 64 + lane < CP_CI) idbuf[c & 1][l * 64 + lane] = r[l];
+    };
+    // The two roles run separate loops with the same barrier per step, so the
+    // compiler sees the gathering waves' loads as one uninterrupted stream and
+    // waits only for the batch a step stores.  Both run whole groups of CP_S
+    // steps (steps past nb store and add nothing), so the unrolled body has no
+    // exits in it.
+    if (wave > 0) {
+        double v[CP_S][CP_M];
+        __syncthreads();                             // chunk 0 published
+        // steps -CP_S .. -1 only request the first batches (the pipeline fill
+        // is the loop itself, so no loads are pending on entry)
+        for (int64_t u0 = -CP_S; u0 <= nb; u0 += CP_S) {
+#pragma unroll
+            for (int j = 0; j < CP_S; ++j) {
+                const int64_t u = u0 + j;            // store batch u, request batch u + CP_S
+                if (u >= 0 && u < nb) {
+#pragma unroll
+                    for (int q = 0; q < CP_M; ++q) ring[u & 1][pw * CP_M + q][lane] = v[j][q];
+                }
+                int idc[CP_M];
+                ids(u + CP_S, idc);
+                rows(idc, v[j]);
+                __syncthreads();
+            }
+        }
+        // drain the requests past the last batch here: the compiler joins this
+        // path with wave 0's before the exit, and loads it believes pending
+        // there would add waits to wave 0's loop
+        __builtin_amdgcn_s_waitcnt(KM_WAIT_VM0);
+    } else {
+        int idr[CP_NL];                              // the next chunk's ids, in flight
+        chunk_load(0, idr);
+        chunk_store(0, idr);
+        chunk_load(1, idr);
+        __syncthreads();
+        double s = 0.0;
+        for (int64_t u0 = -CP_S; u0 <= nb; u0 += CP_S) {
+#pragma unroll
+            for (int j = 0; j < CP_S; ++j) {
+                const int64_t u = u0 + j;            // add batch u - 1
+                if ((u + CP_S + 1) % CP_CH == 0) {   // chunk c is first requested at step u + 1
+                    const int64_t c = (u + CP_S + 1) / CP_CH;
+                    chunk_store(c, idr);
+                    chunk_load(c + 1, idr);
+                }
+                if (u > 0 && u <= nb) {
+                    const int64_t b = u - 1;
+                    const double* rb = &ring[b & 1][0][lane];
+                    if (b + 1 < nb) {
+                        // a full batch: every read issued ahead of the additions
+                        double x[CP_B];
+#pragma unroll
+                        for (int q = 0; q < CP_B; ++q) x[q] = rb[q * 64];
+#pragma unroll
+                        for (int q = 0; q < CP_B; ++q) s += x[q];
+                    } else {
+                        const int m = (int)(cnt - b * CP_B);
+#pragma unroll
+                        for (int q = 0; q < CP_B; ++q)
+                            if (q < m) s += rb[q * 64];
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (d < dim) C[rj * dim + d] = s / (double)cnt;
     }
-    // one or two batches left: b (in va; full if b + 1 < nb), then b + 1
-    if (b + 1 < nb) {
-        rows(vb, i1);
-#pragma unroll
-        for (int q = 0; q < CS_B; ++q) s += va[q];
-#pragma unroll
-        for (int q = 0; q < CS_B; ++q) va[q] = vb[q];
-        ++b;
-    }
-    const int rest = (int)(cnt - b * CS_B);          // 1 .. CS_B members in the last batch
-#pragma unroll
-    for (int q = 0; q < CS_B; ++q)
-        if (q < rest) s += va[q];
-    if (dl) C[rj * dim + d] = s / (double)cnt;
 }
 
 // exact squared distance of every point to its assigned centre, reading the
@@ -1556,7 +1624,8 @@ sc_status kmeans_run(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx
             SC_CHECK_LAUNCH(ctx);
         }
         hipLaunchKernelGGL(k_centroid_sum, dim3((unsigned)((int64_t)R * K * ceil_div(dim, 64))),
-                           dim3(64), 0, st, dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+                           dim3(CP_NT), 0, st, dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty,
+                           w.C);
         SC_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(k_delta, dim3((unsigned)ceil_div((int64_t)R * K, TH / 64)), dim3(TH), 0, st, K,
                            R, dim, w.C, w.Cold, w.active, w.dirty, w.delta);
