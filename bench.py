@@ -683,7 +683,8 @@ def main():
         "converged": res.converged,
         "max_relres": res.max_relres,
         "solver_events": {"p_drops": res.p_drops, "w_drops": res.w_drops,
-                          "gram_fallbacks": res.gram_fallbacks, "restarts": res.restarts},
+                          "gram_fallbacks": res.gram_fallbacks, "restarts": res.restarts,
+                          "locked_cols": res.locked_cols},
         "iterations_per_s": round(iters_total / (lob_ms * 1e-3), 3) if lob_ms > 0 else None,
         "spmm_hbm_gbs_algorithmic": round(achieved, 1),
         "phase_ms_per_step": {kk: round(v["total_ms"] / args.steps, 3) for kk, v in prof.items()},

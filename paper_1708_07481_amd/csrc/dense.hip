@@ -234,6 +234,93 @@ struct GramStage {
     }
 };
 
+// One wave's piece of a workgroup tile: the MFMA sub-tiles [pa0, pa0 + NP) x
+// [qb0, qb0 + NQ) of the tile's (BT/16) x (BT/16) grid, with TRI keeping only
+// q >= p (a piece on the diagonal of a diagonal tile).  All four waves of the
+// workgroup run this loop with the same row range, so they meet at the same
+// barriers whatever their pieces.  B1s or B2s may alias As (the same columns of
+// the same matrix): the caller then skips staging them.
+template <class MF, bool TWO, int NP, int NQ, bool TRI>
+__device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca, int cb,
+                                           const float* __restrict__ A, int64_t lda,
+                                           const float* __restrict__ B1, int64_t ldb1,
+                                           const float* __restrict__ B2, int64_t ldb2,
+                                           float* As, float* B1s, float* B2s, bool ld1, bool ld2,
+                                           int pa0, int qb0, double* p1, double* p2) {
+    constexpr int BT = 32 * MF::WT;
+    constexpr int LS = BT + 16;
+    const int lane = threadIdx.x & 63, lc = lane & 15;
+    using acc_t = typename MF::acc_t;
+    acc_t acc1[NP][NQ], acc2[NP][NQ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            acc1[p][q] = acc_t{0, 0, 0, 0};
+            acc2[p][q] = acc_t{0, 0, 0, 0};
+        }
+    GramStage<BT> ga, gb1, gb2;
+    if (r0 < r1) {
+        ga.load(A, lda, r0, r1, ca, c);
+        if (ld1) gb1.load(B1, ldb1, r0, r1, cb, c);
+        if (TWO && ld2) gb2.load(B2, ldb2, r0, r1, cb, c);
+    }
+    for (int64_t row = r0; row < r1; row += GL_KC) {
+        __syncthreads();
+        ga.store(As);
+        if (ld1) gb1.store(B1s);
+        if (TWO && ld2) gb2.store(B2s);
+        __syncthreads();
+        if (row + GL_KC < r1) {                 // next chunk in flight during this one's MFMAs
+            ga.load(A, lda, row + GL_KC, r1, ca, c);
+            if (ld1) gb1.load(B1, ldb1, row + GL_KC, r1, cb, c);
+            if (TWO && ld2) gb2.load(B2, ldb2, row + GL_KC, r1, cb, c);
+        }
+#pragma unroll 2
+        for (int k = 0; k < GL_KC; k += MF::KR) {
+            typename MF::frag_t fa[NP], fb1[NQ], fb2[NQ];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) fa[p] = MF::lds(As, LS, k, 16 * (pa0 + p) + lc, lane);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                fb1[q] = MF::lds(B1s, LS, k, 16 * (qb0 + q) + lc, lane);
+                if (TWO) fb2[q] = MF::lds(B2s, LS, k, 16 * (qb0 + q) + lc, lane);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (TRI && q < p) continue;
+                    acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
+                    if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
+                }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (TRI && q < p) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = ca + 16 * (pa0 + p) + MF::out_row(lane, v);
+                const int b = cb + 16 * (qb0 + q) + lc;
+                if (a < c && b < c) {
+                    p1[(int64_t)a * c + b] = (double)acc1[p][q][v];
+                    if (TWO) p2[(int64_t)a * c + b] = (double)acc2[p][q][v];
+                }
+            }
+        }
+}
+
+// Only the upper triangle of a Gram product is reduced and mirrored, so a
+// diagonal tile (ti == tj) needs only its MFMA sub-tiles with q >= p: 55 of
+// 100 for WT = 5.  Off the diagonal each wave owns a WT x WT quarter; on it the
+// four waves split the upper sub-tiles into two diagonal triangles and the
+// off-diagonal quarter cut in two column strips (15, 15, 15 and 10 sub-tiles
+// for WT = 5), so the tile's barrier-to-barrier time follows the largest piece.
+// On a diagonal tile a B operand that is the A matrix itself (S'S, V'V) is the
+// A tile already in LDS and is not staged again.
 template <class MF, bool TWO>
 __global__ void __launch_bounds__(256)
 k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
@@ -241,8 +328,7 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
            double* __restrict__ partial, int tiles, const int* __restrict__ pred) {
     if (pred && *pred == 0) return;
     constexpr int WT = MF::WT;
-    constexpr int WTILE = 16 * WT;
-    constexpr int BT = 2 * WTILE;
+    constexpr int BT = 32 * WT;
     constexpr int LS = BT + 16;
     __shared__ __attribute__((aligned(16))) float As[GL_KC * LS];
     __shared__ __attribute__((aligned(16))) float B1s[GL_KC * LS];
@@ -256,71 +342,40 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
     const int chunk = blockIdx.y;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min<int64_t>(n, r0 + chunk_rows);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int ca = ti * BT, cb = tj * BT;
-    const int wa = (wave >> 1) * WTILE, wb = (wave & 1) * WTILE;
-    using acc_t = typename MF::acc_t;
-    acc_t acc1[WT][WT], acc2[WT][WT];
-#pragma unroll
-    for (int p = 0; p < WT; ++p)
-#pragma unroll
-        for (int q = 0; q < WT; ++q) {
-            acc1[p][q] = acc_t{0, 0, 0, 0};
-            acc2[p][q] = acc_t{0, 0, 0, 0};
-        }
-    const int lc = lane & 15;
-    GramStage<BT> ga, gb1, gb2;
-    if (r0 < r1) {
-        ga.load(A, lda, r0, r1, ca, c);
-        gb1.load(B1, ldb1, r0, r1, cb, c);
-        if (TWO) gb2.load(B2, ldb2, r0, r1, cb, c);
-    }
-    for (int64_t row = r0; row < r1; row += GL_KC) {
-        __syncthreads();
-        ga.store(As);
-        gb1.store(B1s);
-        if (TWO) gb2.store(B2s);
-        __syncthreads();
-        if (row + GL_KC < r1) {                 // next chunk in flight during this one's MFMAs
-            ga.load(A, lda, row + GL_KC, r1, ca, c);
-            gb1.load(B1, ldb1, row + GL_KC, r1, cb, c);
-            if (TWO) gb2.load(B2, ldb2, row + GL_KC, r1, cb, c);
-        }
-#pragma unroll 2
-        for (int k = 0; k < GL_KC; k += MF::KR) {
-            typename MF::frag_t fa[WT], fb1[WT], fb2[WT];
-#pragma unroll
-            for (int p = 0; p < WT; ++p) fa[p] = MF::lds(As, LS, k, wa + 16 * p + lc, lane);
-#pragma unroll
-            for (int q = 0; q < WT; ++q) {
-                fb1[q] = MF::lds(B1s, LS, k, wb + 16 * q + lc, lane);
-                if (TWO) fb2[q] = MF::lds(B2s, LS, k, wb + 16 * q + lc, lane);
-            }
-#pragma unroll
-            for (int p = 0; p < WT; ++p)
-#pragma unroll
-                for (int q = 0; q < WT; ++q) {
-                    acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
-                    if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
-                }
-        }
-    }
     const int64_t cc2 = (int64_t)c * c;
     double* p1 = partial + (int64_t)chunk * (TWO ? 2 : 1) * cc2;
     double* p2 = p1 + cc2;
-#pragma unroll
-    for (int p = 0; p < WT; ++p)
-#pragma unroll
-        for (int q = 0; q < WT; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int a = ca + wa + 16 * p + MF::out_row(lane, v);
-                const int b = cb + wb + 16 * q + lc;
-                if (a < c && b < c) {
-                    p1[(int64_t)a * c + b] = (double)acc1[p][q][v];
-                    if (TWO) p2[(int64_t)a * c + b] = (double)acc2[p][q][v];
-                }
-            }
+    if (ti != tj) {
+        gram_piece<MF, TWO, WT, WT, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, B1s,
+                                           B2s, true, true, (wave >> 1) * WT, (wave & 1) * WT, p1,
+                                           p2);
+        return;
+    }
+    const bool same1 = B1 == A && ldb1 == lda;
+    const bool same2 = TWO && B2 == A && ldb2 == lda;
+    float* b1s = same1 ? As : B1s;
+    float* b2s = same2 ? As : B2s;
+    constexpr int QA = (WT + 1) / 2, QB = WT / 2;
+    switch (wave) {
+    case 0:
+        gram_piece<MF, TWO, WT, WT, true>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                          b2s, !same1, !same2, 0, 0, p1, p2);
+        break;
+    case 1:
+        gram_piece<MF, TWO, WT, WT, true>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                          b2s, !same1, !same2, WT, WT, p1, p2);
+        break;
+    case 2:
+        gram_piece<MF, TWO, WT, QA, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                           b2s, !same1, !same2, 0, WT, p1, p2);
+        break;
+    default:
+        gram_piece<MF, TWO, WT, QB, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                           b2s, !same1, !same2, 0, WT + QA, p1, p2);
+        break;
+    }
 }
 
 // sum the chunk partials in chunk order; upper entries, mirrored
@@ -963,7 +1018,7 @@ constexpr int RG_WR = 2;
 constexpr int RG_BM = 4 * 16 * RG_WR;
 constexpr int RG_KC = 32;
 
-template <int NC>
+template <int NC, bool TRI>
 __global__ void __launch_bounds__(256)
 k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
                const float* __restrict__ M, int ldm, int nout, int o1, int o2) {
@@ -1049,6 +1104,39 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
             }
         }
     };
+    // M upper triangular (M[k][j] = 0 for k > j, the Cholesky-QR factor): the
+    // MFMA over rows k .. k + 3 of M reaches only the output tiles j with
+    // 16 j + 15 >= k, so tiles left of (k / 16) are skipped.  Chunks and k
+    // steps are unrolled, which makes each step's first tile a constant.
+    // Skipped products are exact zeros, so the sums are unchanged.
+    auto section_tri = [&](int hi) {
+        if (hi > 0) load(0, min(RG_KC, hi));
+#pragma unroll
+        for (int i = 0; i < (16 * NC + RG_KC - 1) / RG_KC; ++i) {
+            const int kc = i * RG_KC;
+            if (kc >= hi) break;
+            __syncthreads();
+            stage();
+            __syncthreads();
+            if (kc + RG_KC < hi) load(kc + RG_KC, min(RG_KC, hi - kc - RG_KC));
+#pragma unroll
+            for (int kk = 0; kk < RG_KC; kk += 4) {
+                const int j0 = (kc + kk) / 16;
+                float af[RG_WR], bf[NC];
+#pragma unroll
+                for (int w = 0; w < RG_WR; ++w) af[w] = Vs[(wr0 + 16 * w + l16) * VS + kk + lk];
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    if (j >= j0) bf[j] = Ms[(kk + lk) * MS + 16 * j + l16];
+#pragma unroll
+                for (int w = 0; w < RG_WR; ++w)
+#pragma unroll
+                    for (int j = 0; j < NC; ++j)
+                        if (j >= j0)
+                            acc[w][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[w], bf[j], acc[w][j], 0, 0, 0);
+            }
+        }
+    };
     auto store = [&](int o) {
 #pragma unroll
         for (int w = 0; w < RG_WR; ++w)
@@ -1063,6 +1151,11 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
                 }
             }
     };
+    if (TRI) {                                   // a0 = 0, no second section
+        section_tri(a1);
+        store(o1);
+        return;
+    }
     if (b1 > b0) {
         section(b0, b1);
         if (o2 >= 0) store(o2);
@@ -1073,9 +1166,15 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
 
 template <int NC>
 static void rowgemm_mfma_go(sc_ctx* ctx, int64_t n, float* V, int64_t ld, int a0, int a1, int b0,
-                            int b1, const float* M, int ldm, int nout, int o1, int o2) {
-    hipLaunchKernelGGL((k_rowgemm_mfma<NC>), dim3((unsigned)ceil_div(n, RG_BM)), dim3(256), 0,
-                       ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+                            int b1, const float* M, int ldm, int nout, int o1, int o2, bool tri) {
+    if (tri)
+        hipLaunchKernelGGL((k_rowgemm_mfma<NC, true>), dim3((unsigned)ceil_div(n, RG_BM)),
+                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1,
+                           o2);
+    else
+        hipLaunchKernelGGL((k_rowgemm_mfma<NC, false>), dim3((unsigned)ceil_div(n, RG_BM)),
+                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1,
+                           o2);
 }
 
 template <class T, int NC>
@@ -1087,23 +1186,28 @@ static void rowgemm_go(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1,
                        ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
 }
 
+// tri: M is upper triangular with a0 = 0 and an empty second section (the
+// matrix-core path then skips the all-zero products)
 template <class T>
 static sc_status rowgemm(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
-                         const T* M, int ldm, int nout, int o1, int o2) {
+                         const T* M, int ldm, int nout, int o1, int o2, bool tri = false) {
+    if (tri && (a0 != 0 || b1 > b0))
+        return sc_fail(ctx, SC_E_INVAL, "rowgemm: triangular factor with sections [%d,%d) [%d,%d)",
+                       a0, a1, b0, b1);
     const int nc = (nout + 15) / 16;
     if constexpr (sizeof(T) == 4) {
         // matrix-core path: 16-byte aligned rows and section starts
         if (((uintptr_t)V % 16) == 0 && ld % 4 == 0 && a0 % 4 == 0 && b0 % 4 == 0 && nout <= 256) {
             switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
-                case 1: rowgemm_mfma_go<1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 2: rowgemm_mfma_go<2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 3: rowgemm_mfma_go<3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 4: rowgemm_mfma_go<4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 6: rowgemm_mfma_go<6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 8: rowgemm_mfma_go<8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 10: rowgemm_mfma_go<10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                case 12: rowgemm_mfma_go<12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-                default: rowgemm_mfma_go<16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+                case 1: rowgemm_mfma_go<1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 2: rowgemm_mfma_go<2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 3: rowgemm_mfma_go<3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 4: rowgemm_mfma_go<4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 6: rowgemm_mfma_go<6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 8: rowgemm_mfma_go<8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 10: rowgemm_mfma_go<10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 12: rowgemm_mfma_go<12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                default: rowgemm_mfma_go<16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
             }
             SC_CHECK_LAUNCH(ctx);
             return SC_OK;
@@ -1131,8 +1235,8 @@ template <class T>
 sc_status launch_apply_right(sc_ctx* ctx, int64_t n, int c, T* V, int64_t ldv, T* V2, int64_t ldv2,
                              const double* T64, const float* T32) {
     const T* M = Prec<T>::pick(T64, T32);
-    SC_TRY(rowgemm<T>(ctx, n, V, ldv, 0, c, 0, 0, M, c, c, 0, -1));
-    if (V2) SC_TRY(rowgemm<T>(ctx, n, V2, ldv2, 0, c, 0, 0, M, c, c, 0, -1));
+    SC_TRY(rowgemm<T>(ctx, n, V, ldv, 0, c, 0, 0, M, c, c, 0, -1, true));
+    if (V2) SC_TRY(rowgemm<T>(ctx, n, V2, ldv2, 0, c, 0, 0, M, c, c, 0, -1, true));
     return SC_OK;
 }
 template sc_status launch_apply_right<double>(sc_ctx*, int64_t, int, double*, int64_t, double*,
