@@ -203,6 +203,18 @@ struct GramStage {
     // global -> registers (issued ahead of the compute on the previous chunk)
     __device__ void load(const float* __restrict__ M, int64_t ld, int64_t row, int64_t r1, int col0,
                          int c) {
+        if (row + GL_KC <= r1 && col0 + BT <= c) {
+            // a whole chunk inside the matrix: plain loads, no per-element tests
+            // (the issue slots between the matrix-core instructions stay free)
+            const float* base = M + row * ld + col0;
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int q = threadIdx.x + 256 * u;
+                const int rr = q / V4, cc = 4 * (q % V4);
+                v[u] = *reinterpret_cast<const float4*>(base + rr * ld + cc);
+            }
+            return;
+        }
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int q = threadIdx.x + 256 * u;
@@ -1042,14 +1054,18 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
     float4 rv[PV];
     float rm[PM];
     auto load = [&](int kc, int kn) {
+        // whole tiles take plain loads, with no per-element tests
+        const bool whole = kn == RG_KC && row0 + RG_BM <= n && nout == 16 * NC;
 #pragma unroll
         for (int u = 0; u < PV; ++u) {
             const int q = tid + 256 * u;
             const int r = q / (RG_KC / 4), c4 = 4 * (q % (RG_KC / 4));
             const int64_t row = row0 + r;
+            const float* src = V + row * ld + kc + c4;
             float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row < n) {
-                const float* src = V + row * ld + kc + c4;
+            if (whole) {
+                x = *reinterpret_cast<const float4*>(src);
+            } else if (row < n) {
                 if (c4 + 3 < kn) {
                     x = *reinterpret_cast<const float4*>(src);
                 } else {
@@ -1064,7 +1080,8 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
         for (int u = 0; u < PM; ++u) {
             const int q = tid + 256 * u;
             const int k = q / (16 * NC), j = q % (16 * NC);
-            rm[u] = (q < RG_KC * 16 * NC && k < kn && j < nout) ? M[(int64_t)(kc + k) * ldm + j] : 0.0f;
+            const bool in = q < RG_KC * 16 * NC;
+            rm[u] = (in && (whole || (k < kn && j < nout))) ? M[(int64_t)(kc + k) * ldm + j] : 0.0f;
         }
     };
     auto stage = [&]() {
