@@ -246,6 +246,50 @@ struct GramStage {
     }
 };
 
+// Workgroup -> (tile pair, row chunk) for a 1-D launch of upper x chunks
+// workgroups.  Consecutive workgroups go to the eight XCDs in turn, so the
+// pairs of chunk c are given ids that are all congruent to c mod 8: every
+// tile pair of a chunk runs on the same XCD at about the same time, and the
+// rows the pairs share come from that XCD's L2 instead of HBM.  Chunks past
+// the last full group of eight are dealt in plain order.
+__device__ __forceinline__ void gram_block(int upper, int chunks, int& pair, int& chunk) {
+    constexpr int NX = 8;
+    const int L = (int)blockIdx.x;
+    const int full = chunks / NX * NX;
+    if (L < upper * full) {
+        const int g = L / (NX * upper), rem = L % (NX * upper);
+        pair = rem / NX;
+        chunk = g * NX + rem % NX;
+    } else {
+        const int L2 = L - upper * full, r = chunks - full;
+        pair = L2 / r;
+        chunk = full + L2 % r;
+    }
+}
+
+// MFMAs per k step of a wave's piece, and how many of them go between two
+// fragment reads when the next step's reads are spread over this step
+template <int NP, int NQ, bool TRI, bool TWO>
+struct MfCount {
+    static constexpr int tiles = TRI ? NP * (NP + 1) / 2 : NP * NQ;
+    static constexpr int mfma = tiles * (TWO ? 2 : 1);
+    static constexpr int reads = NP + NQ * (TWO ? 2 : 1);
+    static constexpr int per_read = mfma / reads > 0 ? mfma / reads : 1;
+};
+// scheduling hint: N groups of (one LDS read, PER MFMAs)
+template <int N, int PER>
+struct MfInterleave {
+    __device__ static void hint() {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);     // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);   // MFMA
+        MfInterleave<N - 1, PER>::hint();
+    }
+};
+template <int PER>
+struct MfInterleave<0, PER> {
+    __device__ static void hint() {}
+};
+
 // One wave's piece of a workgroup tile: the MFMA sub-tiles [pa0, pa0 + NP) x
 // [qb0, qb0 + NQ) of the tile's (BT/16) x (BT/16) grid, with TRI keeping only
 // q >= p (a piece on the diagonal of a diagonal tile).  All four waves of the
@@ -288,24 +332,36 @@ __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca
             if (ld1) gb1.load(B1, ldb1, row + GL_KC, r1, cb, c);
             if (TWO && ld2) gb2.load(B2, ldb2, row + GL_KC, r1, cb, c);
         }
-#pragma unroll 2
-        for (int k = 0; k < GL_KC; k += MF::KR) {
-            typename MF::frag_t fa[NP], fb1[NQ], fb2[NQ];
+        // k steps of the chunk, unrolled: the fragments of step s + 1 are read
+        // from LDS while the MFMAs of step s run (two fragment sets), and the
+        // scheduler is asked to spread those reads between the MFMAs, so the
+        // matrix cores do not wait on LDS latency at every step
+        constexpr int KS = GL_KC / MF::KR;
+        typename MF::frag_t fa[2][NP], fb1[2][NQ], fb2[2][NQ];
+        auto frags = [&](int k, int b) {
 #pragma unroll
-            for (int p = 0; p < NP; ++p) fa[p] = MF::lds(As, LS, k, 16 * (pa0 + p) + lc, lane);
+            for (int p = 0; p < NP; ++p) fa[b][p] = MF::lds(As, LS, k, 16 * (pa0 + p) + lc, lane);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                fb1[q] = MF::lds(B1s, LS, k, 16 * (qb0 + q) + lc, lane);
-                if (TWO) fb2[q] = MF::lds(B2s, LS, k, 16 * (qb0 + q) + lc, lane);
+                fb1[b][q] = MF::lds(B1s, LS, k, 16 * (qb0 + q) + lc, lane);
+                if (TWO) fb2[b][q] = MF::lds(B2s, LS, k, 16 * (qb0 + q) + lc, lane);
             }
+        };
+        frags(0, 0);
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int b = st & 1;
+            if (st + 1 < KS) frags((st + 1) * MF::KR, b ^ 1);
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (TRI && q < p) continue;
-                    acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
-                    if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
+                    acc1[p][q] = MF::mma(fa[b][p], fb1[b][q], acc1[p][q]);
+                    if (TWO) acc2[p][q] = MF::mma(fa[b][p], fb2[b][q], acc2[p][q]);
                 }
+            if (st + 1 < KS) MfInterleave<NP + NQ * (TWO ? 2 : 1),
+                                          MfCount<NP, NQ, TRI, TWO>::per_read>::hint();
         }
     }
 #pragma unroll
@@ -337,7 +393,7 @@ template <class MF, bool TWO>
 __global__ void __launch_bounds__(256)
 k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
            const float* __restrict__ B1, int64_t ldb1, const float* __restrict__ B2, int64_t ldb2,
-           double* __restrict__ partial, int tiles, const int* __restrict__ pred) {
+           double* __restrict__ partial, int tiles, int chunks, const int* __restrict__ pred) {
     if (pred && *pred == 0) return;
     constexpr int WT = MF::WT;
     constexpr int BT = 32 * WT;
@@ -345,13 +401,14 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
     __shared__ __attribute__((aligned(16))) float As[GL_KC * LS];
     __shared__ __attribute__((aligned(16))) float B1s[GL_KC * LS];
     __shared__ __attribute__((aligned(16))) float B2s[TWO ? GL_KC * LS : 4];
-    int t = blockIdx.x, ti = 0;
+    int t, chunk;
+    gram_block(tiles * (tiles + 1) / 2, chunks, t, chunk);
+    int ti = 0;
     while (t >= tiles - ti) {
         t -= tiles - ti;
         ++ti;
     }
     const int tj = ti + t;
-    const int chunk = blockIdx.y;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min<int64_t>(n, r0 + chunk_rows);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -954,13 +1011,15 @@ static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, 
     if constexpr (sizeof(typename MF::in_t) == 4) {
         constexpr size_t es = sizeof(float);
         if (aligned16(A, lda, es) && aligned16(B1, ldb1, es) && aligned16(B2, ldb2, es)) {
+            const dim3 grid1((unsigned)(upper * p.chunks));
             if (B2)
-                hipLaunchKernelGGL((k_gram_lds<MF, true>), grid, dim3(256), 0, ctx->stream, p.n, p.c,
-                                   p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles, pred);
+                hipLaunchKernelGGL((k_gram_lds<MF, true>), grid1, dim3(256), 0, ctx->stream, p.n,
+                                   p.c, p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles,
+                                   p.chunks, pred);
             else
-                hipLaunchKernelGGL((k_gram_lds<MF, false>), grid, dim3(256), 0, ctx->stream, p.n,
+                hipLaunchKernelGGL((k_gram_lds<MF, false>), grid1, dim3(256), 0, ctx->stream, p.n,
                                    p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles,
-                                   pred);
+                                   p.chunks, pred);
             return;
         }
     }
