@@ -76,6 +76,12 @@ extern "C" sc_status sc_ctx_create(int device, void* hip_stream, sc_ctx** out) {
         delete c;
         return SC_E_HIP;
     }
+    if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess ||
+        c->num_cu <= 0) {
+        delete c;
+        return SC_E_HIP;
+    }
     c->stage_bytes = 1 << 16;
     if (hipHostMalloc(&c->stage, c->stage_bytes, hipHostMallocDefault) != hipSuccess) {
         delete c;

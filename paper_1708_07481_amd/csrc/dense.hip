@@ -246,50 +246,6 @@ struct GramStage {
     }
 };
 
-// Workgroup -> (tile pair, row chunk) for a 1-D launch of upper x chunks
-// workgroups.  Consecutive workgroups go to the eight XCDs in turn, so the
-// pairs of chunk c are given ids that are all congruent to c mod 8: every
-// tile pair of a chunk runs on the same XCD at about the same time, and the
-// rows the pairs share come from that XCD's L2 instead of HBM.  Chunks past
-// the last full group of eight are dealt in plain order.
-__device__ __forceinline__ void gram_block(int upper, int chunks, int& pair, int& chunk) {
-    constexpr int NX = 8;
-    const int L = (int)blockIdx.x;
-    const int full = chunks / NX * NX;
-    if (L < upper * full) {
-        const int g = L / (NX * upper), rem = L % (NX * upper);
-        pair = rem / NX;
-        chunk = g * NX + rem % NX;
-    } else {
-        const int L2 = L - upper * full, r = chunks - full;
-        pair = L2 / r;
-        chunk = full + L2 % r;
-    }
-}
-
-// MFMAs per k step of a wave's piece, and how many of them go between two
-// fragment reads when the next step's reads are spread over this step
-template <int NP, int NQ, bool TRI, bool TWO>
-struct MfCount {
-    static constexpr int tiles = TRI ? NP * (NP + 1) / 2 : NP * NQ;
-    static constexpr int mfma = tiles * (TWO ? 2 : 1);
-    static constexpr int reads = NP + NQ * (TWO ? 2 : 1);
-    static constexpr int per_read = mfma / reads > 0 ? mfma / reads : 1;
-};
-// scheduling hint: N groups of (one LDS read, PER MFMAs)
-template <int N, int PER>
-struct MfInterleave {
-    __device__ static void hint() {
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);     // LDS read
-        __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);   // MFMA
-        MfInterleave<N - 1, PER>::hint();
-    }
-};
-template <int PER>
-struct MfInterleave<0, PER> {
-    __device__ static void hint() {}
-};
-
 // One wave's piece of a workgroup tile: the MFMA sub-tiles [pa0, pa0 + NP) x
 // [qb0, qb0 + NQ) of the tile's (BT/16) x (BT/16) grid, with TRI keeping only
 // q >= p (a piece on the diagonal of a diagonal tile).  All four waves of the
@@ -332,36 +288,24 @@ __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca
             if (ld1) gb1.load(B1, ldb1, row + GL_KC, r1, cb, c);
             if (TWO && ld2) gb2.load(B2, ldb2, row + GL_KC, r1, cb, c);
         }
-        // k steps of the chunk, unrolled: the fragments of step s + 1 are read
-        // from LDS while the MFMAs of step s run (two fragment sets), and the
-        // scheduler is asked to spread those reads between the MFMAs, so the
-        // matrix cores do not wait on LDS latency at every step
-        constexpr int KS = GL_KC / MF::KR;
-        typename MF::frag_t fa[2][NP], fb1[2][NQ], fb2[2][NQ];
-        auto frags = [&](int k, int b) {
+#pragma unroll 2
+        for (int k = 0; k < GL_KC; k += MF::KR) {
+            typename MF::frag_t fa[NP], fb1[NQ], fb2[NQ];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) fa[b][p] = MF::lds(As, LS, k, 16 * (pa0 + p) + lc, lane);
+            for (int p = 0; p < NP; ++p) fa[p] = MF::lds(As, LS, k, 16 * (pa0 + p) + lc, lane);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                fb1[b][q] = MF::lds(B1s, LS, k, 16 * (qb0 + q) + lc, lane);
-                if (TWO) fb2[b][q] = MF::lds(B2s, LS, k, 16 * (qb0 + q) + lc, lane);
+                fb1[q] = MF::lds(B1s, LS, k, 16 * (qb0 + q) + lc, lane);
+                if (TWO) fb2[q] = MF::lds(B2s, LS, k, 16 * (qb0 + q) + lc, lane);
             }
-        };
-        frags(0, 0);
-#pragma unroll
-        for (int st = 0; st < KS; ++st) {
-            const int b = st & 1;
-            if (st + 1 < KS) frags((st + 1) * MF::KR, b ^ 1);
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (TRI && q < p) continue;
-                    acc1[p][q] = MF::mma(fa[b][p], fb1[b][q], acc1[p][q]);
-                    if (TWO) acc2[p][q] = MF::mma(fa[b][p], fb2[b][q], acc2[p][q]);
+                    acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
+                    if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
                 }
-            if (st + 1 < KS) MfInterleave<NP + NQ * (TWO ? 2 : 1),
-                                          MfCount<NP, NQ, TRI, TWO>::per_read>::hint();
         }
     }
 #pragma unroll
@@ -381,34 +325,16 @@ __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca
         }
 }
 
-// Only the upper triangle of a Gram product is reduced and mirrored, so a
-// diagonal tile (ti == tj) needs only its MFMA sub-tiles with q >= p: 55 of
-// 100 for WT = 5.  Off the diagonal each wave owns a WT x WT quarter; on it the
-// four waves split the upper sub-tiles into two diagonal triangles and the
-// off-diagonal quarter cut in two column strips (15, 15, 15 and 10 sub-tiles
-// for WT = 5), so the tile's barrier-to-barrier time follows the largest piece.
-// On a diagonal tile a B operand that is the A matrix itself (S'S, V'V) is the
-// A tile already in LDS and is not staged again.
+// one (tile pair, row chunk) item of the FP32 Gram kernel
 template <class MF, bool TWO>
-__global__ void __launch_bounds__(256)
-k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
-           const float* __restrict__ B1, int64_t ldb1, const float* __restrict__ B2, int64_t ldb2,
-           double* __restrict__ partial, int tiles, int chunks, const int* __restrict__ pred) {
-    if (pred && *pred == 0) return;
+__device__ __forceinline__ void gram_tile(int64_t n, int c, int64_t chunk_rows,
+                                          const float* __restrict__ A, int64_t lda,
+                                          const float* __restrict__ B1, int64_t ldb1,
+                                          const float* __restrict__ B2, int64_t ldb2,
+                                          double* __restrict__ partial, int ti, int tj, int chunk,
+                                          float* As, float* B1s, float* B2s) {
     constexpr int WT = MF::WT;
     constexpr int BT = 32 * WT;
-    constexpr int LS = BT + 16;
-    __shared__ __attribute__((aligned(16))) float As[GL_KC * LS];
-    __shared__ __attribute__((aligned(16))) float B1s[GL_KC * LS];
-    __shared__ __attribute__((aligned(16))) float B2s[TWO ? GL_KC * LS : 4];
-    int t, chunk;
-    gram_block(tiles * (tiles + 1) / 2, chunks, t, chunk);
-    int ti = 0;
-    while (t >= tiles - ti) {
-        t -= tiles - ti;
-        ++ti;
-    }
-    const int tj = ti + t;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
     const int64_t r1 = min<int64_t>(n, r0 + chunk_rows);
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -444,6 +370,81 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
         gram_piece<MF, TWO, WT, QB, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
                                            b2s, !same1, !same2, 0, WT + QA, p1, p2);
         break;
+    }
+}
+
+// Only the upper triangle of a Gram product is reduced and mirrored, so a
+// diagonal tile (ti == tj) needs only its MFMA sub-tiles with q >= p: 55 of
+// 100 for WT = 5.  Off the diagonal each wave owns a WT x WT quarter; on it the
+// four waves split the upper sub-tiles into two diagonal triangles and the
+// off-diagonal quarter cut in two column strips (15, 15, 15 and 10 sub-tiles
+// for WT = 5), so the tile's barrier-to-barrier time follows the largest piece.
+// On a diagonal tile a B operand that is the A matrix itself (S'S, V'V) is the
+// A tile already in LDS and is not staged again.
+//
+// PERSIST: as many workgroups as fit on the device at once (one per CU here)
+// take (tile pair, chunk) items from a counter.  Measured per workgroup,
+// one-item-per-workgroup launches left a CU idle about 120 us between items
+// and spread 5 to 8 items over the CUs, 17 % of the kernel's time.  The BF16
+// instantiation stays one item per workgroup: its loop would spill.
+// Item -> (tile pair, chunk): the off-diagonal (longer) items first, so the
+// last items to finish are short.
+__device__ __forceinline__ void gram_item(int item, int tiles, int chunks, int& ti, int& tj,
+                                          int& chunk) {
+    const int noff = tiles * (tiles - 1) / 2;
+    if (item < noff * chunks) {
+        int m = item % noff;
+        chunk = item / noff;
+        ti = 0;
+        while (m >= tiles - 1 - ti) {           // off-diagonal pairs of row ti: tj > ti
+            m -= tiles - 1 - ti;
+            ++ti;
+        }
+        tj = ti + 1 + m;
+    } else {
+        const int j = item - noff * chunks;
+        ti = tj = j % tiles;
+        chunk = j / tiles;
+    }
+}
+
+template <class MF, bool TWO, bool PERSIST>
+__global__ void __launch_bounds__(256)
+k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
+           const float* __restrict__ B1, int64_t ldb1, const float* __restrict__ B2, int64_t ldb2,
+           double* __restrict__ partial, int tiles, int chunks, int* __restrict__ queue,
+           const int* __restrict__ pred) {
+    if (pred && *pred == 0) return;
+    constexpr int WT = MF::WT;
+    constexpr int BT = 32 * WT;
+    constexpr int LS = BT + 16;
+    __shared__ __attribute__((aligned(16))) float As[GL_KC * LS];
+    __shared__ __attribute__((aligned(16))) float B1s[GL_KC * LS];
+    __shared__ __attribute__((aligned(16))) float B2s[TWO ? GL_KC * LS : 4];
+    const int upper = tiles * (tiles + 1) / 2;
+    const int items = upper * chunks;
+    if (!PERSIST) {                             // one item per workgroup
+        int ti, tj, chunk;
+        gram_item((int)blockIdx.x, tiles, chunks, ti, tj, chunk);
+        gram_tile<MF, TWO>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj, chunk,
+                           As, B1s, B2s);
+        return;
+    }
+    __shared__ int item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        const int item = item_s;
+        __syncthreads();
+        if (item >= items) break;
+        int ti, tj, chunk;
+        gram_item(item, tiles, chunks, ti, tj, chunk);
+        gram_tile<MF, TWO>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj, chunk,
+                           As, B1s, B2s);
+    }
+    if (threadIdx.x == 0 && atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {   // PERSIST only
+        atomicExch(&queue[0], 0);               // last one out: ready for the next launch
+        atomicExch(&queue[1], 0);
     }
 }
 
@@ -1002,6 +1003,23 @@ static bool aligned16(const void* ptr, int64_t ld, size_t es) {
     return ptr == nullptr || (((uintptr_t)ptr % 16) == 0 && ((size_t)ld * es) % 16 == 0);
 }
 
+// workgroups of a persistent FP32 Gram launch: as many as are resident at once
+// (occupancy of the instantiation x compute units), at most one per item
+template <class MF, bool TWO>
+static unsigned gram_grid(sc_ctx* ctx, unsigned items) {
+    static int per_cu = -1;                  // one value per kernel instantiation
+    if (per_cu < 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &b, reinterpret_cast<const void*>(k_gram_lds<MF, TWO, true>), 256, 0) !=
+                hipSuccess ||
+            b < 1)
+            b = 1;
+        per_cu = b;
+    }
+    return std::min<unsigned>(items, (unsigned)(per_cu * ctx->num_cu));
+}
+
 template <class MF>
 static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, int64_t lda,
                     const typename MF::in_t* B1, int64_t ldb1, const typename MF::in_t* B2,
@@ -1010,16 +1028,22 @@ static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, 
     dim3 grid(upper, p.chunks);
     if constexpr (sizeof(typename MF::in_t) == 4) {
         constexpr size_t es = sizeof(float);
-        if (aligned16(A, lda, es) && aligned16(B1, ldb1, es) && aligned16(B2, ldb2, es)) {
-            const dim3 grid1((unsigned)(upper * p.chunks));
+        if (p.queue && aligned16(A, lda, es) && aligned16(B1, ldb1, es) && aligned16(B2, ldb2, es)) {
+            const unsigned items = (unsigned)(upper * p.chunks);
+            constexpr bool PS = !std::is_same<MF, MfBF16>::value;
+            unsigned g2 = items, g1 = items;
+            if constexpr (PS) {
+                g2 = gram_grid<MF, true>(ctx, items);
+                g1 = gram_grid<MF, false>(ctx, items);
+            }
             if (B2)
-                hipLaunchKernelGGL((k_gram_lds<MF, true>), grid1, dim3(256), 0, ctx->stream, p.n,
-                                   p.c, p.chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, p.tiles,
-                                   p.chunks, pred);
+                hipLaunchKernelGGL((k_gram_lds<MF, true, PS>), dim3(g2), dim3(256), 0,
+                                   ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B2, ldb2,
+                                   partial, p.tiles, p.chunks, p.queue, pred);
             else
-                hipLaunchKernelGGL((k_gram_lds<MF, false>), grid1, dim3(256), 0, ctx->stream, p.n,
-                                   p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1, partial, p.tiles,
-                                   p.chunks, pred);
+                hipLaunchKernelGGL((k_gram_lds<MF, false, PS>), dim3(g1), dim3(256), 0,
+                                   ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1,
+                                   partial, p.tiles, p.chunks, p.queue, pred);
             return;
         }
     }

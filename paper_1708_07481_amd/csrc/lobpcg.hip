@@ -96,6 +96,7 @@ struct sc_lobpcg_state {
     // accumulation, [5] Gram-precision probe flag of the current iteration,
     // [6] inconsistent-iterate flag of the last residual
     int *act, *status, *pdrops, *all_locked, *wdrops, *gram_fallbacks, *gflag, *restart_flag;
+    int* gram_queue;                // work counters of the persistent Gram launches
     int32_t* row_order;             // rows longest first, for the SpMM's row groups
     void* order_scr;                // scratch of the sort that makes it
     GramPlan plan3{}, plan3x{}, plank{};
@@ -156,6 +157,8 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.gram_fallbacks = s.status + 4;
     s.gflag = s.status + 5;
     s.restart_flag = s.status + 6;
+    s.gram_queue = c.take<int>(2);
+    s.plan3.queue = s.plan3x.queue = s.plank.queue = s.gram_queue;
     s.row_order = c.take<int32_t>((size_t)n);
     s.order_scr = c.take<char>(row_order_scratch_bytes(n));
     return c.size();
@@ -337,6 +340,8 @@ struct Solver {
         hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->S, words);
         hipLaunchKernelGGL(k_fill_bytes, dim3(2048), dim3(256), 0, st, (uint32_t*)s->LS, words);
         hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->status, (int64_t)8);
+        hipLaunchKernelGGL(k_fill_bytes, dim3(1), dim3(64), 0, st, (uint32_t*)s->gram_queue,
+                           (int64_t)2);
         SC_CHECK_LAUNCH(ctx);
         // the SpMM's row groups take the rows longest first, so that the long
         // rows of high-degree vertices do not trail each launch

@@ -13,6 +13,7 @@
 
 struct sc_ctx {
     int device = 0;
+    int num_cu = 0;                 // compute units of the device (persistent launches)
     hipStream_t stream = nullptr;
     std::string err;
     // pinned host staging area for the small device-to-host reads of the
@@ -173,6 +174,11 @@ struct GramPlan {
     int64_t chunk_rows; // rows per chunk (multiple of 32)
     int bt;             // workgroup output tile edge
     int tiles;          // tiles per side
+    // two zeroed ints of device memory owned by the caller: the FP32 kernels
+    // run as persistent workgroups that take (tile pair, chunk) items from
+    // this counter, and the last workgroup out zeroes both again, so launches
+    // on one stream can share them (nullptr: the unstaged FP32 kernel)
+    int* queue = nullptr;
 };
 // Gram precision for FP32 data: native FP32 MFMA, BF16-rounded inputs, or
 // widened to FP64 (exact products, FP64 accumulation).  FP64 data always
