@@ -678,6 +678,9 @@ def main():
                                    else f"k-means restarts={restarts}")),
                    "name": args.config, "n": n, "nnz": gd.nnz, "k": k},
         "lobpcg_iterations": res.iterations,
+        "converged_cols_per_iteration": ([] if res.relres_hist is None else
+                                         [int((row[:k] <= cfg["tol"]).sum())
+                                          for row in res.relres_hist]),
         "clusters": getattr(km, "clusters", k),
         "kmeans_lloyd_iterations": km.lloyd_iterations,
         "converged": res.converged,

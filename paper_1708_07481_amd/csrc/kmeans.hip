@@ -1061,7 +1061,7 @@ __device__ inline bool km_needs_update(int64_t rj, int K, const int* active, con
 }
 
 // One workgroup per (cluster, 64-coordinate slab): wave 0 runs the chains
-// (lane = coordinate) and waves 1 .. CP_PW gather member rows for it.  A
+// (lane = coordinate) and waves 1 .. PW gather member rows for it.  A
 // single wave doing both issues about ten instructions per member (id
 // read-out, address, load, addition), and a wave issues at most one
 // instruction every four cycles; split this way the chain costs a shared-
@@ -1082,21 +1082,31 @@ __device__ inline bool km_needs_update(int64_t rj, int K, const int* active, con
 // clamped to it and never stored.
 // s_waitcnt immediate (gfx9 layout) for vmcnt(0) with expcnt and lgkmcnt left free
 constexpr int KM_WAIT_VM0 = (0x7 << 4) | (0xF << 8);
-constexpr int CP_PW = 3;                   // gathering waves
 constexpr int CP_M = 15;                   // members per gathering wave and batch
-constexpr int CP_B = CP_PW * CP_M;         // members per batch
 constexpr int CP_S = 4;                    // batches in flight per gathering wave
 constexpr int CP_CH = 16;                  // batches per id chunk
-constexpr int CP_CI = CP_CH * CP_B;        // ids per chunk
-constexpr int CP_NL = (CP_CI + 63) / 64;   // id loads per lane and chunk
-constexpr int CP_NT = 64 * (CP_PW + 1);
 static_assert(CP_S * CP_M <= 63, "rows in flight beyond the vector load counter");
 static_assert(CP_CH > CP_S, "chunk 0 holds the ids the gathering waves start with");
-__global__ void __launch_bounds__(CP_NT)
+// PW gathering waves: 3 (three workgroups per CU, for the first Lloyd
+// iterations, when every cluster is summed again and the launch streams the
+// whole row copy), or 7 (one workgroup per CU with 420 rows in flight, for the
+// late iterations, when a few long chains on a few CUs set the time)
+template <int PW>
+struct CentroidShape {
+    static constexpr int B = PW * CP_M;            // members per batch
+    static constexpr int CI = CP_CH * B;           // ids per chunk
+    static constexpr int NL = (CI + 63) / 64;      // id loads per lane and chunk
+    static constexpr int NT = 64 * (PW + 1);
+};
+template <int PW>
+__global__ void __launch_bounds__(CentroidShape<PW>::NT)
 k_centroid_sum(int dim, int K, int R, const double* __restrict__ Y,
                const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
                const int* __restrict__ active, const int* __restrict__ dirty,
                double* __restrict__ C) {
+    constexpr int CP_B = CentroidShape<PW>::B;
+    constexpr int CP_CI = CentroidShape<PW>::CI;
+    constexpr int CP_NL = CentroidShape<PW>::NL;
     __shared__ double ring[2][CP_B][64];
     __shared__ int idbuf[2][CP_CI];
     const int wps = (dim + 63) / 64;
@@ -1180,12 +1190,15 @@ k_centroid_sum(int dim, int K, int R, const double* __restrict__ Y,
                     const int64_t b = u - 1;
                     const double* rb = &ring[b & 1][0][lane];
                     if (b + 1 < nb) {
-                        // a full batch: every read issued ahead of the additions
-                        double x[CP_B];
+                        // a full batch, CP_M reads issued ahead of their additions
 #pragma unroll
-                        for (int q = 0; q < CP_B; ++q) x[q] = rb[q * 64];
+                        for (int g = 0; g < PW; ++g) {
+                            double x[CP_M];
 #pragma unroll
-                        for (int q = 0; q < CP_B; ++q) s += x[q];
+                            for (int q = 0; q < CP_M; ++q) x[q] = rb[(g * CP_M + q) * 64];
+#pragma unroll
+                            for (int q = 0; q < CP_M; ++q) s += x[q];
+                        }
                     } else {
                         const int m = (int)(cnt - b * CP_B);
 #pragma unroll
@@ -1623,9 +1636,21 @@ sc_status kmeans_run(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx
                                nullptr, nullptr, w.lhist, lt, w.vals);
             SC_CHECK_LAUNCH(ctx);
         }
-        hipLaunchKernelGGL(k_centroid_sum, dim3((unsigned)((int64_t)R * K * ceil_div(dim, 64))),
-                           dim3(CP_NT), 0, st, dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty,
-                           w.C);
+        {
+            // few clusters changed in the last assignment: the wide variant
+            // (one workgroup per CU, more rows in flight per chain)
+            const unsigned grid = (unsigned)((int64_t)R * K * ceil_div(dim, 64));
+            int64_t moved = 0;
+            for (int r = 0; r < R; ++r)
+                if (act_h[r]) moved += ch[r];
+            const bool wide = it > 1 && 2 * moved * ceil_div(dim, 64) <= ctx->num_cu;
+            if (wide)
+                hipLaunchKernelGGL(k_centroid_sum<7>, dim3(grid), dim3(CentroidShape<7>::NT), 0, st,
+                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+            else
+                hipLaunchKernelGGL(k_centroid_sum<3>, dim3(grid), dim3(CentroidShape<3>::NT), 0, st,
+                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+        }
         SC_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(k_delta, dim3((unsigned)ceil_div((int64_t)R * K, TH / 64)), dim3(TH), 0, st, K,
                            R, dim, w.C, w.Cold, w.active, w.dirty, w.delta);
