@@ -232,6 +232,10 @@ sc_status sc_lobpcg_workspace(sc_ctx* ctx, int64_t n, int64_t nnz, const sc_lobp
  *     Cholesky fails); Gram matrices S'LS and S'S (3k x 3k); Rayleigh-Ritz in
  *     FP64 (Cholesky of S'S; on failure P is dropped and the step redone);
  *     P <- [W P] C_WP, X <- X C_X + P (and the same for LX, LP).
+ * Soft locking (Sec. IV, opts.lock_tol): a column whose relres is at or below
+ * lock_tol leaves W; the active W columns are moved to the front of the W
+ * block, and the W products, the Gram matrices and the block update skip the
+ * rest of it (the Rayleigh-Ritz step sees those columns as inactive).
  * Every CholQR equilibrates the columns before the Cholesky.
  * Reduced precision (FP32, FP32_BF16GRAM): a W column whose CholQR pivot
  * fails, or whose pivot in the Cholesky of S'S fails once P is out, is left

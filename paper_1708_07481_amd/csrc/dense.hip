@@ -252,16 +252,30 @@ struct GramStage {
 // workgroup run this loop with the same row range, so they meet at the same
 // barriers whatever their pieces.  B1s or B2s may alias As (the same columns of
 // the same matrix): the caller then skips staging them.
-template <class MF, bool TWO, int NP, int NQ, bool TRI>
+template <class MF, bool TWO, int NP, int NQ, bool TRI, bool PART>
 __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca, int cb,
                                            const float* __restrict__ A, int64_t lda,
                                            const float* __restrict__ B1, int64_t ldb1,
                                            const float* __restrict__ B2, int64_t ldb2,
                                            float* As, float* B1s, float* B2s, bool ld1, bool ld2,
-                                           int pa0, int qb0, double* p1, double* p2) {
+                                           int pa0, int qb0, double* p1, double* p2, int gap_lo,
+                                           int gap_hi) {
     constexpr int BT = 32 * MF::WT;
     constexpr int LS = BT + 16;
     const int lane = threadIdx.x & 63, lc = lane & 15;
+    // PART: MFMA sub-tiles wholly past column c, or wholly inside the unused
+    // columns [gap_lo, gap_hi), are skipped (their results are never read)
+    bool pok[NP], qok[NQ];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int s0 = ca + 16 * (pa0 + p);
+        pok[p] = !PART || (s0 < c && !(s0 >= gap_lo && s0 + 16 <= gap_hi));
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int s0 = cb + 16 * (qb0 + q);
+        qok[q] = !PART || (s0 < c && !(s0 >= gap_lo && s0 + 16 <= gap_hi));
+    }
     using acc_t = typename MF::acc_t;
     acc_t acc1[NP][NQ], acc2[NP][NQ];
 #pragma unroll
@@ -303,6 +317,7 @@ __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (TRI && q < p) continue;
+                    if (PART && !(pok[p] && qok[q])) continue;
                     acc1[p][q] = MF::mma(fa[p], fb1[q], acc1[p][q]);
                     if (TWO) acc2[p][q] = MF::mma(fa[p], fb2[q], acc2[p][q]);
                 }
@@ -326,13 +341,14 @@ __device__ __forceinline__ void gram_piece(int64_t r0, int64_t r1, int c, int ca
 }
 
 // one (tile pair, row chunk) item of the FP32 Gram kernel
-template <class MF, bool TWO>
+template <class MF, bool TWO, bool PART>
 __device__ __forceinline__ void gram_tile(int64_t n, int c, int64_t chunk_rows,
                                           const float* __restrict__ A, int64_t lda,
                                           const float* __restrict__ B1, int64_t ldb1,
                                           const float* __restrict__ B2, int64_t ldb2,
                                           double* __restrict__ partial, int ti, int tj, int chunk,
-                                          float* As, float* B1s, float* B2s) {
+                                          float* As, float* B1s, float* B2s, int gap_lo,
+                                          int gap_hi) {
     constexpr int WT = MF::WT;
     constexpr int BT = 32 * WT;
     const int64_t r0 = (int64_t)chunk * chunk_rows;
@@ -343,9 +359,9 @@ __device__ __forceinline__ void gram_tile(int64_t n, int c, int64_t chunk_rows,
     double* p1 = partial + (int64_t)chunk * (TWO ? 2 : 1) * cc2;
     double* p2 = p1 + cc2;
     if (ti != tj) {
-        gram_piece<MF, TWO, WT, WT, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, B1s,
+        gram_piece<MF, TWO, WT, WT, false, PART>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, B1s,
                                            B2s, true, true, (wave >> 1) * WT, (wave & 1) * WT, p1,
-                                           p2);
+                                           p2, gap_lo, gap_hi);
         return;
     }
     const bool same1 = B1 == A && ldb1 == lda;
@@ -355,20 +371,23 @@ __device__ __forceinline__ void gram_tile(int64_t n, int c, int64_t chunk_rows,
     constexpr int QA = (WT + 1) / 2, QB = WT / 2;
     switch (wave) {
     case 0:
-        gram_piece<MF, TWO, WT, WT, true>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
-                                          b2s, !same1, !same2, 0, 0, p1, p2);
+        gram_piece<MF, TWO, WT, WT, true, PART>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                          b2s, !same1, !same2, 0, 0, p1, p2, gap_lo, gap_hi);
         break;
     case 1:
-        gram_piece<MF, TWO, WT, WT, true>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
-                                          b2s, !same1, !same2, WT, WT, p1, p2);
+        gram_piece<MF, TWO, WT, WT, true, PART>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                          b2s, !same1, !same2, WT, WT, p1, p2, gap_lo,
+                                                gap_hi);
         break;
     case 2:
-        gram_piece<MF, TWO, WT, QA, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
-                                           b2s, !same1, !same2, 0, WT, p1, p2);
+        gram_piece<MF, TWO, WT, QA, false, PART>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                           b2s, !same1, !same2, 0, WT, p1, p2, gap_lo,
+                                                 gap_hi);
         break;
     default:
-        gram_piece<MF, TWO, WT, QB, false>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
-                                           b2s, !same1, !same2, 0, WT + QA, p1, p2);
+        gram_piece<MF, TWO, WT, QB, false, PART>(r0, r1, c, ca, cb, A, lda, B1, ldb1, B2, ldb2, As, b1s,
+                                           b2s, !same1, !same2, 0, WT + QA, p1, p2,
+                                                 gap_lo, gap_hi);
         break;
     }
 }
@@ -408,12 +427,12 @@ __device__ __forceinline__ void gram_item(int item, int tiles, int chunks, int& 
     }
 }
 
-template <class MF, bool TWO, bool PERSIST>
+template <class MF, bool TWO, bool PERSIST, bool PART>
 __global__ void __launch_bounds__(256)
 k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, int64_t lda,
            const float* __restrict__ B1, int64_t ldb1, const float* __restrict__ B2, int64_t ldb2,
            double* __restrict__ partial, int tiles, int chunks, int* __restrict__ queue,
-           const int* __restrict__ pred) {
+           int gap_lo, int gap_hi, const int* __restrict__ pred) {
     if (pred && *pred == 0) return;
     constexpr int WT = MF::WT;
     constexpr int BT = 32 * WT;
@@ -426,8 +445,8 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
     if (!PERSIST) {                             // one item per workgroup
         int ti, tj, chunk;
         gram_item((int)blockIdx.x, tiles, chunks, ti, tj, chunk);
-        gram_tile<MF, TWO>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj, chunk,
-                           As, B1s, B2s);
+        gram_tile<MF, TWO, PART>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj, chunk,
+                                 As, B1s, B2s, gap_lo, gap_hi);
         return;
     }
     __shared__ int item_s;
@@ -439,8 +458,21 @@ k_gram_lds(int64_t n, int c, int64_t chunk_rows, const float* __restrict__ A, in
         if (item >= items) break;
         int ti, tj, chunk;
         gram_item(item, tiles, chunks, ti, tj, chunk);
-        gram_tile<MF, TWO>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj, chunk,
-                           As, B1s, B2s);
+        // a tile wholly inside the unused columns: nothing of the pair is read
+        if (PART && ((ti * BT >= gap_lo && (ti + 1) * BT <= gap_hi) ||
+                     (tj * BT >= gap_lo && (tj + 1) * BT <= gap_hi)))
+            continue;
+        // only the items that reach past column c or into the unused columns
+        // take the sub-tile tests; the others run the unconditional code
+        const bool part_item =
+            PART && ((tj + 1) * BT > c || (ti * BT < gap_hi && (ti + 1) * BT > gap_lo) ||
+                     (tj * BT < gap_hi && (tj + 1) * BT > gap_lo));
+        if (part_item)
+            gram_tile<MF, TWO, true>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj,
+                                     chunk, As, B1s, B2s, gap_lo, gap_hi);
+        else
+            gram_tile<MF, TWO, false>(n, c, chunk_rows, A, lda, B1, ldb1, B2, ldb2, partial, ti, tj,
+                                      chunk, As, B1s, B2s, gap_lo, gap_hi);
     }
     if (threadIdx.x == 0 && atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {   // PERSIST only
         atomicExch(&queue[0], 0);               // last one out: ready for the next launch
@@ -833,8 +865,8 @@ __device__ inline void rowgemm_section(const T* __restrict__ V, int64_t ld, int6
 
 template <class T, int RPT, int NC>
 __global__ void __launch_bounds__(256)
-k_rowgemm(int64_t n, T* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
-          const T* __restrict__ M, int ldm, int nout, int o1, int o2) {
+k_rowgemm(int64_t n, T* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1, int b2,
+          int b3, const T* __restrict__ M, int ldm, int nout, int o1, int o2) {
     constexpr int BM = 16 * RPT;
     __shared__ T Vs[RG_BK][BM + 1];
     __shared__ T Ms[RG_BK][16 * NC];
@@ -849,6 +881,7 @@ k_rowgemm(int64_t n, T* __restrict__ V, int64_t ld, int a0, int a1, int b0, int 
         }
     rowgemm_section<T, RPT, NC>(V, ld, r0, n, a0, a1, M, ldm, nout, Vs, Ms, acc1);
     rowgemm_section<T, RPT, NC>(V, ld, r0, n, b0, b1, M, ldm, nout, Vs, Ms, acc2);
+    rowgemm_section<T, RPT, NC>(V, ld, r0, n, b2, b3, M, ldm, nout, Vs, Ms, acc2);
     __syncthreads();
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
@@ -873,8 +906,8 @@ constexpr int RES_ROWS = 256;
 
 template <class T>
 __global__ void __launch_bounds__(256)
-k_residual(int64_t n, int kp, int k, T* __restrict__ S, const T* __restrict__ LS, int64_t ld,
-           const double* __restrict__ theta, double* __restrict__ partial) {
+k_residual(int64_t n, int kp, int k, int woff, T* __restrict__ S, const T* __restrict__ LS,
+           int64_t ld, const double* __restrict__ theta, double* __restrict__ partial) {
     const int64_t r0 = (int64_t)blockIdx.x * RES_ROWS;
     const int64_t r1 = min<int64_t>(n, r0 + RES_ROWS);
     for (int j = threadIdx.x; j < kp; j += 256) {
@@ -884,12 +917,12 @@ k_residual(int64_t n, int kp, int k, T* __restrict__ S, const T* __restrict__ LS
             for (int64_t i = r0; i < r1; ++i) {
                 const T x = S[i * ld + j];
                 const T r = fma(-th, x, LS[i * ld + j]);
-                S[i * ld + kp + j] = r;
+                S[i * ld + woff + j] = r;
                 rr = fma((double)r, (double)r, rr);
                 xx = fma((double)x, (double)x, xx);
             }
         } else {
-            for (int64_t i = r0; i < r1; ++i) S[i * ld + kp + j] = T(0);
+            for (int64_t i = r0; i < r1; ++i) S[i * ld + woff + j] = T(0);
         }
         partial[((int64_t)blockIdx.x * 2 + 0) * kp + j] = rr;
         partial[((int64_t)blockIdx.x * 2 + 1) * kp + j] = xx;
@@ -919,13 +952,16 @@ k_residual_finalize(int nblocks, int kp, int k, int k_conv, const double* __rest
                     double lock_tol,
                     double* __restrict__ relres, double* __restrict__ hist_row, int* __restrict__ wmask,
                     int* status, double* out_max, int* out_all_locked,
-                    const double* __restrict__ theta, int* __restrict__ out_restart) {
+                    const double* __restrict__ theta, int* __restrict__ out_restart,
+                    int* __restrict__ out_wcount) {
     __shared__ double mx[256];
     __shared__ int locked_all[256];
     __shared__ int bad[256];
+    __shared__ int nact[256];
     double my_max = 0.0;
     int my_all = 1;
     int my_bad = 0;
+    int my_act = 0;
     for (int j = threadIdx.x; j < kp; j += 256) {
         double rr = 0.0, xx = 0.0;
         for (int b = 0; b < nblocks; ++b) {
@@ -947,6 +983,7 @@ k_residual_finalize(int nblocks, int kp, int k, int k_conv, const double* __rest
                 if (!(th >= -slack && th <= op_norm + slack) || rel > 1.0) my_bad = 1;
             }
             my_all &= !active;
+            my_act += active;
             if (j < k_conv) my_max = fmax(my_max, rel);
         } else {
             relres[j] = 0.0;
@@ -956,18 +993,21 @@ k_residual_finalize(int nblocks, int kp, int k, int k_conv, const double* __rest
     mx[threadIdx.x] = my_max;
     locked_all[threadIdx.x] = my_all;
     bad[threadIdx.x] = my_bad;
+    nact[threadIdx.x] = my_act;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = 0.0;
-        int a = 1, b = 0;
+        int a = 1, b = 0, w = 0;
         for (int t = 0; t < 256; ++t) {
             m = fmax(m, mx[t]);
             a &= locked_all[t];
             b |= bad[t];
+            w += nact[t];
         }
         *out_max = m;
         *out_all_locked = a;
         if (out_restart) *out_restart = b;
+        if (out_wcount) *out_wcount = w;
     }
 }
 
@@ -1011,7 +1051,7 @@ static unsigned gram_grid(sc_ctx* ctx, unsigned items) {
     if (per_cu < 0) {
         int b = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &b, reinterpret_cast<const void*>(k_gram_lds<MF, TWO, true>), 256, 0) !=
+                &b, reinterpret_cast<const void*>(k_gram_lds<MF, TWO, true, false>), 256, 0) !=
                 hipSuccess ||
             b < 1)
             b = 1;
@@ -1036,14 +1076,32 @@ static void gram_go(sc_ctx* ctx, const GramPlan& p, const typename MF::in_t* A, 
                 g2 = gram_grid<MF, true>(ctx, items);
                 g1 = gram_grid<MF, false>(ctx, items);
             }
-            if (B2)
-                hipLaunchKernelGGL((k_gram_lds<MF, true, PS>), dim3(g2), dim3(256), 0,
-                                   ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B2, ldb2,
-                                   partial, p.tiles, p.chunks, p.queue, pred);
-            else
-                hipLaunchKernelGGL((k_gram_lds<MF, false, PS>), dim3(g1), dim3(256), 0,
-                                   ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B1, ldb1,
-                                   partial, p.tiles, p.chunks, p.queue, pred);
+            // (the BF16 instantiation with skipping would spill: it computes the
+            // zero sub-tiles instead)
+            const bool part = PS && (p.c % p.bt != 0 || p.gap_hi > p.gap_lo);
+            if (B2) {
+                if (part)
+                    hipLaunchKernelGGL((k_gram_lds<MF, true, PS, PS>), dim3(g2), dim3(256), 0,
+                                       ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B2,
+                                       ldb2, partial, p.tiles, p.chunks, p.queue, p.gap_lo,
+                                       p.gap_hi, pred);
+                else
+                    hipLaunchKernelGGL((k_gram_lds<MF, true, PS, false>), dim3(g2), dim3(256), 0,
+                                       ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B2,
+                                       ldb2, partial, p.tiles, p.chunks, p.queue, p.gap_lo,
+                                       p.gap_hi, pred);
+            } else {
+                if (part)
+                    hipLaunchKernelGGL((k_gram_lds<MF, false, PS, PS>), dim3(g1), dim3(256), 0,
+                                       ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B1,
+                                       ldb1, partial, p.tiles, p.chunks, p.queue, p.gap_lo,
+                                       p.gap_hi, pred);
+                else
+                    hipLaunchKernelGGL((k_gram_lds<MF, false, PS, false>), dim3(g1), dim3(256), 0,
+                                       ctx->stream, p.n, p.c, p.chunk_rows, A, lda, B1, ldb1, B1,
+                                       ldb1, partial, p.tiles, p.chunks, p.queue, p.gap_lo,
+                                       p.gap_hi, pred);
+            }
             return;
         }
     }
@@ -1116,7 +1174,7 @@ constexpr int RG_KC = 32;
 template <int NC, bool TRI>
 __global__ void __launch_bounds__(256)
 k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
-               const float* __restrict__ M, int ldm, int nout, int o1, int o2) {
+               int b2, int b3, const float* __restrict__ M, int ldm, int nout, int o1, int o2) {
     constexpr int VS = RG_KC + 2;
     constexpr int MS = 16 * NC + ((NC % 2 == 0) ? 16 : 0);
     __shared__ __attribute__((aligned(16))) float Vs[RG_BM * VS];
@@ -1256,8 +1314,9 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
         store(o1);
         return;
     }
-    if (b1 > b0) {
-        section(b0, b1);
+    if (b1 > b0 || b3 > b2) {
+        if (b1 > b0) section(b0, b1);
+        if (b3 > b2) section(b2, b3);
         if (o2 >= 0) store(o2);
     }
     section(a0, a1);
@@ -1266,65 +1325,69 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
 
 template <int NC>
 static void rowgemm_mfma_go(sc_ctx* ctx, int64_t n, float* V, int64_t ld, int a0, int a1, int b0,
-                            int b1, const float* M, int ldm, int nout, int o1, int o2, bool tri) {
+                            int b1, int b2, int b3, const float* M, int ldm, int nout, int o1,
+                            int o2, bool tri) {
     if (tri)
         hipLaunchKernelGGL((k_rowgemm_mfma<NC, true>), dim3((unsigned)ceil_div(n, RG_BM)),
-                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1,
-                           o2);
+                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm,
+                           nout, o1, o2);
     else
         hipLaunchKernelGGL((k_rowgemm_mfma<NC, false>), dim3((unsigned)ceil_div(n, RG_BM)),
-                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1,
-                           o2);
+                           dim3(256), 0, ctx->stream, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm,
+                           nout, o1, o2);
 }
 
 template <class T, int NC>
 static void rowgemm_go(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
-                       const T* M, int ldm, int nout, int o1, int o2) {
+                       int b2, int b3, const T* M, int ldm, int nout, int o1, int o2) {
     constexpr int RPT = sizeof(T) == 8 ? 2 : 4;
     constexpr int BM = 16 * RPT;
     hipLaunchKernelGGL((k_rowgemm<T, RPT, NC>), dim3((unsigned)ceil_div(n, BM)), dim3(256), 0,
-                       ctx->stream, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+                       ctx->stream, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2);
 }
 
-// tri: M is upper triangular with a0 = 0 and an empty second section (the
+// Section b is [b0, b1) followed by [b2, b3) (either may be empty).
+// tri: M is upper triangular with a0 = 0 and an empty section b (the
 // matrix-core path then skips the all-zero products)
 template <class T>
 static sc_status rowgemm(sc_ctx* ctx, int64_t n, T* V, int64_t ld, int a0, int a1, int b0, int b1,
-                         const T* M, int ldm, int nout, int o1, int o2, bool tri = false) {
-    if (tri && (a0 != 0 || b1 > b0))
+                         int b2, int b3, const T* M, int ldm, int nout, int o1, int o2,
+                         bool tri = false) {
+    if (tri && (a0 != 0 || b1 > b0 || b3 > b2))
         return sc_fail(ctx, SC_E_INVAL, "rowgemm: triangular factor with sections [%d,%d) [%d,%d)",
                        a0, a1, b0, b1);
     const int nc = (nout + 15) / 16;
     if constexpr (sizeof(T) == 4) {
         // matrix-core path: 16-byte aligned rows and section starts
-        if (((uintptr_t)V % 16) == 0 && ld % 4 == 0 && a0 % 4 == 0 && b0 % 4 == 0 && nout <= 256) {
+        if (((uintptr_t)V % 16) == 0 && ld % 4 == 0 && a0 % 4 == 0 && b0 % 4 == 0 &&
+            b2 % 4 == 0 && nout <= 256) {
             switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
-                case 1: rowgemm_mfma_go<1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 2: rowgemm_mfma_go<2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 3: rowgemm_mfma_go<3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 4: rowgemm_mfma_go<4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 6: rowgemm_mfma_go<6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 8: rowgemm_mfma_go<8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 10: rowgemm_mfma_go<10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                case 12: rowgemm_mfma_go<12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
-                default: rowgemm_mfma_go<16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2, tri); break;
+                case 1: rowgemm_mfma_go<1>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 2: rowgemm_mfma_go<2>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 3: rowgemm_mfma_go<3>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 4: rowgemm_mfma_go<4>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 6: rowgemm_mfma_go<6>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 8: rowgemm_mfma_go<8>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 10: rowgemm_mfma_go<10>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                case 12: rowgemm_mfma_go<12>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
+                default: rowgemm_mfma_go<16>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2, tri); break;
             }
             SC_CHECK_LAUNCH(ctx);
             return SC_OK;
         }
     }
     switch (nc <= 4 ? nc : nc <= 6 ? 6 : nc <= 8 ? 8 : nc <= 10 ? 10 : nc <= 12 ? 12 : 16) {
-        case 1: rowgemm_go<T, 1>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 2: rowgemm_go<T, 2>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 3: rowgemm_go<T, 3>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 4: rowgemm_go<T, 4>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 6: rowgemm_go<T, 6>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 8: rowgemm_go<T, 8>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 10: rowgemm_go<T, 10>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
-        case 12: rowgemm_go<T, 12>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2); break;
+        case 1: rowgemm_go<T, 1>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 2: rowgemm_go<T, 2>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 3: rowgemm_go<T, 3>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 4: rowgemm_go<T, 4>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 6: rowgemm_go<T, 6>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 8: rowgemm_go<T, 8>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 10: rowgemm_go<T, 10>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
+        case 12: rowgemm_go<T, 12>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2); break;
         default:
             if (nout > 256) return sc_fail(ctx, SC_E_UNSUPPORTED, "rowgemm: %d columns > 256", nout);
-            rowgemm_go<T, 16>(ctx, n, V, ld, a0, a1, b0, b1, M, ldm, nout, o1, o2);
+            rowgemm_go<T, 16>(ctx, n, V, ld, a0, a1, b0, b1, b2, b3, M, ldm, nout, o1, o2);
             break;
     }
     SC_CHECK_LAUNCH(ctx);
@@ -1335,8 +1398,8 @@ template <class T>
 sc_status launch_apply_right(sc_ctx* ctx, int64_t n, int c, T* V, int64_t ldv, T* V2, int64_t ldv2,
                              const double* T64, const float* T32) {
     const T* M = Prec<T>::pick(T64, T32);
-    SC_TRY(rowgemm<T>(ctx, n, V, ldv, 0, c, 0, 0, M, c, c, 0, -1, true));
-    if (V2) SC_TRY(rowgemm<T>(ctx, n, V2, ldv2, 0, c, 0, 0, M, c, c, 0, -1, true));
+    SC_TRY(rowgemm<T>(ctx, n, V, ldv, 0, c, 0, 0, 0, 0, M, c, c, 0, -1, true));
+    if (V2) SC_TRY(rowgemm<T>(ctx, n, V2, ldv2, 0, c, 0, 0, 0, 0, M, c, c, 0, -1, true));
     return SC_OK;
 }
 template sc_status launch_apply_right<double>(sc_ctx*, int64_t, int, double*, int64_t, double*,
@@ -1345,35 +1408,38 @@ template sc_status launch_apply_right<float>(sc_ctx*, int64_t, int, float*, int6
                                              int64_t, const double*, const float*);
 
 template <class T>
-sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, T* S, int64_t ld, const double* C64,
-                              const float* C32) {
+sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, int kw, T* S, int64_t ld,
+                              const double* C64, const float* C32) {
     const T* M = Prec<T>::pick(C64, C32);
-    return rowgemm<T>(ctx, n, S, ld, 0, kp, kp, 3 * kp, M, kp, kp, 0, 2 * kp);
+    // [W P] C_WP: the W columns in use, then P (the unused W columns' rows of
+    // C are zero)
+    return rowgemm<T>(ctx, n, S, ld, 0, kp, kp, kp + kw, 2 * kp, 3 * kp, M, kp, kp, 0, 2 * kp);
 }
-template sc_status launch_block_update<double>(sc_ctx*, int64_t, int, double*, int64_t,
+template sc_status launch_block_update<double>(sc_ctx*, int64_t, int, int, double*, int64_t,
                                                const double*, const float*);
-template sc_status launch_block_update<float>(sc_ctx*, int64_t, int, float*, int64_t, const double*,
+template sc_status launch_block_update<float>(sc_ctx*, int64_t, int, int, float*, int64_t, const double*,
                                               const float*);
 
 template <class T>
-sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* LS, int64_t ld,
-                          const double* theta, double* partial, int* nblocks_out) {
+sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, int woff, T* S, const T* LS,
+                          int64_t ld, const double* theta, double* partial, int* nblocks_out) {
     const int nb = (int)ceil_div(n, RES_ROWS);
-    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(256), 0, ctx->stream, n, kp, k, S, LS, ld,
-                       theta, partial);
+    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(256), 0, ctx->stream, n, kp, k, woff, S, LS,
+                       ld, theta, partial);
     SC_CHECK_LAUNCH(ctx);
     *nblocks_out = nb;
     return SC_OK;
 }
-template sc_status launch_residual<double>(sc_ctx*, int64_t, int, int, double*, const double*,
+template sc_status launch_residual<double>(sc_ctx*, int64_t, int, int, int, double*, const double*,
                                            int64_t, const double*, double*, int*);
-template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, float*, const float*, int64_t,
-                                          const double*, double*, int*);
+template sc_status launch_residual<float>(sc_ctx*, int64_t, int, int, int, float*, const float*,
+                                          int64_t, const double*, double*, int*);
 
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, int k_conv,
-                                   double* partial, double op_norm, double lock_tol, double* relres, double* hist_row, int* wmask,
-                                   int* status, double* out_max, int* out_all_locked,
-                                   const double* theta, int* out_restart) {
+                                   double* partial, double op_norm, double lock_tol, double* relres,
+                                   double* hist_row, int* wmask, int* status, double* out_max,
+                                   int* out_all_locked, const double* theta, int* out_restart,
+                                   int* out_wcount) {
     if (nblocks > 1) {
         hipLaunchKernelGGL(k_residual_colsum, dim3(kp, 2), dim3(256), 0, ctx->stream, nblocks, kp,
                            partial);
@@ -1381,7 +1447,7 @@ sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, int 
     }
     hipLaunchKernelGGL(k_residual_finalize, dim3(1), dim3(256), 0, ctx->stream, nblocks, kp, k,
                        k_conv, partial, op_norm, lock_tol, relres, hist_row, wmask, status, out_max,
-                       out_all_locked, theta, out_restart);
+                       out_all_locked, theta, out_restart, out_wcount);
     SC_CHECK_LAUNCH(ctx);
     return SC_OK;
 }

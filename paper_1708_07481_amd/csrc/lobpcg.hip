@@ -6,7 +6,9 @@
 //
 // Workspace layout: S = [X W P] and LS = [LX LW LP], each n x 3kp row-major
 // (kp = k rounded up to a multiple of 4; pad columns stay zero), the Gram
-// matrices, the small factors, and the per-iteration residual history.
+// matrices, the small factors, and the per-iteration residual history.  With
+// soft locking the active W columns are moved to the front of the W block;
+// the rest of the block is then skipped by the products that span the basis.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,6 +27,46 @@ __global__ void k_fill_bytes(uint32_t* p, int64_t words) {
 // mask[0..c) = (j < ones) for `c` columns
 __global__ void k_set_mask(int* mask, int c, int ones) {
     for (int j = threadIdx.x; j < c; j += blockDim.x) mask[j] = j < ones ? 1 : 0;
+}
+
+// Soft locking (Sec. IV): the active W columns (mask[j], j < k) listed in
+// ascending order, and the mask rewritten for the compacted block (its first
+// `count` columns active).  One workgroup.
+__global__ void k_wlist(int k, int kp, int* __restrict__ mask, int* __restrict__ list) {
+    __shared__ int flags[256];
+    for (int j = threadIdx.x; j < kp; j += blockDim.x) flags[j] = j < k ? mask[j] : 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int j = 0; j < kp; ++j)
+            if (flags[j]) list[m++] = j;
+        for (int j = 0; j < kp; ++j) flags[j] = j < m;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kp; j += blockDim.x) mask[j] = flags[j];
+}
+
+// W[i][j] <- W[i][list[j]] for j < count, in place: one wave per row reads all
+// of its row's active entries, then writes them (list[j] >= j).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_compact_w(int64_t n, int count, T* __restrict__ W, int64_t ld, const int* __restrict__ list) {
+    constexpr int PER = 4;                           // up to 256 columns per row
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    T* row = W + i * ld;
+    T v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int j = lane + 64 * t;
+        v[t] = j < count ? row[list[j]] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int j = lane + 64 * t;
+        if (j < count) row[j] = v[t];
+    }
 }
 
 template <class Tin, class T>
@@ -97,6 +139,8 @@ struct sc_lobpcg_state {
     // [6] inconsistent-iterate flag of the last residual
     int *act, *status, *pdrops, *all_locked, *wdrops, *gram_fallbacks, *gflag, *restart_flag;
     int* gram_queue;                // work counters of the persistent Gram launches
+    int* wlist;                     // active W columns, compacted to the front of W
+    int kw = 0;                     // W columns active in the next iteration
     int32_t* row_order;             // rows longest first, for the SpMM's row groups
     void* order_scr;                // scratch of the sort that makes it
     GramPlan plan3{}, plan3x{}, plank{};
@@ -158,6 +202,7 @@ static size_t carve(Carver& c, int64_t n, int k, int maxit, sc_precision prec, s
     s.gflag = s.status + 5;
     s.restart_flag = s.status + 6;
     s.gram_queue = c.take<int>(2);
+    s.wlist = c.take<int>(kp);
     s.plan3.queue = s.plan3x.queue = s.plank.queue = s.gram_queue;
     s.row_order = c.take<int32_t>((size_t)n);
     s.order_scr = c.take<char>(row_order_scratch_bytes(n));
@@ -205,17 +250,28 @@ struct Solver {
     static const T* val(sc_lobpcg_state* s) { return static_cast<const T*>(s->val); }
     static const T* diag(sc_lobpcg_state* s) { return static_cast<const T*>(s->diag); }
 
-    // W/X/P block CholQR with mask `m` (kp columns at column offset `off`)
+    // Gram plan for a basis (or block) narrower than the one the state was
+    // sized for: same persistent work counter, partials within the buffer
+    static GramPlan narrow_plan(const sc_lobpcg_state* s, const GramPlan& full, int c, int bytes) {
+        if (c == full.c) return full;
+        GramPlan p = gram_plan(s->n, c, bytes);
+        p.queue = full.queue;
+        return p;
+    }
+
+    // W/X/P block CholQR with mask act[off..off + c) on the c columns at
+    // column offset `off` (c = kp, or the active W columns after compaction)
     static sc_status cholqr(sc_ctx* ctx, sc_lobpcg_state* s, int off, int with_L, int mode,
-                            int* counter) {
+                            int* counter, int c = 0) {
         const int64_t ld = s->K3;
+        if (c <= 0) c = s->kp;
         T* V = S(s) + off;
         ProfScope ps(ctx, SC_KIND_CHOLQR);
-        SC_TRY(launch_gram<T>(ctx, s->plank, V, ld, V, ld, nullptr, 0, s->Gwpart, s->Gw, nullptr,
-                              GRAM_NATIVE));
-        SC_TRY(launch_cholqr_factor(ctx, s->kp, s->Gw, s->act + off, s->chol_tol, s->T64, s->T32,
+        SC_TRY(launch_gram<T>(ctx, narrow_plan(s, s->plank, c, (int)sizeof(T)), V, ld, V, ld,
+                              nullptr, 0, s->Gwpart, s->Gw, nullptr, GRAM_NATIVE));
+        SC_TRY(launch_cholqr_factor(ctx, c, s->Gw, s->act + off, s->chol_tol, s->T64, s->T32,
                                     s->cq_scr, mode, s->status, counter));
-        SC_TRY(launch_apply_right<T>(ctx, s->n, s->kp, V, ld, with_L ? LS(s) + off : nullptr, ld,
+        SC_TRY(launch_apply_right<T>(ctx, s->n, c, V, ld, with_L ? LS(s) + off : nullptr, ld,
                                      s->T64, s->T32));
         return SC_OK;
     }
@@ -229,46 +285,53 @@ struct Solver {
     // widened to FP64 (exact products, FP64 accumulation) and the ordinary
     // set-up (P-drop rule, dependent W columns left out) runs on those.  The
     // recomputation is predicated on a device flag: no host round trip.
-    static sc_status rr_and_update(sc_ctx* ctx, sc_lobpcg_state* s) {
+    // kw: W columns in use (kp, or the active ones after compaction; the
+    // columns [kp + kw, 2kp) are then left out of the Gram products and the
+    // block update, and are inactive in the Rayleigh-Ritz step)
+    static sc_status rr_and_update(sc_ctx* ctx, sc_lobpcg_state* s, int kw) {
         const int64_t ld = s->K3;
+        const int c = s->K3;
+        GramPlan p3 = s->plan3, p3x = s->plan3x;
+        p3.gap_lo = p3x.gap_lo = s->kp + kw;
+        p3.gap_hi = p3x.gap_hi = 2 * s->kp;
         if (s->prec == SC_PREC_FP64) {
             {
                 ProfScope ps(ctx, SC_KIND_GRAM);
-                SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
-                                      s->GB, GRAM_NATIVE));
+                SC_TRY(launch_gram<T>(ctx, p3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA, s->GB,
+                                      GRAM_NATIVE));
             }
             ProfScope ps(ctx, SC_KIND_RR);
-            SC_TRY(launch_rayleigh_ritz(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
+            SC_TRY(launch_rayleigh_ritz(ctx, c, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
                                         s->C64, s->C32, s->theta, s->rr_scr, s->status, s->pdrops,
                                         nullptr));
         } else {
             const int bf16 = s->prec == SC_PREC_FP32_BF16GRAM;
             {
                 ProfScope ps(ctx, SC_KIND_GRAM);
-                SC_TRY(launch_gram<T>(ctx, s->plan3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
-                                      s->GB, bf16 ? GRAM_BF16 : GRAM_NATIVE));
+                SC_TRY(launch_gram<T>(ctx, p3, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA, s->GB,
+                                      bf16 ? GRAM_BF16 : GRAM_NATIVE));
             }
             {
                 ProfScope ps(ctx, SC_KIND_RR);
-                SC_TRY(launch_rr_setup(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act,
+                SC_TRY(launch_rr_setup(ctx, c, s->kp, s->k, s->GA, s->GB, s->act,
                                        bf16 ? BF16_PIVOT_TOL : FP32_PIVOT_TOL, s->rr_scr, s->status,
                                        s->pdrops, nullptr, s->gflag, s->gram_fallbacks, nullptr));
             }
             {
                 ProfScope ps(ctx, SC_KIND_GRAM_FP64ACC);
-                SC_TRY(launch_gram<T>(ctx, s->plan3x, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
+                SC_TRY(launch_gram<T>(ctx, p3x, S(s), ld, LS(s), ld, S(s), ld, s->Gpart, s->GA,
                                       s->GB, GRAM_F32_EXACT, s->gflag));
             }
             ProfScope ps(ctx, SC_KIND_RR);
-            SC_TRY(launch_rr_setup(ctx, s->K3, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
+            SC_TRY(launch_rr_setup(ctx, c, s->kp, s->k, s->GA, s->GB, s->act, s->chol_tol,
                                    s->rr_scr, s->status, s->pdrops, s->gflag, nullptr, nullptr,
                                    s->wdrops));
-            SC_TRY(launch_rr_solve(ctx, s->K3, s->kp, s->k, s->C64, s->C32, s->theta, s->rr_scr,
+            SC_TRY(launch_rr_solve(ctx, c, s->kp, s->k, s->C64, s->C32, s->theta, s->rr_scr,
                                    s->status));
         }
         ProfScope ps(ctx, SC_KIND_UPDATE);
-        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, S(s), ld, s->C64, s->C32));
-        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, LS(s), ld, s->C64, s->C32));
+        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, kw, S(s), ld, s->C64, s->C32));
+        SC_TRY(launch_block_update<T>(ctx, s->n, s->kp, kw, LS(s), ld, s->C64, s->C32));
         return SC_OK;
     }
 
@@ -278,14 +341,15 @@ struct Solver {
         int nb = 0;
         {
             ProfScope ps(ctx, SC_KIND_RESIDUAL);
-            SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, S(s), LS(s), s->K3, s->theta,
-                                      s->res_part, &nb));
+            SC_TRY(launch_residual<T>(ctx, s->n, s->kp, s->k, s->kp, S(s), LS(s), s->K3,
+                                      s->theta, s->res_part, &nb));
             SC_TRY(launch_residual_finalize(ctx, nb, s->kp, s->k, s->k_conv, s->res_part, s->op_norm,
                                             s->lock_tol,
                                             s->relres, s->hist + (int64_t)s->t * s->kp,
                                             s->act + s->kp, s->status, s->out_max,
                                             s->all_locked, s->theta,
-                                            s->prec == SC_PREC_FP64 ? nullptr : s->restart_flag));
+                                            s->prec == SC_PREC_FP64 ? nullptr : s->restart_flag,
+                                            s->status + 7));
         }
         char* h = s->readback;
         SC_CHECK_HIP(ctx, hipMemcpyAsync(h, s->status, 8 * sizeof(int), hipMemcpyDeviceToHost,
@@ -322,6 +386,7 @@ struct Solver {
         // reduced precision: an inconsistent iterate (LX drifted from L X) is
         // never reported as converged; the next iteration restarts from X
         s->need_restart = s->prec != SC_PREC_FP64 && st[6] != 0;
+        s->kw = st[7];
         s->converged = !s->need_restart && ((mx <= s->tol) || st[2]);
         s->done = s->converged || s->t >= s->maxit;
         return SC_OK;
@@ -384,7 +449,7 @@ struct Solver {
         // Rayleigh-Ritz on span(X) alone
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
         SC_CHECK_LAUNCH(ctx);
-        SC_TRY(rr_and_update(ctx, s));
+        SC_TRY(rr_and_update(ctx, s, s->kp));
         s->t = 0;
         s->has_p = 0;
         SC_TRY(residual(ctx, s));
@@ -415,7 +480,7 @@ struct Solver {
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, s->K3, s->k);
         SC_CHECK_LAUNCH(ctx);
-        SC_TRY(rr_and_update(ctx, s));
+        SC_TRY(rr_and_update(ctx, s, s->kp));
         s->has_p = 0;
         s->t += 1;
         return residual_enqueue(ctx, s);
@@ -427,25 +492,40 @@ struct Solver {
         hipStream_t st = ctx->stream;
         const int64_t ld = s->K3;
         const int kp = s->kp;
-        // X stays fully active; the W mask was set by the residual step
+        // X stays fully active; the W mask was set by the residual step.
+        // Soft locking (Sec. IV): when columns have left W, the active ones
+        // move to the front of the W block, and the W products, the basis
+        // Gram matrices and the block update run without the rest.
+        const int woff = kp;
+        const int kw = std::max(0, std::min(s->kw, s->k));
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act, kp, s->k);
         SC_CHECK_LAUNCH(ctx);
-        // a rank-deficient residual block: an error in FP64 (the plain
-        // method), dependent columns left out in the reduced-precision modes
-        if (s->prec == SC_PREC_FP64)
-            SC_TRY(cholqr(ctx, s, kp, 0, CQ_REQUIRE_ALL, nullptr));
-        else
-            SC_TRY(cholqr(ctx, s, kp, 0, CQ_DROP_DEPENDENT, s->wdrops));
-        {
+        if (kw < s->k) {
+            hipLaunchKernelGGL(k_wlist, dim3(1), dim3(256), 0, st, s->k, kp, s->act + woff,
+                               s->wlist);
+            if (kw > 0)
+                hipLaunchKernelGGL((k_compact_w<T>), dim3((unsigned)ceil_div(s->n, 4)), dim3(256),
+                                   0, st, s->n, kw, S(s) + woff, ld, s->wlist);
+            SC_CHECK_LAUNCH(ctx);
+        }
+        const int wc = kw < s->k ? kw : kp;          // W columns in use
+        if (wc > 0) {
+            // a rank-deficient residual block: an error in FP64 (the plain
+            // method), dependent columns left out in the reduced-precision modes
+            if (s->prec == SC_PREC_FP64)
+                SC_TRY(cholqr(ctx, s, woff, 0, CQ_REQUIRE_ALL, nullptr, wc));
+            else
+                SC_TRY(cholqr(ctx, s, woff, 0, CQ_DROP_DEPENDENT, s->wdrops, wc));
             ProfScope ps(ctx, SC_KIND_SPMM);
-            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s), s->k, S(s) + kp, ld,
-                                  LS(s) + kp, ld, s->row_order));
+            SC_TRY(launch_spmm<T>(ctx, s->n, s->row_ptr, s->col, val(s), diag(s),
+                                  kw < s->k ? kw : s->k, S(s) + woff, ld, LS(s) + woff, ld,
+                                  s->row_order));
         }
         hipLaunchKernelGGL(k_set_mask, dim3(1), dim3(256), 0, st, s->act + 2 * kp, kp,
                            s->has_p ? s->k : 0);
         SC_CHECK_LAUNCH(ctx);
         if (s->has_p) SC_TRY(cholqr(ctx, s, 2 * kp, 1, CQ_DROP_ALL, s->pdrops));
-        SC_TRY(rr_and_update(ctx, s));
+        SC_TRY(rr_and_update(ctx, s, wc));
         s->has_p = 1;
         s->t += 1;
         return residual_enqueue(ctx, s);

@@ -179,6 +179,9 @@ struct GramPlan {
     // this counter, and the last workgroup out zeroes both again, so launches
     // on one stream can share them (nullptr: the unstaged FP32 kernel)
     int* queue = nullptr;
+    // columns [gap_lo, gap_hi) are not used (their results are never read):
+    // MFMA sub-tiles wholly inside skip their products
+    int gap_lo = 0, gap_hi = 0;
 };
 // Gram precision for FP32 data: native FP32 MFMA, BF16-rounded inputs, or
 // widened to FP64 (exact products, FP64 accumulation).  FP64 data always
@@ -210,24 +213,29 @@ sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, d
 template <class T>
 sc_status launch_apply_right(sc_ctx* ctx, int64_t n, int c, T* V, int64_t ldv, T* V2,
                              int64_t ldv2, const double* T64, const float* T32);
-// Block update on S (n x 3kp, row stride ld): P <- [W P] C_WP, X <- X C_X + P.
+// Block update on S = [X W P] (n x 3kp, row stride ld): P <- [W P] C_WP,
+// X <- X C_X + P.  kw: W columns in use (the first kw of the W block; the rest
+// of the block and their rows of C are skipped).
 template <class T>
-sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, T* S, int64_t ld, const double* C64,
-                              const float* C32);
-// Residual R = LX - X diag(theta) into W; per-block partial sums of R^2, X^2.
+sc_status launch_block_update(sc_ctx* ctx, int64_t n, int kp, int kw, T* S, int64_t ld,
+                              const double* C64, const float* C32);
+// Residual R = LX - X diag(theta) into columns [woff, woff + kp) of S;
+// per-block partial sums of R^2, X^2.
 template <class T>
-sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, T* S, const T* LS, int64_t ld,
-                          const double* theta, double* partial, int* nblocks_out);
+sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, int woff, T* S, const T* LS,
+                          int64_t ld, const double* theta, double* partial, int* nblocks_out);
 // Finalise: column totals of the block partials (in place), then relres,
 // history row, W mask, flags; out[0] = max relres, out_flags[0] = all columns
 // locked.  relres_j = ||r_j|| / (op_norm ||x_j||), op_norm >= ||L|| (2 for the
 // normalised Laplacian).  With out_restart non-null it is set to 1 when the
 // iterate is inconsistent (a Ritz value outside [0, op_norm] by more than
 // op_norm * 5e-4, or relres > 1, impossible when LX = L X), else 0.
+// out_wcount[0] = the number of W columns left active (relres > lock_tol).
 sc_status launch_residual_finalize(sc_ctx* ctx, int nblocks, int kp, int k, int k_conv,
                                    double* partial, double op_norm, double lock_tol, double* relres,
                                    double* hist_row, int* wmask, int* status, double* out_max,
-                                   int* out_all_locked, const double* theta, int* out_restart);
+                                   int* out_all_locked, const double* theta, int* out_restart,
+                                   int* out_wcount);
 
 // Rayleigh-Ritz (FP64) on the active columns: C (K3 x kp), theta (kp).
 // Split in two: the set-up (active set, Cholesky of G_B with the P-drop
