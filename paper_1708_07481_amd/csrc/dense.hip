@@ -1191,9 +1191,9 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
     // staging registers: the next chunk's V tile (float4) and M rows, loaded
     // while the current chunk is on the matrix cores
     constexpr int PV = RG_BM * (RG_KC / 4) / 256;
-    constexpr int PM = (RG_KC * 16 * NC + 255) / 256;
+    constexpr int PM = (RG_KC * 4 * NC + 255) / 256;     // float4 of M per thread
     float4 rv[PV];
-    float rm[PM];
+    float4 rm[PM];
     auto load = [&](int kc, int kn) {
         // whole tiles take plain loads, with no per-element tests
         const bool whole = kn == RG_KC && row0 + RG_BM <= n && nout == 16 * NC;
@@ -1217,12 +1217,25 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
             }
             rv[u] = x;
         }
+        // rows of M by 16-byte loads when they are whole and aligned
+        const bool m4 = whole && ldm % 4 == 0 && ((uintptr_t)M % 16) == 0;
 #pragma unroll
         for (int u = 0; u < PM; ++u) {
             const int q = tid + 256 * u;
-            const int k = q / (16 * NC), j = q % (16 * NC);
-            const bool in = q < RG_KC * 16 * NC;
-            rm[u] = (in && (whole || (k < kn && j < nout))) ? M[(int64_t)(kc + k) * ldm + j] : 0.0f;
+            const int k = q / (4 * NC), j = 4 * (q % (4 * NC));
+            const float* src = M + (int64_t)(kc + k) * ldm + j;
+            float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (q < RG_KC * 4 * NC) {
+                if (m4) {
+                    x = *reinterpret_cast<const float4*>(src);
+                } else if (k < kn) {
+                    if (j < nout) x.x = src[0];
+                    if (j + 1 < nout) x.y = src[1];
+                    if (j + 2 < nout) x.z = src[2];
+                    if (j + 3 < nout) x.w = src[3];
+                }
+            }
+            rm[u] = x;
         }
     };
     auto stage = [&]() {
@@ -1237,7 +1250,8 @@ k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int
 #pragma unroll
         for (int u = 0; u < PM; ++u) {
             const int q = tid + 256 * u;
-            if (q < RG_KC * 16 * NC) Ms[(q / (16 * NC)) * MS + q % (16 * NC)] = rm[u];
+            if (q < RG_KC * 4 * NC)
+                *reinterpret_cast<float4*>(Ms + (q / (4 * NC)) * MS + 4 * (q % (4 * NC))) = rm[u];
         }
     };
     auto section = [&](int lo, int hi) {
