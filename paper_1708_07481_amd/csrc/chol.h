@@ -7,11 +7,15 @@
 //   1. the CHOL_NB x CHOL_NB diagonal block is factored in LDS (pivot test
 //      s_j > tol * diag0_j against the matrix's original diagonal);
 //   2. the panel rows right of the block are solved, R_pp' X = A_p,rest, one
-//      thread per column, and kept in LDS;
-//   3. the trailing upper triangle is updated, A -= X'X, in 4 x 4 register
-//      tiles reading X from LDS.
+//      thread per column (the column's panel entries loaded before the
+//      substitution starts), and kept in LDS;
+//   3. the trailing upper triangle is updated, A -= X'X: a wave takes four
+//      rows and up to 256 columns from the first upper one, each lane four
+//      columns 64 apart, so that a wave's LDS reads of X are one broadcast
+//      (the rows) and consecutive words (the columns), free of bank conflicts.
 // Each trailing element is read and written once per panel (instead of once
-// per column in the unblocked form).
+// per column in the unblocked form).  Every element takes the same sequence
+// of operations whatever the workgroup size.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,11 +75,13 @@ __device__ inline int chol_blocked(int m, double* __restrict__ U, double tol, Ch
         }
         // 2. panel solve: column c of the rows p0..q0-1, forward substitution
         for (int c = tid; c < len; c += NTH) {
-            double x[CHOL_NB];
+            double x[CHOL_NB];                    // the loaded entries, then the solution
+#pragma unroll
+            for (int i = 0; i < CHOL_NB; ++i) x[i] = i < nb ? U[(int64_t)(p0 + i) * m + q0 + c] : 0.0;
 #pragma unroll
             for (int i = 0; i < CHOL_NB; ++i) {
                 if (i < nb) {
-                    double s = U[(int64_t)(p0 + i) * m + q0 + c];
+                    double s = x[i];
                     for (int l = 0; l < i; ++l) s -= L.blk[l][i] * x[l];
                     x[i] = s / L.blk[i][i];
                     U[(int64_t)(p0 + i) * m + q0 + c] = x[i];
@@ -84,33 +90,40 @@ __device__ inline int chol_blocked(int m, double* __restrict__ U, double tol, Ch
             }
         }
         __syncthreads();
-        // 3. trailing update of the upper triangle in 4 x 4 tiles
-        const int T = (len + 3) / 4;
-        for (int t = tid; t < T * T; t += NTH) {
-            const int ta = t / T, tb = t % T;
-            if (tb < ta) continue;
-            const int a0 = 4 * ta, b0 = 4 * tb;
-            double acc[4][4] = {};
-            for (int i = 0; i < nb; ++i) {
-                double xa[4], xb[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    xa[r] = a0 + r < len ? L.panel[i][a0 + r] : 0.0;
-                    xb[r] = b0 + r < len ? L.panel[i][b0 + r] : 0.0;
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[r][c] = fma(xa[r], xb[c], acc[r][c]);
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int a = a0 + r;
-                if (a >= len) break;
+        // 3. trailing update of the upper triangle: rows a0..a0+3 of a wave,
+        //    columns a0 + 256 cb + lane + 64 c of a lane (clamped reads, masked
+        //    writes)
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int ta = wave; 4 * ta < len; ta += NTH / 64) {
+            const int a0 = 4 * ta;
+            double* __restrict__ Ur = U + (int64_t)(q0 + a0) * m + q0;
+            for (int cb = 0; a0 + 256 * cb < len; ++cb) {
+                int bc[4];
+                bool okc[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int b = b0 + c;
-                    if (b < len && b >= a) U[(int64_t)(q0 + a) * m + q0 + b] -= acc[r][c];
+                    const int b = a0 + 256 * cb + lane + 64 * c;
+                    okc[c] = b < len;
+                    bc[c] = okc[c] ? b : len - 1;
+                }
+                double acc[4][4] = {};
+                for (int i = 0; i < nb; ++i) {
+                    double xa[4], xb[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xa[r] = L.panel[i][min(a0 + r, len - 1)];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) xb[c] = L.panel[i][bc[c]];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[r][c] = fma(xa[r], xb[c], acc[r][c]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (a0 + r >= len) break;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (okc[c] && bc[c] >= a0 + r) Ur[(int64_t)r * m + bc[c]] -= acc[r][c];
                 }
             }
         }

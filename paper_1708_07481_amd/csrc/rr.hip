@@ -629,8 +629,8 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
         }
         __syncthreads();
         m = m_s;
-        for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
-            const int a = (int)(q / m), b = (int)(q % m);
+        for (int q = tid; q < m * m; q += NT) {         // m <= MAXM: 32-bit indices
+            const int a = q / m, b = q - a * m;
             U[q] = GB[(int64_t)idx[a] * K3 + idx[b]];
         }
         __syncthreads();
@@ -681,8 +681,8 @@ k_rr_setup(int K3, int kp, const double* __restrict__ GA, const double* __restri
         }
         return;
     }
-    for (int64_t q = tid; q < (int64_t)m * m; q += NT) {
-        const int a = (int)(q / m), b = (int)(q % m);
+    for (int q = tid; q < m * m; q += NT) {
+        const int a = q / m, b = q - a * m;
         Am[q] = GA[(int64_t)idx[a] * K3 + idx[b]];
     }
     if (tid == 0) {
@@ -844,6 +844,7 @@ k_rr_tridiag(const int* __restrict__ info, double* __restrict__ M, double* __res
 constexpr int TD_NT = 256;
 constexpr int TD_WAVES = TD_NT / 64;
 constexpr int TD_GRID = 32;
+static_assert(MAXM % TD_NT == 0, "the exchange loads take MAXM / TD_NT values per thread");
 constexpr int TDL_GRID = 32;    // workgroups of the LDS-resident reduction
 constexpr int TDL_RG = 4;       // rows per wave whose dot products run together
 // bound on the spin of one barrier wait (each spin sleeps ~128 clocks); a
@@ -1076,20 +1077,32 @@ k_tridiag_lds(const int* __restrict__ info, int m_max, double* __restrict__ M,
             }
         }
         grid_sync(bar, gen, status);
-        // 2. w, the next column, and the update of the own rows
+        // 2. w, the next column, and the update of the own rows.  All of a
+        //    thread's loads of P and of the column are issued before any is
+        //    used, so the exchange costs one memory latency.
+        double pv[MAXM / TD_NT], cv[MAXM / TD_NT];
+#pragma unroll
+        for (int q = 0; q < MAXM / TD_NT; ++q) {
+            const int r = tid + q * TD_NT;
+            pv[q] = r < len ? Pb[j + 1 + r] : 0.0;
+            cv[q] = r < len ? Cb[j + 1 + r] : 0.0;
+        }
         part = 0.0;
-        for (int r = tid; r < len; r += TD_NT) {
-            const double pr = Pb[j + 1 + r];
-            ws[r] = pr;
-            part = fma(pr, vs[r], part);
+#pragma unroll
+        for (int q = 0; q < MAXM / TD_NT; ++q) {
+            const int r = tid + q * TD_NT;
+            if (r < len) {
+                ws[r] = pv[q];
+                col[j + 1 + r] = cv[q];
+                part = fma(pv[q], vs[r], part);
+            }
         }
         const double Kc = 0.5 * tj * block_sum_td(part, red);
         for (int r = tid; r < len; r += TD_NT) ws[r] = ws[r] - Kc * vs[r];
         __syncthreads();
-        for (int r = tid; r < len; r += TD_NT) {
-            const double cv = Cb[j + 1 + r];
-            col[j + 1 + r] = tj != 0.0 ? cv - (vs[r] * ws[0] + ws[r] * vs[0]) : cv;
-        }
+        if (tj != 0.0)
+            for (int r = tid; r < len; r += TD_NT)
+                col[j + 1 + r] = col[j + 1 + r] - (vs[r] * ws[0] + ws[r] * vs[0]);
         if (tj != 0.0) {
             for (int s = s0 + wave; s * G + g < m; s += TD_WAVES) {
                 const int r = s * G + g - (j + 1);
