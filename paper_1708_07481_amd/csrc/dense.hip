@@ -601,7 +601,8 @@ k_cholqr_factor(int c, const double* __restrict__ G, int* __restrict__ mask, dou
 //   - blocked right-looking Cholesky with panels of CQL_NB rows: wave 0
 //     factors the diagonal block, one thread per column solves the panel
 //     rows (kept also in Xp), and the trailing triangle takes the rank-CQL_NB
-//     update in 4 x 4 register tiles; three barriers per panel;
+//     update, four rows per wave and lane-consecutive columns; three
+//     barriers per panel;
 //   - R^-1 one wave per column j by a column sweep of R x = e_j: for
 //     a = j .. 0, x_a = b_a / R(a, a) (b_a broadcast from its lane, the
 //     reciprocal precomputed), then b_l -= R(l, a) x_a on the lanes' rows l < a.
@@ -709,24 +710,31 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
                 }
             }
             __syncthreads();
-            // 3. trailing upper triangle in 4 x 4 tiles
-            const int T = (len + 3) / 4;
-            for (int t = tid; t < T * T; t += CQ_TH) {
-                const int ta = t / T, tb = t % T;
-                if (tb < ta) continue;
-                const int a0 = q0 + 4 * ta, b0 = q0 + 4 * tb;
-                double acc[4][4] = {};
-                for (int i = 0; i < nb; ++i) {
-                    double xa[4], xb[4];
+            // 3. trailing upper triangle: a wave takes rows a0..a0+3, a lane the
+            //    columns a0 + lane + 64 c, so that a wave's reads of Xp are one
+            //    broadcast (the rows) and consecutive words (the columns), and
+            //    its updates of P consecutive words; clamped reads, masked writes
+            for (int ta = wave; 4 * ta < len; ta += NW) {
+                const int a0 = q0 + 4 * ta;
+                int bc[CQL_SLOTS];
+                bool okc[CQL_SLOTS];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        xa[r] = a0 + r < m ? Xp[i][a0 + r] : 0.0;
-                        xb[r] = b0 + r < m ? Xp[i][b0 + r] : 0.0;
-                    }
+                for (int c = 0; c < CQL_SLOTS; ++c) {
+                    const int b = a0 + lane + 64 * c;
+                    okc[c] = b < m;
+                    bc[c] = okc[c] ? b : m - 1;
+                }
+                double acc[4][CQL_SLOTS] = {};
+                for (int i = 0; i < nb; ++i) {
+                    double xa[4], xb[CQL_SLOTS];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) xa[r] = Xp[i][min(a0 + r, m - 1)];
+#pragma unroll
+                    for (int c = 0; c < CQL_SLOTS; ++c) xb[c] = Xp[i][bc[c]];
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[r][q] = fma(xa[r], xb[q], acc[r][q]);
+                        for (int c = 0; c < CQL_SLOTS; ++c) acc[r][c] = fma(xa[r], xb[c], acc[r][c]);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -734,10 +742,8 @@ k_cholqr_factor_lds(int c, const double* __restrict__ G, int* __restrict__ mask,
                     if (aa >= m) break;
                     const int o = ro[aa];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int bb = b0 + q;
-                        if (bb < m && bb >= aa) P[o + bb] -= acc[r][q];
-                    }
+                    for (int c = 0; c < CQL_SLOTS; ++c)
+                        if (okc[c] && bc[c] >= aa) P[o + bc[c]] -= acc[r][c];
                 }
             }
             __syncthreads();
@@ -1169,12 +1175,21 @@ sc_status launch_cholqr_factor(sc_ctx* ctx, int c, const double* G, int* mask, d
 // [a0, a1)); section a is then added and the total goes to the o1 columns.
 constexpr int RG_WR = 2;
 constexpr int RG_BM = 4 * 16 * RG_WR;
-constexpr int RG_KC = 32;
+// K chunk width and waves per SIMD: the 160-column block update (NC = 10)
+// takes 16-wide chunks, which fit it in 144 registers and so three
+// workgroups per CU (2.7 % faster than two at 32-wide chunks); the
+// triangular apply keeps 32-wide chunks (16 costs it 5 %), and the other
+// widths already fit three workgroups or cannot.
+template <int NC, bool TRI>
+constexpr int rg_kc() { return (NC == 10 && !TRI) ? 16 : 32; }
+template <int NC, bool TRI>
+constexpr int rg_waves() { return (NC == 10 && !TRI) ? 3 : 1; }
 
 template <int NC, bool TRI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(rg_waves<NC, TRI>())))
 k_rowgemm_mfma(int64_t n, float* __restrict__ V, int64_t ld, int a0, int a1, int b0, int b1,
                int b2, int b3, const float* __restrict__ M, int ldm, int nout, int o1, int o2) {
+    constexpr int RG_KC = rg_kc<NC, TRI>();
     constexpr int VS = RG_KC + 2;
     constexpr int MS = 16 * NC + ((NC % 2 == 0) ? 16 : 0);
     __shared__ __attribute__((aligned(16))) float Vs[RG_BM * VS];
