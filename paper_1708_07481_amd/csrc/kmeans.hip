@@ -1098,23 +1098,53 @@ struct CentroidShape {
     static constexpr int NL = (CI + 63) / 64;      // id loads per lane and chunk
     static constexpr int NT = 64 * (PW + 1);
 };
+// Workgroup order of a centroid launch: the (restart, cluster) pairs that
+// need an update, longest member list first, then the others (which exit at
+// once).  The longest chains set a launch's length, and workgroups start in
+// index order as slots free up, so the longest ones start first (longest
+// processing time first).  Rank of pair i = the pairs with a larger key, or
+// an equal key and a lower index: a permutation, one thread per pair.
+__global__ void __launch_bounds__(TH)
+k_centroid_order(int K, int RK, const int* __restrict__ active, const int* __restrict__ dirty,
+                 const int64_t* __restrict__ seg, int* __restrict__ order) {
+    __shared__ int64_t ks[TH];
+    const int i = blockIdx.x * TH + threadIdx.x;
+    auto key = [&](int j) -> int64_t {
+        return km_needs_update(j, K, active, dirty, seg) ? seg[2 * j + 1] - seg[2 * j] : 0;
+    };
+    const int64_t ki = i < RK ? key(i) : -1;
+    int rank = 0;
+    for (int c0 = 0; c0 < RK; c0 += TH) {
+        __syncthreads();
+        ks[threadIdx.x] = c0 + (int)threadIdx.x < RK ? key(c0 + threadIdx.x) : -1;
+        __syncthreads();
+        const int cn = min(TH, RK - c0);
+        for (int t = 0; t < cn; ++t) {
+            const int64_t kj = ks[t];
+            rank += (kj > ki) || (kj == ki && c0 + t < i);
+        }
+    }
+    if (i < RK) order[rank] = i;
+}
+
 template <int PW>
 __global__ void __launch_bounds__(CentroidShape<PW>::NT)
 k_centroid_sum(int dim, int K, int R, const double* __restrict__ Y,
                const uint32_t* __restrict__ members, const int64_t* __restrict__ seg,
                const int* __restrict__ active, const int* __restrict__ dirty,
-               double* __restrict__ C) {
+               const int* __restrict__ order, double* __restrict__ C) {
     constexpr int CP_B = CentroidShape<PW>::B;
     constexpr int CP_CI = CentroidShape<PW>::CI;
     constexpr int CP_NL = CentroidShape<PW>::NL;
     __shared__ double ring[2][CP_B][64];
     __shared__ int idbuf[2][CP_CI];
     const int wps = (dim + 63) / 64;
-    const int64_t rj = blockIdx.x / wps;
-    if (rj >= (int64_t)R * K) return;
+    const int64_t slot = blockIdx.x / wps;
+    if (slot >= (int64_t)R * K) return;
+    const int64_t rj = order[slot];
     if (!km_needs_update(rj, K, active, dirty, seg)) return;
     const int wave = uniform((int)(threadIdx.x >> 6)), lane = (int)(threadIdx.x & 63);
-    const int d = (int)(blockIdx.x - rj * wps) * 64 + lane;
+    const int d = (int)(blockIdx.x - slot * wps) * 64 + lane;
     const int dd = d < dim ? d : dim - 1;
     const int64_t lo = seg[2 * rj];
     const int64_t cnt = seg[2 * rj + 1] - lo;       // >= 1
@@ -1330,7 +1360,7 @@ struct KmWs {
     uint64_t *tsum, *lhist, *lscan_tmp;
     uint32_t *vals, *pts, *fl;
     int32_t* lab;
-    int *changed, *active, *cnt, *fcnt, *status, *dirty;
+    int *changed, *active, *cnt, *fcnt, *status, *dirty, *order;
     int64_t* seg;
     double *ccur, *hsv;
     float* secf;
@@ -1373,6 +1403,7 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.fcnt = c.take<int>(R);
     w.status = c.take<int>(1);
     w.dirty = c.take<int>((size_t)R * K);
+    w.order = c.take<int>((size_t)R * K);
     w.seg = c.take<int64_t>(2 * (size_t)R * K);
     w.Rpad = seed_stride(R);
     w.ccur = c.take<double>((size_t)w.Rpad * dim);
@@ -1644,12 +1675,14 @@ sc_status kmeans_run(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx
             for (int r = 0; r < R; ++r)
                 if (act_h[r]) moved += ch[r];
             const bool wide = it > 1 && 2 * moved * ceil_div(dim, 64) <= ctx->num_cu;
+            hipLaunchKernelGGL(k_centroid_order, dim3((unsigned)ceil_div((int64_t)R * K, TH)), dim3(TH),
+                               0, st, K, R * K, w.active, w.dirty, w.seg, w.order);
             if (wide)
                 hipLaunchKernelGGL(k_centroid_sum<7>, dim3(grid), dim3(CentroidShape<7>::NT), 0, st,
-                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.order, w.C);
             else
                 hipLaunchKernelGGL(k_centroid_sum<3>, dim3(grid), dim3(CentroidShape<3>::NT), 0, st,
-                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.C);
+                                   dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.order, w.C);
         }
         SC_CHECK_LAUNCH(ctx);
         hipLaunchKernelGGL(k_delta, dim3((unsigned)ceil_div((int64_t)R * K, TH / 64)), dim3(TH), 0, st, K,
