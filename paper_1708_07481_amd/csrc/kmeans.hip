@@ -1101,30 +1101,44 @@ struct CentroidShape {
 // Workgroup order of a centroid launch: the (restart, cluster) pairs that
 // need an update, longest member list first, then the others (which exit at
 // once).  The longest chains set a launch's length, and workgroups start in
-// index order as slots free up, so the longest ones start first (longest
-// processing time first).  Rank of pair i = the pairs with a larger key, or
-// an equal key and a lower index: a permutation, one thread per pair.
-__global__ void __launch_bounds__(TH)
+// index order as slots free up, so the longest ones should start first
+// (longest processing time first).  One workgroup buckets the pairs by the
+// leading three bits of their member count (four buckets per power of two,
+// so a bucket's counts lie within a factor of 1.25) and lays the buckets out
+// in descending order; within a bucket the order is that of the atomic
+// position grabs.  The order only decides when a workgroup starts: every
+// cluster's sum is the same whatever it is.
+constexpr int CO_TH = 1024;
+constexpr int CO_NB = 4 * 64;
+__device__ inline int centroid_bucket(int64_t c) {
+    if (c <= 0) return 0;
+    const int e = 63 - __clzll((unsigned long long)c);              // leading one
+    const int sub = e >= 2 ? (int)((c >> (e - 2)) & 3) : (int)((c << (2 - e)) & 3);
+    return 4 * e + sub + 1 < CO_NB ? 4 * e + sub + 1 : CO_NB - 1;
+}
+__global__ void __launch_bounds__(CO_TH)
 k_centroid_order(int K, int RK, const int* __restrict__ active, const int* __restrict__ dirty,
                  const int64_t* __restrict__ seg, int* __restrict__ order) {
-    __shared__ int64_t ks[TH];
-    const int i = blockIdx.x * TH + threadIdx.x;
-    auto key = [&](int j) -> int64_t {
-        return km_needs_update(j, K, active, dirty, seg) ? seg[2 * j + 1] - seg[2 * j] : 0;
-    };
-    const int64_t ki = i < RK ? key(i) : -1;
-    int rank = 0;
-    for (int c0 = 0; c0 < RK; c0 += TH) {
-        __syncthreads();
-        ks[threadIdx.x] = c0 + (int)threadIdx.x < RK ? key(c0 + threadIdx.x) : -1;
-        __syncthreads();
-        const int cn = min(TH, RK - c0);
-        for (int t = 0; t < cn; ++t) {
-            const int64_t kj = ks[t];
-            rank += (kj > ki) || (kj == ki && c0 + t < i);
+    __shared__ int hist[CO_NB], start[CO_NB];
+    for (int b = threadIdx.x; b < CO_NB; b += CO_TH) hist[b] = 0;
+    __syncthreads();
+    for (int j = threadIdx.x; j < RK; j += CO_TH) {
+        const int64_t c = km_needs_update(j, K, active, dirty, seg) ? seg[2 * j + 1] - seg[2 * j] : 0;
+        atomicAdd(&hist[centroid_bucket(c)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = CO_NB - 1; b >= 0; --b) {
+            start[b] = acc;
+            acc += hist[b];
         }
     }
-    if (i < RK) order[rank] = i;
+    __syncthreads();
+    for (int j = threadIdx.x; j < RK; j += CO_TH) {
+        const int64_t c = km_needs_update(j, K, active, dirty, seg) ? seg[2 * j + 1] - seg[2 * j] : 0;
+        order[atomicAdd(&start[centroid_bucket(c)], 1)] = j;
+    }
 }
 
 template <int PW>
@@ -1675,8 +1689,8 @@ sc_status kmeans_run(sc_ctx* ctx, int64_t n, int dim, const void* X, int64_t ldx
             for (int r = 0; r < R; ++r)
                 if (act_h[r]) moved += ch[r];
             const bool wide = it > 1 && 2 * moved * ceil_div(dim, 64) <= ctx->num_cu;
-            hipLaunchKernelGGL(k_centroid_order, dim3((unsigned)ceil_div((int64_t)R * K, TH)), dim3(TH),
-                               0, st, K, R * K, w.active, w.dirty, w.seg, w.order);
+            hipLaunchKernelGGL(k_centroid_order, dim3(1), dim3(CO_TH), 0, st, K, R * K, w.active,
+                               w.dirty, w.seg, w.order);
             if (wide)
                 hipLaunchKernelGGL(k_centroid_sum<7>, dim3(grid), dim3(CentroidShape<7>::NT), 0, st,
                                    dim, K, R, w.Y, w.vals, w.seg, w.active, w.dirty, w.order, w.C);
