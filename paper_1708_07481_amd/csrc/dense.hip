@@ -8,6 +8,7 @@
 // deterministic (no floating-point atomics).
 #include "chol.h"
 #include "sc_internal.h"
+#include <type_traits>
 
 namespace {
 
@@ -935,6 +936,68 @@ k_residual(int64_t n, int kp, int k, int woff, T* __restrict__ S, const T* __res
     }
 }
 
+// The same residual with 16-byte accesses: a thread takes V = 16 / sizeof(T)
+// adjacent columns of every RS-th row of the block (G = kp / V column groups,
+// RS = 256 / G row lanes); each column's FP64 sums are then added over the
+// row lanes in lane order.  For kp a multiple of V with kp / V <= 256, and
+// strides, the W offset and both pointers multiples of 16 bytes.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_residual_vec(int64_t n, int kp, int k, int woff, T* __restrict__ S, const T* __restrict__ LS,
+               int64_t ld, const double* __restrict__ theta, double* __restrict__ partial) {
+    constexpr int V = 16 / (int)sizeof(T);
+    using VT = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    __shared__ double red[2][256 * V];
+    const int G = kp / V, RS = 256 / G;
+    const int g = (int)threadIdx.x % G, sl = (int)threadIdx.x / G;
+    const int64_t r0 = (int64_t)blockIdx.x * RES_ROWS;
+    const int64_t r1 = min<int64_t>(n, r0 + RES_ROWS);
+    double rr[V], xx[V];
+    T th[V];
+    bool on[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int j = g * V + v;
+        on[v] = j < k;
+        th[v] = on[v] ? (T)theta[j] : T(0);
+        rr[v] = 0.0;
+        xx[v] = 0.0;
+    }
+    if (sl < RS) {
+#pragma unroll 4
+        for (int64_t i = r0 + sl; i < r1; i += RS) {
+            const VT xv = *reinterpret_cast<const VT*>(S + i * ld + g * V);
+            const VT lv = *reinterpret_cast<const VT*>(LS + i * ld + g * V);
+            const T* x = reinterpret_cast<const T*>(&xv);
+            const T* l = reinterpret_cast<const T*>(&lv);
+            VT rv;
+            T* r = reinterpret_cast<T*>(&rv);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                r[v] = on[v] ? fma(-th[v], x[v], l[v]) : T(0);
+                rr[v] = fma((double)r[v], (double)r[v], rr[v]);
+                if (on[v]) xx[v] = fma((double)x[v], (double)x[v], xx[v]);
+            }
+            *reinterpret_cast<VT*>(S + i * ld + woff + g * V) = rv;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            red[0][sl * kp + g * V + v] = rr[v];
+            red[1][sl * kp + g * V + v] = xx[v];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kp; j += 256) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < RS; ++q) {
+            a += red[0][q * kp + j];
+            b += red[1][q * kp + j];
+        }
+        partial[((int64_t)blockIdx.x * 2 + 0) * kp + j] = a;
+        partial[((int64_t)blockIdx.x * 2 + 1) * kp + j] = b;
+    }
+}
+
 // per-column totals of the block partials, in place into block 0's slots:
 // workgroup (j, t) sums partial[b][t][j] over the blocks b (fixed tree order)
 __global__ void __launch_bounds__(256)
@@ -1453,8 +1516,15 @@ template <class T>
 sc_status launch_residual(sc_ctx* ctx, int64_t n, int kp, int k, int woff, T* S, const T* LS,
                           int64_t ld, const double* theta, double* partial, int* nblocks_out) {
     const int nb = (int)ceil_div(n, RES_ROWS);
-    hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(256), 0, ctx->stream, n, kp, k, woff, S, LS,
-                       ld, theta, partial);
+    constexpr int V = 16 / (int)sizeof(T);
+    const bool vec = kp % V == 0 && kp / V <= 256 && ld % V == 0 && woff % V == 0 &&
+                     (uintptr_t)S % 16 == 0 && (uintptr_t)LS % 16 == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_residual_vec<T>), dim3(nb), dim3(256), 0, ctx->stream, n, kp, k, woff, S,
+                           LS, ld, theta, partial);
+    else
+        hipLaunchKernelGGL((k_residual<T>), dim3(nb), dim3(256), 0, ctx->stream, n, kp, k, woff, S, LS,
+                           ld, theta, partial);
     SC_CHECK_LAUNCH(ctx);
     *nblocks_out = nb;
     return SC_OK;
