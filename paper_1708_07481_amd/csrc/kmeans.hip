@@ -29,6 +29,10 @@ namespace {
 constexpr int TH = 256;
 constexpr double BOUND_MARGIN = 1e-12;   // relative inflation of every bound
 constexpr double BOUND_TINY = 1e-150;    // absolute slack for zero distances
+// The Hamerly bounds are formed in FP64 and stored in FP32 rounded outward
+// (upper bounds up, lower bounds down), so a stored bound is never tighter
+// than the FP64 one; a bound only decides which points are scanned, and the
+// labels come from exact distances.
 
 __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) { return __umul64hi(a, b); }
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -342,13 +346,13 @@ k_seed_d2(int64_t n, int dim, int R, int Rpad, int j, const TT* __restrict__ Yt,
 
 // first assignment from the seeding's distances: Hamerly bounds from the
 // least distance (D2) and the lower bound of the second least (secf)
-__global__ void k_first_bounds(int64_t nr, const double* __restrict__ D2, double* __restrict__ ub,
-                               const float* __restrict__ secf, double* __restrict__ lb) {
+__global__ void k_first_bounds(int64_t nr, const double* __restrict__ D2, float* __restrict__ ub,
+                               const float* __restrict__ secf, float* __restrict__ lb) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nr) return;
-    ub[e] = sqrt(D2[e]) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+    ub[e] = __double2float_ru(sqrt(D2[e]) * (1.0 + BOUND_MARGIN) + BOUND_TINY);
     const double s = secf[e];
-    lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+    lb[e] = isinf(s) ? INFINITY : __double2float_rd(sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY);
 }
 
 // Ct[r][d][j] = C[r][j][d] for j < K; columns K <= j < Kpad hold +inf, a
@@ -381,7 +385,7 @@ __global__ void __launch_bounds__(TH)
 k_assign_list(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, int64_t ldy,
               const YDiv* __restrict__ dv, const double* __restrict__ Ct, const uint32_t* __restrict__ pts,
               const int* __restrict__ cnt, const int* __restrict__ active,
-              int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
+              int32_t* __restrict__ lab, float* __restrict__ ub, float* __restrict__ lb,
               int* __restrict__ changed, int* __restrict__ dirty, int first) {
     constexpr int DC = 32;
     __shared__ double ys[DC][65];   // padded row: fewer LDS bank conflicts on the transposing store
@@ -483,8 +487,8 @@ k_assign_list(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, int
             }
         }
         lab[e] = j;
-        ub[e] = sqrt(b) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
-        lb[e] = isinf(s) ? INFINITY : sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
+        ub[e] = __double2float_ru(sqrt(b) * (1.0 + BOUND_MARGIN) + BOUND_TINY);
+        lb[e] = isinf(s) ? INFINITY : __double2float_rd(sqrt(s) * (1.0 - BOUND_MARGIN) - BOUND_TINY);
     }
 }
 
@@ -578,7 +582,7 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, i
                 const double* __restrict__ hsv, const uint16_t* __restrict__ hsi,
                 const uint32_t* __restrict__ pts,
                 const int* __restrict__ cnt, const int* __restrict__ active,
-                int32_t* __restrict__ lab, double* __restrict__ ub, double* __restrict__ lb,
+                int32_t* __restrict__ lab, float* __restrict__ ub, float* __restrict__ lb,
                 int* __restrict__ changed, int* __restrict__ dirty, uint32_t* __restrict__ fl,
                 int* __restrict__ fcnt) {
     constexpr int NW = TH / 64;
@@ -757,10 +761,10 @@ k_assign_pruned(int64_t n, int dim, int K, int Kpad, const TT* __restrict__ Y, i
         dirty[(int64_t)r * K + bj] = 1;
     }
     lab[e] = bj;
-    ub[e] = sqrt(best) * (1.0 + BOUND_MARGIN) + BOUND_TINY;
+    ub[e] = __double2float_ru(sqrt(best) * (1.0 + BOUND_MARGIN) + BOUND_TINY);
     double l = isinf(second) ? INFINITY : sqrt(second) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
     if (hmin < INFINITY) l = fmin(l, (2.0 * hmin - u) * (1.0 - BOUND_MARGIN) - BOUND_TINY);
-    lb[e] = l;
+    lb[e] = __double2float_rd(l);
 }
 
 // centre displacements: delta[r][j] = ||c_new - c_old|| (inflated); a centre
@@ -838,8 +842,8 @@ k_delta_max(int K, const int* __restrict__ active, const double* __restrict__ de
 // so per-wave atomics would serialise on a handful of addresses).
 constexpr int PPT = 8;
 __global__ void __launch_bounds__(TH)
-k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, double* __restrict__ ub,
-         double* __restrict__ lb, const double* __restrict__ delta, const double* __restrict__ dinfo,
+k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, float* __restrict__ ub,
+         float* __restrict__ lb, const double* __restrict__ delta, const double* __restrict__ dinfo,
          const int* __restrict__ active, uint32_t* __restrict__ pts, int* __restrict__ cnt) {
     __shared__ int wtot[TH / 64];
     __shared__ int base_s;
@@ -860,8 +864,8 @@ k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, double* __restrict__
             const double dmax = a == amax ? dmax1 : dmax0;
             const double uu = (ub[e] + delta[(int64_t)r * K + a]) * (1.0 + BOUND_MARGIN);
             const double ll = (lb[e] - dmax) * (1.0 - BOUND_MARGIN) - BOUND_TINY;
-            ub[e] = uu;
-            lb[e] = ll;
+            ub[e] = __double2float_ru(uu);
+            lb[e] = __double2float_rd(ll);
             need = !(uu < ll);
         }
         masks[u] = __ballot(need);
@@ -1370,7 +1374,8 @@ int assign_kpad(int K) {
 }
 
 struct KmWs {
-    double *Y, *D2, *C, *Cold, *Ct, *ub, *lb, *delta, *dinfo, *part, *inertia;
+    double *Y, *D2, *C, *Cold, *Ct, *delta, *dinfo, *part, *inertia;
+    float *ub, *lb;      // Hamerly bounds, stored in FP32 rounded outward
     uint64_t *tsum, *lhist, *lscan_tmp;
     uint32_t *vals, *pts, *fl;
     int32_t* lab;
@@ -1398,8 +1403,8 @@ size_t carve_km(Carver& c, int64_t n, int dim, int K, int R, KmWs& w) {
     w.C = c.take<double>(cent);
     w.Cold = c.take<double>(cent);
     w.Ct = c.take<double>((size_t)R * assign_kpad(K) * dim);
-    w.ub = c.take<double>(nr);
-    w.lb = c.take<double>(nr);
+    w.ub = c.take<float>(nr);
+    w.lb = c.take<float>(nr);
     w.delta = c.take<double>((size_t)R * K);
     w.dinfo = c.take<double>(3 * (size_t)R);
     w.part = c.take<double>(ceil_div(n, TH * 16) + 1);
