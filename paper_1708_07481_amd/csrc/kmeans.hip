@@ -895,33 +895,37 @@ k_bounds(int64_t n, int K, const int32_t* __restrict__ lab, float* __restrict__ 
 // Member lists: a stable counting sort of each active restart's points by
 // label (ascending vertex order within a label).  Tiles of LS_TILE points:
 // per-tile label histograms (label-major, tile-minor), one exclusive scan per
-// restart, then every tile is ordered by label in LDS with one stable one-bit
-// split per label bit and scattered to its offsets.  The scan also gives the
+// restart, then every tile is ordered by label in LDS with stable two-bit
+// splits (two label bits per pass) and scattered to its offsets.  The scan also gives the
 // segment of every label directly.
 constexpr int LS_ITEMS = 8;
 constexpr int LS_TILE = TH * LS_ITEMS;
 
-__device__ inline uint32_t ls_block_excl_scan(uint32_t v, uint32_t* total, uint32_t* wsum) {
+// Exclusive scan over the workgroup of four 16-bit counters packed in a
+// 64-bit word (each field's block total stays below 2^16: a tile holds
+// LS_TILE points); *total = the block's sums.
+static_assert(2 * LS_TILE < 65536, "16-bit digit counters plus digit bases");
+__device__ inline uint64_t ls_block_excl_scan4(uint64_t v, uint64_t* total, uint64_t* wsum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
+    uint64_t x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o, 64);
+        const uint64_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t acc = 0;
+        uint64_t acc = 0;
         for (int w = 0; w < TH / 64; ++w) {
-            const uint32_t t = wsum[w];
+            const uint64_t t = wsum[w];
             wsum[w] = acc;
             acc += t;
         }
         wsum[TH / 64] = acc;
     }
     __syncthreads();
-    const uint32_t r = x - v + wsum[wave];
+    const uint64_t r = x - v + wsum[wave];
     *total = wsum[TH / 64];
     __syncthreads();
     return r;
@@ -977,7 +981,7 @@ k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
               uint32_t* __restrict__ vals) {
     __shared__ uint16_t kb[2][LS_TILE];
     __shared__ uint32_t vb[2][LS_TILE];
-    __shared__ uint32_t wsum[TH / 64 + 1];
+    __shared__ uint64_t wsum[TH / 64 + 1];
     __shared__ uint32_t lstart[PR_KMAX];
     const int r = blockIdx.y;
     if (!active[r]) return;
@@ -997,30 +1001,32 @@ k_lab_scatter(int64_t n, int K, int nbits, const int* __restrict__ active,
         vb[0][p] = v;
     }
     __syncthreads();
+    // stable LSD radix sort of the tile in shared memory, two key bits per
+    // pass: a digit's items go to its base (the tile's items with smaller
+    // digits) plus the items with the same digit before them (earlier
+    // threads, then earlier items of the same thread)
     int cur = 0;
-    for (int bit = 0; bit < nbits; ++bit) {
+    for (int bit = 0; bit < nbits; bit += 2) {
+        const uint32_t dmask = bit + 1 < nbits ? 3u : 1u;
         uint16_t k[LS_ITEMS];
         uint32_t v[LS_ITEMS];
-        uint32_t zeros = 0;
+        uint64_t cnt4 = 0;
 #pragma unroll
         for (int t = 0; t < LS_ITEMS; ++t) {
             k[t] = kb[cur][threadIdx.x * LS_ITEMS + t];
             v[t] = vb[cur][threadIdx.x * LS_ITEMS + t];
-            zeros += ((k[t] >> bit) & 1) ? 0u : 1u;
+            cnt4 += 1ull << (16 * ((k[t] >> bit) & dmask));
         }
-        uint32_t Z;
-        const uint32_t zt = ls_block_excl_scan(zeros, &Z, wsum);
-        uint32_t zb = 0;
+        uint64_t tot;
+        uint64_t pos = ls_block_excl_scan4(cnt4, &tot, wsum);
+        // digit bases, packed like the counters: field d = sum of totals below d
+        const uint64_t base = (tot << 16) + (tot << 32) + (tot << 48);
+        pos += base;
 #pragma unroll
         for (int t = 0; t < LS_ITEMS; ++t) {
-            const uint32_t P = threadIdx.x * LS_ITEMS + t;
-            uint32_t np;
-            if (((k[t] >> bit) & 1) == 0) {
-                np = zt + zb;
-                ++zb;
-            } else {
-                np = Z + (P - (zt + zb));
-            }
+            const int sh = 16 * (int)((k[t] >> bit) & dmask);
+            const uint32_t np = (uint32_t)((pos >> sh) & 0xFFFFu);
+            pos += 1ull << sh;
             kb[cur ^ 1][np] = k[t];
             vb[cur ^ 1][np] = v[t];
         }
