@@ -163,6 +163,7 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y
             const double* __restrict__ D2, int shift, double* __restrict__ C,
             double* __restrict__ ccur) {
     __shared__ uint64_t part[PICK_NT];
+    __shared__ uint64_t wtot[PICK_NT / 64];
     __shared__ int64_t pick;
     __shared__ int64_t tile_s;
     __shared__ uint64_t base_s;
@@ -174,18 +175,34 @@ k_seed_pick(int64_t n, int dim, int K, int j, int Rpad, const TT* __restrict__ Y
         const int64_t ntiles = (n + SEED_TILE - 1) / SEED_TILE;
         const uint64_t* ts = tsum + (int64_t)r * ntiles;
         const int64_t per = (ntiles + PICK_NT - 1) / PICK_NT;
-        const int64_t t0 = min((int64_t)tid * per, ntiles), t1 = min(t0 + per, ntiles);
-        uint64_t mine = 0;
-        for (int64_t t = t0; t < t1; ++t) mine += ts[t];
-        part[tid] = mine;
+        // thread tid's sum covers the tiles [tid per, (tid + 1) per); a wave's 64
+        // ranges are one contiguous run of tiles, which its lanes read coalesced
+        // and add into the owners' slots (integer sums: any order gives the same)
+        part[tid] = 0;
         __syncthreads();
-        // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
-        for (int o = 1; o < PICK_NT; o <<= 1) {
-            const uint64_t add = tid >= o ? part[tid - o] : 0;
-            __syncthreads();
-            part[tid] += add;
-            __syncthreads();
+        {
+            const int wave = tid >> 6, lane = tid & 63;
+            const int64_t w0 = min((int64_t)wave * 64 * per, ntiles), w1 = min(w0 + 64 * per, ntiles);
+            for (int64_t q = w0 + lane; q < w1; q += 64) atomicAdd(&part[(uint32_t)q / (uint32_t)per], ts[q]);
         }
+        __syncthreads();
+        const uint64_t mine = part[tid];
+        // inclusive scan of the per-thread sums: within waves by shuffles, then
+        // the totals of the earlier waves
+        {
+            const int wave = tid >> 6, lane = tid & 63;
+            uint64_t incl = mine;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint64_t x = __shfl_up(incl, o);
+                if (lane >= o) incl += x;
+            }
+            if (lane == 63) wtot[wave] = incl;
+            __syncthreads();
+            for (int w = 0; w < wave; ++w) incl += wtot[w];
+            part[tid] = incl;
+        }
+        __syncthreads();
         const uint64_t T = part[PICK_NT - 1];
         if (T > 0) {
             const uint64_t t = mulhi64(u, T);
