@@ -1,7 +1,7 @@
 // Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
 // Each pass: per-tile digit histograms, one device scan of the
 // (digit-major, tile-minor) histogram, then every tile is sorted by the digit
-// in LDS with eight stable one-bit splits and scattered to its offsets.
+// in LDS with four stable two-bit splits and scattered to its offsets.
 #include "sc_internal.h"
 
 namespace {
@@ -12,31 +12,31 @@ constexpr int TILE = TH * ITEMS;
 constexpr int NW = TH / 64;
 constexpr int RADIX = 256;
 
-__device__ inline uint32_t wave_incl_scan32(uint32_t x, int lane) {
+// Exclusive scan over the workgroup of four 16-bit counters packed in a
+// 64-bit word (a tile holds TILE < 2^15 keys, so no field overflows even with
+// its digit base); *total = the block's sums.
+static_assert(2 * TILE < 65536, "16-bit digit counters plus digit bases");
+__device__ inline uint64_t block_excl_scan4(uint64_t v, uint64_t* total, uint64_t* wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
+        const uint64_t y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    return x;
-}
-
-__device__ inline uint32_t block_excl_scan32(uint32_t v, uint32_t* total, uint32_t* wsum) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = wave_incl_scan32(v, lane);
     if (lane == 63) wsum[wave] = x;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t acc = 0;
+        uint64_t acc = 0;
         for (int w = 0; w < NW; ++w) {
-            uint32_t t = wsum[w];
+            const uint64_t t = wsum[w];
             wsum[w] = acc;
             acc += t;
         }
         wsum[NW] = acc;
     }
     __syncthreads();
-    uint32_t r = x - v + wsum[wave];
+    const uint64_t r = x - v + wsum[wave];
     *total = wsum[NW];
     __syncthreads();
     return r;
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(TH) k_digit_scatter(const uint64_t* __restrict
                                                        int ntiles) {
     __shared__ uint64_t kbuf[2][TILE];
     __shared__ uint32_t vbuf[2][TILE];
-    __shared__ uint32_t wsum[NW + 1];
+    __shared__ uint64_t wsum4[NW + 1];
     __shared__ uint32_t lstart[RADIX];
     const int64_t base = (int64_t)blockIdx.x * TILE;
     const int cnt = (int)min<int64_t>(TILE, n - base);
@@ -84,31 +84,29 @@ __global__ void __launch_bounds__(TH) k_digit_scatter(const uint64_t* __restrict
         }
     }
     __syncthreads();
+    // stable split of the tile by the digit's bits, two per pass: a key goes
+    // to its 2-bit value's base (the tile's keys with smaller values) plus the
+    // keys with the same value before it (earlier threads, then earlier items)
     int cur = 0;
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < 8; b += 2) {
         const int bit = shift + b;
         uint64_t k[ITEMS];
         uint32_t v[ITEMS];
-        uint32_t zeros = 0;
+        uint64_t cnt4 = 0;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             k[i] = kbuf[cur][threadIdx.x * ITEMS + i];
             v[i] = vbuf[cur][threadIdx.x * ITEMS + i];
-            zeros += ((k[i] >> bit) & 1) ? 0u : 1u;
+            cnt4 += 1ull << (16 * (int)((k[i] >> bit) & 3));
         }
-        uint32_t Z;
-        uint32_t zt = block_excl_scan32(zeros, &Z, wsum);
-        uint32_t zb = 0;
+        uint64_t tot;
+        uint64_t pos = block_excl_scan4(cnt4, &tot, wsum4);
+        pos += (tot << 16) + (tot << 32) + (tot << 48);     // field d += totals below d
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t P = threadIdx.x * ITEMS + i;
-            uint32_t np;
-            if (((k[i] >> bit) & 1) == 0) {
-                np = zt + zb;
-                ++zb;
-            } else {
-                np = Z + (P - (zt + zb));
-            }
+            const int sh = 16 * (int)((k[i] >> bit) & 3);
+            const uint32_t np = (uint32_t)((pos >> sh) & 0xFFFFu);
+            pos += 1ull << sh;
             kbuf[cur ^ 1][np] = k[i];
             vbuf[cur ^ 1][np] = v[i];
         }
