@@ -864,28 +864,27 @@ __device__ inline double block_sum_td(double v, double* red) {
     return s;
 }
 
-// grid barrier: bar[0] arrivals, bar[1] generation (both zero at launch)
+// grid barrier: bar[0] counts the arrivals of the whole launch (zero at
+// launch); barrier number g (from 1) is passed once bar[0] reaches
+// g * gridDim.x, so the last arrival's own increment releases every
+// workgroup.  Thread 0 publishes the workgroup's writes with an agent-scope
+// release fence before arriving and acquires the others' after the wait.
 __device__ inline void grid_sync(unsigned* bar, unsigned& gen, int* status) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned g = gen;
-        if (atomicAdd(bar, 1u) == gridDim.x - 1) {
-            atomicExch(bar, 0u);
-            __threadfence();
-            atomicAdd(bar + 1, 1u);
-        } else {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > TD_SPIN_LIMIT) {
-                    atomicOr(status, DEV_SYNC_TIMEOUT);
-                    break;
-                }
+        const unsigned target = (gen + 1u) * gridDim.x;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > TD_SPIN_LIMIT) {
+                atomicOr(status, DEV_SYNC_TIMEOUT);
+                break;
             }
         }
-        gen = g + 1;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        gen = gen + 1u;
     }
     __syncthreads();
 }
@@ -1212,7 +1211,7 @@ k_rr_back(int k, const int* __restrict__ info, const double* __restrict__ M,
 
 // reduction to tridiagonal form: a cooperative kernel when the matrix is
 // large enough to feed many workgroups (m_max >= 128), else one workgroup.
-// `P` holds >= 4 MAXM doubles, `bar` two unsigned ints.
+// `P` holds >= 4 MAXM doubles, `bar` two unsigned ints (zeroed before the launch).
 static sc_status tridiagonalize_launch(sc_ctx* ctx, int m_max, const int* info, double* M,
                                        double* tri, double* P, unsigned* bar, int* status) {
     hipStream_t st = ctx->stream;
