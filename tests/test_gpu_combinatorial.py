@@ -139,14 +139,20 @@ def test_combinatorial_fp32_against_fp64_oracle(orc, ctx):
     # relres 1e-3 of this operator's range 2 max d, whose bottom is far below it
     ro = orc.lobpcg(go, vo, X0, 25, 0.0, diag=do)
     N = 2 * do.max()
+    # FP32 multivectors: a Ritz value collects about (row length + 3k) roundings
+    # of unit 2^-24 relative to the operator's range N, (40 + 57) 2^-24 < 1e-5
+    # (measured 4.4e-7 N).  A BF16 Gram rounds the basis entries to 2^-9 before
+    # the products; the Ritz values move to first order in that rounding of the
+    # Gram entries, damped by the averaging over n rows: 1e-4 N (measured 2.1e-5 N).
+    bound = {"fp32": 1e-5, "fp32_bf16gram": 1e-4}
     for prec in ("fp32", "fp32_bf16gram"):
         rg = api.lobpcg_solve(ctx, gd, v32, to_dev(X0.astype(np.float32)), 25, 0.0, prec,
                               diag=d32)
         assert rg.iterations == 25 and rg.max_relres < 1e-2, (prec, rg.max_relres)
         th = host(rg.theta)
         assert np.all(np.isfinite(th)) and th.min() >= -1e-3 * N and th.max() <= N
-        # FP32 multivectors: Ritz values to ~1e-5 of the operator's range
-        assert np.max(np.abs(th - ro.theta)) < 1e-4 * N, (prec, np.max(np.abs(th - ro.theta)))
+        dev = np.max(np.abs(th - ro.theta))
+        assert dev < bound[prec] * N, (prec, dev / N)
 
 
 def test_combinatorial_end_to_end_labels(orc, ctx):
