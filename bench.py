@@ -355,12 +355,14 @@ def run_serve(args):
 def spmm_variants(args, cfg, g0):
     """Time the FP32 product Y = L X (k = the workload's block width) in the
     layouts that change its memory traffic: natural row order; rows longest
-    first (bit-identical); 16-bit gather copies of X (FP16, BF16: accuracy
+    first (bit-identical); both with 16-byte instead of 4-byte lane reads of
+    the neighbour rows (bit-identical); 16-bit gather copies of X (FP16, BF16: accuracy
     against the FP32 product reported); the vertices renumbered by reverse
     Cuthill-McKee (SciPy on the host, its time included) and, as the best any
     community-finding order could do, by the generator's blocks.  Each variant:
     2 untimed then 10 timed launches on the library's stream (HIP events).
-    Dispatch order: natural, longest first, FP16, BF16, RCM, blocks."""
+    Dispatch order: natural, longest first, their 16-byte-lane twins, FP16,
+    BF16, RCM, blocks."""
     import numpy as np
     import torch
     from paper_1708_07481_amd import api
@@ -403,6 +405,11 @@ def spmm_variants(args, cfg, g0):
                                  "order_ms": round(1e3 * t_order, 2),
                                  "bit_identical": bool(torch.equal(Y, Y0))}
     log(f"longest rows first: {ms:.3f} ms (order {1e3 * t_order:.1f} ms)")
+    for name, o in (("natural_lane16", None), ("longest_rows_first_lane16", order)):
+        ms = timed(lambda: api.spmm_ex(ctx, g, v32, X, Y, order=o, lane16=True))
+        out[name] = {"ms": round(ms, 4), "algorithmic_GBs": rate(ms),
+                     "bit_identical": bool(torch.equal(Y, Y0))}
+        log(f"{name}: {ms:.3f} ms")
     ref = Y0.double()
     scale = float(ref.abs().max())
     for name, dt in (("fp16_gather", torch.float16), ("bf16_gather", torch.bfloat16)):

@@ -307,14 +307,25 @@ sc_status sc_lobpcg_end(sc_ctx* ctx, sc_lobpcg_state* state, void* X_out, double
  *           neighbour rows from Xg, a 16-bit copy of X (row stride ldg >= k,
  *           _Float16 or bfloat16), widened to FP32 on load; a row's own x_ij
  *           always comes from X.  Half the gathered bytes, at the copy's
- *           precision.
+ *           precision; where k is a multiple of 32 (at most 192) and the
+ *           strides and pointers allow, every lane reads 16-byte pieces (8
+ *           entries) of the copy.  SC_GATHER_FP32_LANE16: as SC_GATHER_FP32
+ *           but, where k splits into 16-byte pieces over 8 or 16 lanes, every
+ *           lane reads 16-byte pieces of the neighbour rows instead of 4-byte
+ *           elements (the same fma chains, a bit-identical result; kept to
+ *           compare the two access widths).
  *   order   NULL, or an int32 permutation of the n rows: the row groups of the
  *           launch take the rows in that order (sc_row_order gives the rows
  *           longest first, so long rows do not trail the launch).  The
  *           arithmetic of every row is unchanged.
  * No synchronisation.
  */
-typedef enum { SC_GATHER_FP32 = 0, SC_GATHER_FP16 = 1, SC_GATHER_BF16 = 2 } sc_gather;
+typedef enum {
+    SC_GATHER_FP32 = 0,
+    SC_GATHER_FP16 = 1,
+    SC_GATHER_BF16 = 2,
+    SC_GATHER_FP32_LANE16 = 3
+} sc_gather;
 sc_status sc_spmm_ex(sc_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
                      const int32_t* col, const float* val, const float* diag, int k,
                      const float* X, int64_t ldx, const void* Xg, int64_t ldg, int gather,

@@ -47,7 +47,7 @@ class sc_kmeans_opts(C.Structure):
 
 SC_KM_SCAN_AUTO, SC_KM_SCAN_PRUNED, SC_KM_SCAN_FULL = 0, 1, 2
 SC_RAND_NORMAL, SC_RAND_UNIFORM, SC_RAND_RAW = 0, 1, 2
-SC_GATHER_FP32, SC_GATHER_FP16, SC_GATHER_BF16 = 0, 1, 2
+SC_GATHER_FP32, SC_GATHER_FP16, SC_GATHER_BF16, SC_GATHER_FP32_LANE16 = 0, 1, 2, 3
 
 
 SC_KIND_SPMM, SC_KIND_GRAM, SC_KIND_RR, SC_KIND_UPDATE, SC_KIND_CHOLQR, SC_KIND_RESIDUAL, \

@@ -179,15 +179,17 @@ def spmm(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
 
 def spmm_ex(ctx: Context, g: DeviceCSR, val: torch.Tensor, X: torch.Tensor,
             Y: torch.Tensor | None = None, Xg: torch.Tensor | None = None,
-            order: torch.Tensor | None = None, diag: torch.Tensor | None = None) -> torch.Tensor:
+            order: torch.Tensor | None = None, diag: torch.Tensor | None = None,
+            lane16: bool = False) -> torch.Tensor:
     """FP32 Y = L X with an optional 16-bit gather copy Xg (float16 or
-    bfloat16) and an optional row order (int32 permutation)."""
+    bfloat16) and an optional row order (int32 permutation); lane16 takes
+    16-byte lane reads of the FP32 neighbour rows instead of 4-byte ones."""
     n, k = X.shape
     if X.dtype != torch.float32 or val.dtype != torch.float32:
         raise TypeError("spmm_ex takes FP32 X and values")
     if Y is None:
         Y = torch.empty_like(X)
-    gather = _lib.SC_GATHER_FP32
+    gather = _lib.SC_GATHER_FP32_LANE16 if lane16 else _lib.SC_GATHER_FP32
     if Xg is not None:
         gather = {torch.float16: _lib.SC_GATHER_FP16, torch.bfloat16: _lib.SC_GATHER_BF16}[Xg.dtype]
     ctx.check(lib().sc_spmm_ex(ctx.handle, n, g.nnz, _ptr(g.row_ptr), _ptr(g.col), _ptr(val),

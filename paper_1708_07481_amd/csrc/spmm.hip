@@ -12,6 +12,8 @@
 // contiguous row of X per stored entry.
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "sc_internal.h"
 
 namespace {
@@ -85,6 +87,231 @@ __global__ void __launch_bounds__(TH) k_spmm(int64_t n, const int64_t* __restric
         if (ok[c]) Y[row * ldy + lane + LPR * c] = acc[c];
 }
 
+// Same product with 16-byte lane accesses (sc_spmm_ex's SC_GATHER_FP32_LANE16,
+// for comparing access widths; the solver takes k_spmm): lane l of a group of LPR lanes owns
+// the V = 16 / sizeof(T) adjacent columns j = V (l + LPR c) + e (c < NC,
+// e < V), and every gathered neighbour row is read as NC 16-byte pieces per
+// lane.  A wave then holds 64 / LPR rows and issues one load instruction per
+// 1 KB of neighbour rows instead of one per 256 B.  Each output element is
+// still a_i x_ij followed by the fma chain over the row in ascending column
+// order, so the result is bit-identical to k_spmm.  Requires k = V LPR NC,
+// ldx and ldy multiples of V and 16-byte aligned X and Y.
+template <class T, int LPR, int NC>
+__global__ void __launch_bounds__(TH) k_spmm_vec(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val,
+                                                  const T* __restrict__ diag,
+                                                  const T* __restrict__ X, int64_t ldx,
+                                                  const int32_t* __restrict__ order,
+                                                  T* __restrict__ Y, int64_t ldy) {
+    constexpr int V = 16 / (int)sizeof(T);
+    using vec = T __attribute__((ext_vector_type(V)));
+    const int64_t grp = ((int64_t)blockIdx.x * TH + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (grp >= n) return;
+    const int64_t row = order ? (int64_t)order[grp] : grp;
+    const int64_t lo = row_ptr[row], hi = row_ptr[row + 1];
+    const T a = diag ? diag[row] : T(1);
+    vec acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const vec x = *reinterpret_cast<const vec*>(X + row * ldx + V * (lane + LPR * c));
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[c][e] = diag ? a * x[e] : x[e];
+    }
+    int64_t p = lo;
+    for (; p + 4 <= hi; p += 4) {
+        int32_t cp[4];
+        T vp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            cp[u] = col[p + u];
+            vp[u] = val[p + u];
+        }
+        vec g[4][NC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                g[u][c] = *reinterpret_cast<const vec*>(X + (int64_t)cp[u] * ldx +
+                                                        V * (lane + LPR * c));
+        // all 4 NC pieces in flight before the first use (the scheduler would
+        // otherwise keep two or three, for fewer registers)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[c][e] = fma(vp[u], g[u][c][e], acc[c][e]);
+    }
+    for (; p < hi; ++p) {
+        const int32_t cp = col[p];
+        const T vp = val[p];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const vec g = *reinterpret_cast<const vec*>(X + (int64_t)cp * ldx + V * (lane + LPR * c));
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[c][e] = fma(vp, g[e], acc[c][e]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        *reinterpret_cast<vec*>(Y + row * ldy + V * (lane + LPR * c)) = acc[c];
+}
+
+template <class T, int LPR, int NC>
+sc_status go_vec(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
+                 const T* diag, const T* X, int64_t ldx, const int32_t* order, T* Y,
+                 int64_t ldy) {
+    const int64_t rows_per_block = TH / LPR;
+    hipLaunchKernelGGL((k_spmm_vec<T, LPR, NC>), dim3(ceil_div(n, rows_per_block)), dim3(TH), 0,
+                       ctx->stream, n, rp, col, val, diag, X, ldx, order, Y, ldy);
+    SC_CHECK_LAUNCH(ctx);
+    return SC_OK;
+}
+
+// The 16-byte layout when k splits into whole 16-byte pieces over 8 or 16
+// lanes (at most 6 pieces per lane) and the rows are 16-byte aligned; returns
+// false when it does not apply.
+template <class T>
+bool try_vec(sc_ctx* ctx, sc_status* st, int64_t n, const int64_t* rp, const int32_t* col,
+             const T* val, const T* diag, int k, const T* X, int64_t ldx, const int32_t* order,
+             T* Y, int64_t ldy) {
+    constexpr int V = 16 / (int)sizeof(T);
+    if (k % V || ldx % V || ldy % V || (reinterpret_cast<uintptr_t>(X) & 15) ||
+        (reinterpret_cast<uintptr_t>(Y) & 15))
+        return false;
+    const int kv = k / V;
+    int lpr = 0;
+    if (kv % 8 == 0 && kv / 8 <= 6) lpr = 8;
+    else if (kv % 16 == 0 && kv / 16 <= 6) lpr = 16;
+    else return false;
+    const int nc = kv / lpr;
+#define SC_SPMM_VEC(L, C) \
+    if (lpr == L && nc == C) { \
+        *st = go_vec<T, L, C>(ctx, n, rp, col, val, diag, X, ldx, order, Y, ldy); \
+        return true; \
+    }
+    SC_SPMM_VEC(8, 1) SC_SPMM_VEC(8, 2) SC_SPMM_VEC(8, 3)
+    SC_SPMM_VEC(8, 4) SC_SPMM_VEC(8, 5) SC_SPMM_VEC(8, 6)
+    SC_SPMM_VEC(16, 5)
+#undef SC_SPMM_VEC
+    return false;
+}
+
+// FP32 product with the neighbour rows from a 16-bit copy Xg, 16-byte lane
+// reads: lane l of a group of LPR lanes owns the 8 adjacent columns
+// j = 8 (l + LPR c) + e, reads them as one 16-byte piece of the copy per
+// neighbour, widens each to FP32 and runs the same fma chain as k_spmm (the
+// row's own x_ij from X in FP32), so the result is bit-identical to k_spmm
+// with the same copy.  Requires k = 8 LPR NC, ldx a multiple of 4, ldg and ldy
+// multiples of 8 (ldy of 4), and 16-byte aligned X, Xg and Y.
+__device__ __forceinline__ float widen16(unsigned short u, _Float16*) {
+    return (float)__builtin_bit_cast(_Float16, u);
+}
+__device__ __forceinline__ float widen16(unsigned short u, __hip_bfloat16*) {
+    return __uint_as_float((unsigned)u << 16);
+}
+
+template <class TG, int LPR, int NC>
+__global__ void __launch_bounds__(TH) k_spmm_vec16(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val,
+                                                    const float* __restrict__ diag,
+                                                    const float* __restrict__ X, int64_t ldx,
+                                                    const TG* __restrict__ Xg, int64_t ldg,
+                                                    const int32_t* __restrict__ order,
+                                                    float* __restrict__ Y, int64_t ldy) {
+    using h8 = unsigned short __attribute__((ext_vector_type(8)));
+    using f4 = float __attribute__((ext_vector_type(4)));
+    const int64_t grp = ((int64_t)blockIdx.x * TH + threadIdx.x) / LPR;
+    const int lane = threadIdx.x % LPR;
+    if (grp >= n) return;
+    const int64_t row = order ? (int64_t)order[grp] : grp;
+    const int64_t lo = row_ptr[row], hi = row_ptr[row + 1];
+    const float a = diag ? diag[row] : 1.0f;
+    const unsigned short* G = reinterpret_cast<const unsigned short*>(Xg);
+    float acc[NC][8];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const float* xr = X + row * ldx + 8 * (lane + LPR * c);
+        const f4 x0 = *reinterpret_cast<const f4*>(xr), x1 = *reinterpret_cast<const f4*>(xr + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            acc[c][e] = diag ? a * x0[e] : x0[e];
+            acc[c][e + 4] = diag ? a * x1[e] : x1[e];
+        }
+    }
+    int64_t p = lo;
+    for (; p + 4 <= hi; p += 4) {
+        int32_t cp[4];
+        float vp[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            cp[u] = col[p + u];
+            vp[u] = val[p + u];
+        }
+        h8 g[4][NC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                g[u][c] = *reinterpret_cast<const h8*>(G + (int64_t)cp[u] * ldg + 8 * (lane + LPR * c));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    acc[c][e] = fma(vp[u], widen16(g[u][c][e], (TG*)nullptr), acc[c][e]);
+    }
+    for (; p < hi; ++p) {
+        const int32_t cp = col[p];
+        const float vp = val[p];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const h8 g = *reinterpret_cast<const h8*>(G + (int64_t)cp * ldg + 8 * (lane + LPR * c));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[c][e] = fma(vp, widen16(g[e], (TG*)nullptr), acc[c][e]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        float* yr = Y + row * ldy + 8 * (lane + LPR * c);
+        *reinterpret_cast<f4*>(yr) = f4{acc[c][0], acc[c][1], acc[c][2], acc[c][3]};
+        *reinterpret_cast<f4*>(yr + 4) = f4{acc[c][4], acc[c][5], acc[c][6], acc[c][7]};
+    }
+}
+
+// The 16-byte layout for a 16-bit gather copy when k = 32 NC (NC <= 6) and the
+// strides and pointers are aligned; returns false when it does not apply.
+template <class TG>
+bool try_vec16(sc_ctx* ctx, sc_status* st, int64_t n, const int64_t* rp, const int32_t* col,
+               const float* val, const float* diag, int k, const float* X, int64_t ldx,
+               const TG* Xg, int64_t ldg, const int32_t* order, float* Y, int64_t ldy) {
+    if (k % 32 || k / 32 > 6 || ldx % 4 || ldy % 4 || ldg % 8 ||
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Xg) |
+          reinterpret_cast<uintptr_t>(Y)) & 15))
+        return false;
+    constexpr int LPR = 4;
+    const int64_t grid = ceil_div(n, (int64_t)(TH / LPR));
+#define SC_SPMM_V16(C)                                                                          \
+    case C:                                                                                     \
+        hipLaunchKernelGGL((k_spmm_vec16<TG, LPR, C>), dim3(grid), dim3(TH), 0, ctx->stream, n, \
+                           rp, col, val, diag, X, ldx, Xg, ldg, order, Y, ldy);                 \
+        break;
+    switch (k / 32) {
+        SC_SPMM_V16(1) SC_SPMM_V16(2) SC_SPMM_V16(3) SC_SPMM_V16(4) SC_SPMM_V16(5) SC_SPMM_V16(6)
+    default: return false;
+    }
+#undef SC_SPMM_V16
+    const hipError_t e = hipGetLastError();
+    *st = e == hipSuccess ? SC_OK : sc_fail(ctx, SC_E_HIP, "spmm launch: %s", hipGetErrorString(e));
+    return true;
+}
+
 template <class T, class TG, int LPR, int NC>
 sc_status go(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
              const T* diag, int k, const T* X, int64_t ldx, const TG* Xg, int64_t ldg,
@@ -96,11 +323,23 @@ sc_status go(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, cons
     return SC_OK;
 }
 
+// vec_lanes: take the 16-byte lane layouts (k_spmm_vec, k_spmm_vec16) where
+// they apply.
 template <class T, class TG>
 sc_status dispatch(sc_ctx* ctx, int64_t n, const int64_t* rp, const int32_t* col, const T* val,
                    const T* diag, int k, const T* X, int64_t ldx, const TG* Xg, int64_t ldg,
-                   const int32_t* order, T* Y, int64_t ldy) {
+                   const int32_t* order, T* Y, int64_t ldy, bool vec_lanes = false) {
     if (n <= 0 || k <= 0) return SC_OK;
+    if constexpr (std::is_same<T, float>::value && std::is_same<TG, float>::value) {
+        sc_status st;
+        if (vec_lanes && try_vec<T>(ctx, &st, n, rp, col, val, diag, k, X, ldx, order, Y, ldy))
+            return st;
+    } else if constexpr (std::is_same<T, float>::value) {
+        sc_status st;
+        if (vec_lanes &&
+            try_vec16<TG>(ctx, &st, n, rp, col, val, diag, k, X, ldx, Xg, ldg, order, Y, ldy))
+            return st;
+    }
 #define SC_SPMM_GO(L, C) go<T, TG, L, C>(ctx, n, rp, col, val, diag, k, X, ldx, Xg, ldg, order, Y, ldy)
     if (k <= 8) return SC_SPMM_GO(8, 1);
     if (k <= 16) return SC_SPMM_GO(16, 1);
@@ -166,7 +405,7 @@ extern "C" sc_status sc_spmm_ex(sc_ctx* ctx, int64_t n, int64_t nnz, const int64
     if (!row_ptr || !X || !Y || (nnz > 0 && (!col || !val)))
         return sc_fail(ctx, SC_E_INVAL, "spmm_ex: null pointer argument");
     if (X == Y) return sc_fail(ctx, SC_E_INVAL, "spmm_ex: X and Y must not alias");
-    if (gather != SC_GATHER_FP32 && (!Xg || ldg < k))
+    if ((gather == SC_GATHER_FP16 || gather == SC_GATHER_BF16) && (!Xg || ldg < k))
         return sc_fail(ctx, SC_E_INVAL, "spmm_ex: a 16-bit gather copy needs Xg and ldg >= k");
     SC_CHECK_HIP(ctx, hipSetDevice(ctx->device));
     ProfScope ps(ctx, SC_KIND_SPMM);
@@ -174,13 +413,17 @@ extern "C" sc_status sc_spmm_ex(sc_ctx* ctx, int64_t n, int64_t nnz, const int64
     case SC_GATHER_FP32:
         return dispatch<float, float>(ctx, n, row_ptr, col, val, diag, k, X, ldx, X, ldx, order, Y,
                                       ldy);
+    case SC_GATHER_FP32_LANE16:
+        return dispatch<float, float>(ctx, n, row_ptr, col, val, diag, k, X, ldx, X, ldx, order, Y,
+                                      ldy, true);
     case SC_GATHER_FP16:
         return dispatch<float, _Float16>(ctx, n, row_ptr, col, val, diag, k, X, ldx,
-                                         static_cast<const _Float16*>(Xg), ldg, order, Y, ldy);
+                                         static_cast<const _Float16*>(Xg), ldg, order, Y, ldy,
+                                         true);
     case SC_GATHER_BF16:
         return dispatch<float, __hip_bfloat16>(ctx, n, row_ptr, col, val, diag, k, X, ldx,
                                                static_cast<const __hip_bfloat16*>(Xg), ldg, order,
-                                               Y, ldy);
+                                               Y, ldy, true);
     default:
         return sc_fail(ctx, SC_E_INVAL, "spmm_ex: unknown gather type %d", gather);
     }

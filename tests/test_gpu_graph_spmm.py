@@ -82,7 +82,7 @@ def test_laplacian_bit_exact(orc, ctx, name, make):
     assert np.array_equal(host(di), dio)
 
 
-@pytest.mark.parametrize("k", [1, 5, 8, 19, 44, 64, 98, 130, 160])
+@pytest.mark.parametrize("k", [1, 5, 8, 19, 32, 44, 64, 96, 98, 130, 160])
 def test_spmm_fp64_bit_exact(orc, ctx, k):
     from paper_1708_07481_amd import api
     import torch
@@ -101,6 +101,13 @@ def test_spmm_fp64_bit_exact(orc, ctx, k):
     api.spmm(ctx, gd, v64, big[:, k:2 * k], out[:, 2 * k:3 * k])
     assert np.array_equal(host(out[:, 2 * k:3 * k]), Yo)
     assert float(out[:, :2 * k].abs().max()) == 0.0
+    # a block inside rows of 3k (the solver's layout: 16-byte aligned when k is even)
+    big = torch.zeros((g0.n, 3 * k), dtype=torch.float64, device="cuda")
+    big[:, k:2 * k] = to_dev(X)
+    out = torch.zeros((g0.n, 3 * k), dtype=torch.float64, device="cuda")
+    api.spmm(ctx, gd, v64, big[:, k:2 * k], out[:, 2 * k:3 * k])
+    assert np.array_equal(host(out[:, 2 * k:3 * k]), Yo)
+    assert float(out[:, :2 * k].abs().max()) == 0.0
 
 
 @pytest.mark.parametrize("k", [8, 44, 160])
@@ -115,3 +122,58 @@ def test_spmm_fp32(orc, ctx, k):
     Yd = host(api.spmm(ctx, gd, v32, to_dev(X))).astype(np.float64)
     # FP32 arithmetic: |err| <= (deg + 1) * 2^-24 * (|x| + sum |v x|), well below 1e-5 here
     assert np.max(np.abs(Yd - Yo)) < 1e-5 * max(1.0, np.abs(Yo).max())
+
+
+@pytest.mark.parametrize("k", [4, 32, 64, 96, 128, 160, 192, 200])
+def test_spmm_fp32_access_widths_bit_identical(ctx, k):
+    """4-byte lane reads of the neighbour rows and 16-byte ones (where k allows
+    them) run the same fma chains: identical FP32 results, with and without the
+    diagonal and the longest-first row order, also inside rows of 3k."""
+    from paper_1708_07481_amd import api
+    import torch
+    g0 = dcsbm(3001, 7, 24.0, 0.7, "dirichlet", 2.0, seed=k + 3)
+    gd = api.graph_build(ctx, g0.n, torch.from_numpy(g0.src).cuda(), torch.from_numpy(g0.dst).cuda())
+    _, v32, _ = api.laplacian_csr(ctx, gd, False, True)
+    X = to_dev(np.random.default_rng(k).standard_normal((g0.n, k)).astype(np.float32))
+    d32 = gd.degree.to(torch.float32)
+    order = api.row_order(ctx, gd)
+    for diag in (None, d32):
+        for o in (None, order):
+            Y = api.spmm_ex(ctx, gd, v32, X, order=o, diag=diag)
+            Y16 = api.spmm_ex(ctx, gd, v32, X, order=o, diag=diag, lane16=True)
+            assert torch.equal(Y, Y16), (k, diag is None, o is None)
+    big = torch.zeros((g0.n, 3 * k), dtype=torch.float32, device="cuda")
+    big[:, k:2 * k] = X
+    out = torch.zeros((g0.n, 3 * k), dtype=torch.float32, device="cuda")
+    api.spmm_ex(ctx, gd, v32, big[:, k:2 * k], out[:, 2 * k:3 * k], order=order, lane16=True)
+    Y4 = api.spmm_ex(ctx, gd, v32, X, order=order)
+    assert torch.equal(out[:, 2 * k:3 * k], Y4)
+    assert float(out[:, :2 * k].abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("k", [32, 160, 200])
+def test_spmm_fp32_16bit_gather_copy(ctx, k):
+    """FP32 product with the neighbour rows from a 16-bit copy (16-byte lane
+    reads where k is a multiple of 32, 2-byte ones otherwise): within the FP32
+    rounding of the exact product with the widened copy."""
+    from paper_1708_07481_amd import api
+    import scipy.sparse as sp
+    import torch
+    g0 = dcsbm(3001, 7, 24.0, 0.7, "dirichlet", 2.0, seed=k + 5)
+    gd = api.graph_build(ctx, g0.n, torch.from_numpy(g0.src).cuda(), torch.from_numpy(g0.dst).cuda())
+    _, v32, _ = api.laplacian_csr(ctx, gd, False, True)
+    nnz = gd.nnz
+    A = sp.csr_matrix((host(v32)[:nnz].astype(np.float64), host(gd.col)[:nnz], host(gd.row_ptr)),
+                      shape=(g0.n, g0.n))
+    X = np.random.default_rng(k).standard_normal((g0.n, k)).astype(np.float32)
+    Xd = to_dev(X)
+    order = api.row_order(ctx, gd)
+    lens = np.diff(host(gd.row_ptr)).astype(np.float64)[:, None]
+    for dt in (torch.float16, torch.bfloat16):
+        Xg = Xd.to(dt)
+        Xw = Xg.float().cpu().numpy().astype(np.float64)
+        ref = X.astype(np.float64) + A @ Xw
+        mag = np.abs(X.astype(np.float64)) + abs(A) @ np.abs(Xw)
+        for o in (None, order):
+            Y = host(api.spmm_ex(ctx, gd, v32, Xd, Xg=Xg, order=o)).astype(np.float64)
+            assert np.all(np.abs(Y - ref) <= 2 * (lens + 1) * 2.0 ** -24 * mag + 1e-30), (k, dt)
