@@ -54,3 +54,15 @@ def test_one_hip_runtime_is_mapped():
 def test_binding_declares_every_symbol():
     from paper_1708_07481_amd._lib import SIGNATURES
     assert sorted(SIGNATURES) == _declared()
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator the binding names has the header's value."""
+    from paper_1708_07481_amd import _lib
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {n: int(v) for n, v in re.findall(r"\b(SC_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    named = [n for n in dir(_lib) if n.startswith("SC_") and isinstance(getattr(_lib, n), int)]
+    assert len(named) >= 20
+    for n in named:
+        assert n in consts, n
+        assert getattr(_lib, n) == consts[n], (n, getattr(_lib, n), consts[n])
