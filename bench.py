@@ -76,6 +76,24 @@ def spmm_traffic(cfg_name, launches_bytes):
         return None
 
 
+def copy_rate_gbs(torch, dev):
+    """Achievable HBM rate of a plain device copy: 512 MiB read and 512 MiB
+    written per launch (torch.mul by 1.0), 2 untimed then 10 timed launches
+    between HIP events on torch's stream; bytes read plus written per second."""
+    x = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    for _ in range(2):
+        torch.mul(x, 1.0, out=y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(10):
+        torch.mul(x, 1.0, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 10
+    return 2 * x.numel() * 4 / (ms * 1e-3) / 1e9
+
+
 def host_info():
     """Host CPU of this run: logical CPUs, model name and sockets (lscpu)."""
     import subprocess
@@ -706,6 +724,11 @@ def main():
                  "frac": round(achieved / HBM_PEAK_GBS, 4), "avg_ms": round(spmm["avg_ms"], 4),
                  "algorithmic_bytes_per_launch": alg_bytes,
                  "traffic": spmm_traffic(args.config, alg_bytes)}
+    # the achievable HBM rate on this machine beside the published peak (after the
+    # timed steps)
+    copy_gbs = copy_rate_gbs(torch, dev)
+    spmm_line["copy_GBs"] = round(copy_gbs, 1)
+    spmm_line["frac_of_copy"] = round(achieved / copy_gbs, 4)
     # The dominant kernel: the Gram products of the Rayleigh-Ritz step, S'LS and
     # S'S in one launch (split over row chunks, then an ordered reduction), one
     # launch per Rayleigh-Ritz step; its algorithmic work is the two
