@@ -177,3 +177,23 @@ def test_spmm_fp32_16bit_gather_copy(ctx, k):
         for o in (None, order):
             Y = host(api.spmm_ex(ctx, gd, v32, Xd, Xg=Xg, order=o)).astype(np.float64)
             assert np.all(np.abs(Y - ref) <= 2 * (lens + 1) * 2.0 ** -24 * mag + 1e-30), (k, dt)
+
+
+def test_spmm_ex_argument_errors(ctx):
+    """sc_spmm_ex rejects an unknown gather type and a 16-bit gather without
+    its copy, before any launch."""
+    from paper_1708_07481_amd import _lib, api
+    from paper_1708_07481_amd._lib import SC_E_INVAL, SpectralError
+    from paper_1708_07481_amd.api import _ptr
+    import torch
+    g0 = dcsbm(500, 4, 10.0, 0.8, seed=3)
+    gd = api.graph_build(ctx, g0.n, torch.from_numpy(g0.src).cuda(), torch.from_numpy(g0.dst).cuda())
+    _, v32, _ = api.laplacian_csr(ctx, gd, False, True)
+    X = torch.zeros((g0.n, 32), dtype=torch.float32, device="cuda")
+    Y = torch.empty_like(X)
+    for gather in (_lib.SC_GATHER_FP16, _lib.SC_GATHER_BF16, 7):
+        with pytest.raises(SpectralError) as e:
+            ctx.check(_lib.lib().sc_spmm_ex(ctx.handle, g0.n, gd.nnz, _ptr(gd.row_ptr),
+                                            _ptr(gd.col), _ptr(v32), None, 32, _ptr(X), 32,
+                                            None, 0, gather, None, _ptr(Y), 32), "sc_spmm_ex")
+        assert e.value.status == SC_E_INVAL
